@@ -1,0 +1,160 @@
+/*
+ * cclr.h — C ABI of the MI355X CCSD linear-response library (libcclr.so).
+ *
+ * The method is relativistic (complex, spin-orbital) coupled-cluster linear
+ * response of arXiv:2307.14296.  The library applies the CCSD Jacobian
+ * A = <mu-bar|[H0, tau_nu]|CC> (Table 1) from the right and from the left,
+ * shifted by a complex frequency z = omega + i*gamma, solves the damped
+ * response equations (A - z) t = -xi (eq. "LR response equation_cpp") and the
+ * Lambda equation lambda A = -eta (theory section, eq. "Lambda") with a
+ * Davidson-type subspace solver (SI, "Davidson scheme"), and assembles the
+ * symmetric CC-CC response function <<X;Y>> (eq. "CC-CC response function").
+ * The contractions follow the SI working equations for the sigma vectors,
+ * the Hbar intermediates, xi^X, eta^X and the Hessian product t^X F.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - o occupied and v virtual spin orbitals, n = o + v, occupied first.
+ * - Complex numbers are interleaved double pairs (cclr_c64), identical in
+ *   layout to C99 double _Complex and numpy/torch complex128.
+ * - Tensors are row-major and C-contiguous:
+ *     f[p][q]              n x n Fock matrix, f[p][q] = <p|f|q>
+ *     blocks of <pq||rs>   oooo[o][o][o][o], ooov[o][o][o][v], oovv[o][o][v][v],
+ *                          ovov[o][v][o][v], ovvv[o][v][v][v], vvvv[v][v][v][v]
+ *                          (all other blocks follow from antisymmetry and
+ *                          <pq||rs> = conj(<rs||pq>))
+ *     t1[i][a] = t^a_i, t2[i][j][a][b] = t^ab_ij (antisymmetric in ij and ab)
+ *     right vectors r1[i][a], r2[i][j][a][b]; left vectors l1[i][a] = l^i_a,
+ *     l2[i][j][a][b] = l^ij_ab; perturbations X[p][q] = <p|X|q> (n x n).
+ *   Only the unique doubles (i > j, a > b) of an input vector are read; the
+ *   doubles of an output vector are written in full antisymmetric form.
+ *   With nvec > 1 the vectors are stacked along a leading dimension.
+ * - Tensor arguments are DEVICE pointers (HIP device memory, e.g. the
+ *   data_ptr() of a torch tensor on the GPU).  Scalars and arrays of
+ *   frequencies, and the response-function output, are HOST pointers.
+ * - Work is enqueued on options.hip_stream (NULL = the null stream); every
+ *   call returns after that stream has completed the call's work.
+ * - The caller owns every buffer it passes; the context keeps its own device
+ *   copies of f, the integral blocks, t, lambda and the intermediates and
+ *   retains no caller pointer after a call returns.  A context is used by one
+ *   host thread at a time; distinct contexts are independent.
+ * - Return codes: CCLR_OK (0); CCLR_ENOTCONV (> 0: result written, solver
+ *   did not reach the tolerance, see cclr_solve_info); negative codes are
+ *   errors, with cclr_last_error() describing them.  Inputs containing
+ *   NaN/Inf are rejected with CCLR_EINVAL.
+ */
+#ifndef CCLR_H
+#define CCLR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } cclr_c64;
+typedef struct cclr_ctx cclr_ctx;
+
+enum {
+  CCLR_OK = 0,
+  CCLR_ENOTCONV = 1,
+  CCLR_EINVAL = -1,
+  CCLR_ENOMEM = -2,
+  CCLR_EHIP = -3,
+  CCLR_ESTATE = -4
+};
+
+/* arithmetic of the bulk contractions (solver, residuals and dot products
+ * are always FP64) */
+enum { CCLR_FP64 = 0, CCLR_FP32 = 1, CCLR_BF16X3 = 2 };
+
+enum { CCLR_RIGHT = 0, CCLR_LEFT = 1 };
+
+typedef struct {
+  int prec;              /* CCLR_FP64 (default)                               */
+  double tol;            /* solver stop: ||R|| <= tol * ||rhs|| (1e-10)       */
+  int maxiter;           /* sigma applications per right-hand side (500)      */
+  int max_subspace;      /* subspace size before a restart (48)               */
+  size_t device_mem_cap; /* bytes the context may allocate, 0 = unlimited     */
+  void* hip_stream;      /* hipStream_t; NULL = null stream                   */
+} cclr_options;
+
+typedef struct {
+  int iters;        /* Davidson iterations (max over right-hand sides)        */
+  int converged;    /* 1 if every right-hand side met the tolerance           */
+  double resnorm;   /* max relative residual norm ||R||/||rhs|| at exit       */
+  double time_ms;   /* wall time of the call                                  */
+  long nsigma;      /* number of single-vector Jacobian transforms applied    */
+} cclr_solve_info;
+
+/* Fill *opt with the defaults listed above. */
+int cclr_default_options(cclr_options* opt);
+
+/* New context for o >= 2 occupied and v >= 2 virtual spin orbitals.
+ * opt may be NULL (defaults).  On success *out owns device resources until
+ * cclr_destroy. */
+int cclr_create(int o, int v, const cclr_options* opt, cclr_ctx** out);
+int cclr_destroy(cclr_ctx* ctx);
+
+/* Copy f and the six canonical blocks of <pq||rs> (device pointers, layouts
+ * above) into the context.  Invalidates amplitudes, intermediates and lambda. */
+int cclr_set_hamiltonian(cclr_ctx* ctx, const cclr_c64* f,
+                         const cclr_c64* oooo, const cclr_c64* ooov, const cclr_c64* oovv,
+                         const cclr_c64* ovov, const cclr_c64* ovvv, const cclr_c64* vvvv);
+
+/* Copy t1 and t2 and build the property-independent Hbar intermediates
+ * F^i_m, F^a_e, F^m_e, W^ij_mn, W^mb_ej, W^ie_mn, W^ef_am, W^ef_ab, W^mn_ie,
+ * W^am_ef (SI, eqs. F_im ... W_amef).  Needs cclr_set_hamiltonian first
+ * (CCLR_ESTATE otherwise).  Invalidates lambda. */
+int cclr_set_amplitudes(cclr_ctx* ctx, const cclr_c64* t1, const cclr_c64* t2);
+
+/* s = (A - z_k) r_k for k < nvec, z_k = omega[k] + i*gamma[k]  (right
+ * EOM-EE sigma vector, SI eqs. sigma_sin-ee and sigma_double-ee). */
+int cclr_jacobian_right(cclr_ctx* ctx, int nvec, const double* omega, const double* gamma,
+                        const cclr_c64* r1, const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2);
+
+/* s = l_k (A - z_k)  (left sigma vector, SI eqs. sigma_sin-ee-left and
+ * sigma_double-ee-left; the transposed transform of the Lambda and left
+ * response equations). */
+int cclr_jacobian_left(cclr_ctx* ctx, int nvec, const double* omega, const double* gamma,
+                       const cclr_c64* l1, const cclr_c64* l2, cclr_c64* s1, cclr_c64* s2);
+
+/* Damped linear systems, one per right-hand side k < nrhs:
+ *   side == CCLR_RIGHT:  (A - z_k) x_k = -b_k
+ *   side == CCLR_LEFT :  x_k (A - z_k) = -b_k
+ * Davidson subspace iteration (SI, "Davidson scheme"): pivoted unit start
+ * vector, projected system G'beta = -C', preconditioner (z - D)^-1 with D the
+ * Fock-like diagonal, antisymmetry kept by packed (i>j, a>b) storage,
+ * classical Gram-Schmidt applied twice.  info may be NULL. */
+int cclr_solve_damped(cclr_ctx* ctx, int side, int nrhs, const double* omega, const double* gamma,
+                      const cclr_c64* b1, const cclr_c64* b2, cclr_c64* x1, cclr_c64* x2,
+                      cclr_solve_info* info);
+
+/* Solve lambda A = -eta0 (eta0 singles F^i_a, doubles <ij||ab>) and keep
+ * lambda in the context.  Needs cclr_set_amplitudes. */
+int cclr_solve_lambda(cclr_ctx* ctx, cclr_solve_info* info);
+
+/* Copy the context's lambda (l1[o][v], l2[o][o][v][v], device pointers). */
+int cclr_get_lambda(const cclr_ctx* ctx, cclr_c64* l1, cclr_c64* l2);
+
+/* Symmetric CC-CC linear response function for every pair of the nx
+ * perturbations X[p] (host array of device pointers to n x n matrices) at
+ * each of nfreq complex frequencies z = omega[w] + i*gamma[w]:
+ *   out[w][p][q] = <<X_p; X_q>>_z = 1/2 [ g_pq(z) + conj g_pq(-conj z) ],
+ *   g_pq(z) = eta^p t^q(z) + eta^q t^p(-z) + F t^p(-z) t^q(z),
+ * with xi, eta, t^X F from the SI working equations and t^X from
+ * cclr_solve_damped.  Solves lambda first if the context has none.  out is a
+ * HOST array of nfreq*nx*nx complex values.  The polarizability is
+ * alpha = -<<mu;mu>>. */
+int cclr_response_function(cclr_ctx* ctx, int nx, const cclr_c64* const* X,
+                           int nfreq, const double* omega, const double* gamma,
+                           cclr_c64* out, cclr_solve_info* info);
+
+/* Message describing the last error on ctx (or a creation error if ctx is
+ * NULL); valid until the next call on the same context. */
+const char* cclr_last_error(const cclr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCLR_H */

@@ -1,0 +1,36 @@
+/*
+ * cclr_debug.h — internal test hooks of libcclr (not part of the public ABI).
+ *
+ * Used by the test suite to check single building blocks of the library on
+ * the GPU: the complex GEMM kernel, the contraction engine and the Hbar
+ * intermediates.  All tensor pointers are device pointers to complex128
+ * data; dims/strides are host arrays of element counts.
+ */
+#ifndef CCLR_DEBUG_H
+#define CCLR_DEBUG_H
+#include "cclr.h"
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[b][m][n] (+)= alpha * sum_k op(A)[b][m][k] op(B)[b][k][n] with element strides;
+ * op = complex conjugate when conjA/conjB is set; beta 0 overwrites, 1 accumulates. */
+int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long sAb, long long sAm, long long sAk,
+                   int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn, int conjB, cclr_c64* C,
+                   long long sCb, long long sCm, long long sCn, double alpha_re, double alpha_im, int beta);
+
+/* C[lc] += alpha * sum A[la] B[lb] through the contraction engine; A, B, C are
+ * contiguous row-major tensors with the given dims (nd = strlen of labels). */
+int cclr_dbg_contract(cclr_ctx* ctx, double alpha_re, double alpha_im, const cclr_c64* A, const char* la,
+                      const long long* adims, const cclr_c64* B, const char* lb, const long long* bdims, cclr_c64* C,
+                      const char* lc, const long long* cdims);
+
+/* Copy the named intermediate (Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv,
+ * Wovoo, Wvvvo, Wvvvv, Wp, diag) into dst; *count receives its element count
+ * (dst may be NULL to query the count only). */
+int cclr_dbg_get(cclr_ctx* ctx, const char* name, cclr_c64* dst, long long* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,189 @@
+"""Python binding of libcclr, the MI355X CCSD linear-response library.
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name in ``libcclr.so`` (declared in ``include/cclr.h``).  Tensor
+arguments are torch tensors that live on the GPU (complex128, contiguous);
+their device pointers are passed through.  Every step of the computation
+runs in the library's HIP kernels; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcclr.so")
+
+CCLR_OK = 0
+CCLR_ENOTCONV = 1
+CCLR_EINVAL = -1
+CCLR_ENOMEM = -2
+CCLR_EHIP = -3
+CCLR_ESTATE = -4
+CCLR_FP64, CCLR_FP32, CCLR_BF16X3 = 0, 1, 2
+CCLR_RIGHT, CCLR_LEFT = 0, 1
+
+EXPORTED = (
+    "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_amplitudes",
+    "cclr_jacobian_right", "cclr_jacobian_left", "cclr_solve_damped", "cclr_solve_lambda", "cclr_get_lambda",
+    "cclr_response_function", "cclr_last_error",
+)
+
+
+class cclr_options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
+                ("max_subspace", ctypes.c_int), ("device_mem_cap", ctypes.c_size_t), ("hip_stream", ctypes.c_void_p)]
+
+
+class cclr_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("resnorm", ctypes.c_double),
+                ("time_ms", ctypes.c_double), ("nsigma", ctypes.c_long)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CclrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcclr error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libcclr.so from the package directory; fail loudly if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    L.cclr_default_options.argtypes = [ctypes.POINTER(cclr_options)]
+    L.cclr_create.argtypes = [I, I, ctypes.POINTER(cclr_options), ctypes.POINTER(P)]
+    L.cclr_destroy.argtypes = [P]
+    L.cclr_set_hamiltonian.argtypes = [P] + [P] * 7
+    L.cclr_set_amplitudes.argtypes = [P, P, P]
+    L.cclr_jacobian_right.argtypes = [P, I, D, D, P, P, P, P]
+    L.cclr_jacobian_left.argtypes = [P, I, D, D, P, P, P, P]
+    L.cclr_solve_damped.argtypes = [P, I, I, D, D, P, P, P, P, ctypes.POINTER(cclr_solve_info)]
+    L.cclr_solve_lambda.argtypes = [P, ctypes.POINTER(cclr_solve_info)]
+    L.cclr_get_lambda.argtypes = [P, P, P]
+    L.cclr_response_function.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(cclr_solve_info)]
+    L.cclr_last_error.argtypes = [P]
+    L.cclr_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("cclr_last_error",):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: tensor must be on the GPU")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name}: expected complex128, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dbl(xs):
+    xs = [float(x) for x in xs]
+    return (ctypes.c_double * max(1, len(xs)))(*xs)
+
+
+def _check(ctx, rc, allow_notconv=False):
+    if rc == CCLR_OK or (allow_notconv and rc == CCLR_ENOTCONV):
+        return rc
+    msg = lib().cclr_last_error(ctx)
+    raise CclrError(rc, msg.decode() if msg else "")
+
+
+def cclr_default_options():
+    o = cclr_options()
+    lib().cclr_default_options(ctypes.byref(o))
+    return o
+
+
+def cclr_create(o, v, options=None, stream=None):
+    """Returns an opaque context handle.  ``stream``: a torch.cuda.Stream
+    (default: torch's current stream)."""
+    import torch
+    opt = options if options is not None else cclr_default_options()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    opt.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+    h = ctypes.c_void_p()
+    rc = lib().cclr_create(int(o), int(v), ctypes.byref(opt), ctypes.byref(h))
+    _check(None, rc)
+    return h
+
+
+def cclr_destroy(ctx):
+    return lib().cclr_destroy(ctx)
+
+
+def cclr_last_error(ctx=None):
+    m = lib().cclr_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def cclr_set_hamiltonian(ctx, f, oooo, ooov, oovv, ovov, ovvv, vvvv):
+    args = [_ptr(x, n) for x, n in zip((f, oooo, ooov, oovv, ovov, ovvv, vvvv),
+                                       ("f", "oooo", "ooov", "oovv", "ovov", "ovvv", "vvvv"))]
+    return _check(ctx, lib().cclr_set_hamiltonian(ctx, *args))
+
+
+def cclr_set_amplitudes(ctx, t1, t2):
+    return _check(ctx, lib().cclr_set_amplitudes(ctx, _ptr(t1, "t1"), _ptr(t2, "t2")))
+
+
+def cclr_jacobian_right(ctx, omega, gamma, r1, r2, s1, s2):
+    n = len(omega)
+    return _check(ctx, lib().cclr_jacobian_right(ctx, n, _dbl(omega), _dbl(gamma), _ptr(r1, "r1"), _ptr(r2, "r2"),
+                                                 _ptr(s1, "s1"), _ptr(s2, "s2")))
+
+
+def cclr_jacobian_left(ctx, omega, gamma, l1, l2, s1, s2):
+    n = len(omega)
+    return _check(ctx, lib().cclr_jacobian_left(ctx, n, _dbl(omega), _dbl(gamma), _ptr(l1, "l1"), _ptr(l2, "l2"),
+                                                _ptr(s1, "s1"), _ptr(s2, "s2")))
+
+
+def cclr_solve_damped(ctx, side, omega, gamma, b1, b2, x1, x2):
+    info = cclr_solve_info()
+    rc = lib().cclr_solve_damped(ctx, int(side), len(omega), _dbl(omega), _dbl(gamma), _ptr(b1, "b1"),
+                                 _ptr(b2, "b2"), _ptr(x1, "x1"), _ptr(x2, "x2"), ctypes.byref(info))
+    _check(ctx, rc, allow_notconv=True)
+    return rc, info
+
+
+def cclr_solve_lambda(ctx):
+    info = cclr_solve_info()
+    rc = lib().cclr_solve_lambda(ctx, ctypes.byref(info))
+    _check(ctx, rc, allow_notconv=True)
+    return rc, info
+
+
+def cclr_get_lambda(ctx, l1, l2):
+    return _check(ctx, lib().cclr_get_lambda(ctx, _ptr(l1, "l1"), _ptr(l2, "l2")))
+
+
+def cclr_response_function(ctx, X, omega, gamma):
+    """Returns (rc, out[nfreq][nx][nx] as a host numpy complex128 array, info)."""
+    import numpy as np
+    nx, nf = len(X), len(omega)
+    ptrs = (ctypes.c_void_p * nx)(*[_ptr(x, "X").value for x in X])
+    out = np.zeros((max(nf, 1), nx, nx), dtype=np.complex128)
+    info = cclr_solve_info()
+    rc = lib().cclr_response_function(ctx, nx, ptrs, nf, _dbl(omega), _dbl(gamma),
+                                      ctypes.c_void_p(out.ctypes.data), ctypes.byref(info))
+    _check(ctx, rc, allow_notconv=True)
+    return rc, out[:nf], info

@@ -1,0 +1,406 @@
+// C ABI of libcclr (declared in include/cclr.h).
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+
+#include "internal.h"
+
+void launch_check_finite(const cplx* p, i64 n, int* flag, hipStream_t s);
+void launch_bdot(int npair, const cplx* const* xs, const cplx* const* xd, const cplx* const* ys,
+                 const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s);
+int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
+             cclr_solve_info* info);
+void build_xi(cclr_ctx* c, const cplx* X, const VecSet& out);
+void build_eta(cclr_ctx* c, const cplx* X, const VecSet& out);
+void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out);
+
+static thread_local std::string g_create_error;
+
+namespace {
+template <class F>
+int guarded(cclr_ctx* c, F&& f) {
+  try {
+    if (c) {
+      c->err.clear();
+      HIPCHK(hipSetDevice(c->device));
+    }
+    return f();
+  } catch (const CclrError& e) {
+    if (c) c->err = e.what();
+    else g_create_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return CCLR_ENOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return CCLR_EHIP;
+  }
+}
+
+void check_ptr(const void* p, const char* what) {
+  REQUIRE(p != nullptr, CCLR_EINVAL, std::string("null pointer: ") + what);
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw CclrError(CCLR_EINVAL, std::string(what) + " is not a HIP device pointer");
+  }
+  REQUIRE(attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged, CCLR_EINVAL,
+          std::string(what) + " must point to device memory");
+}
+
+void check_finite(cclr_ctx* c, const cplx* p, i64 n, const char* what) {
+  int* flag = (int*)c->arena.get(sizeof(int));
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+  launch_check_finite(p, n, flag, c->stream);
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  REQUIRE(!h, CCLR_EINVAL, std::string("non-finite value in ") + what);
+}
+
+void copy_in(cclr_ctx* c, DevBuf& dst, const cclr_c64* src, i64 n, const char* what) {
+  check_ptr(src, what);
+  dst.alloc(c, sizeof(cplx) * (size_t)n);
+  HIPCHK(hipMemcpyAsync(dst.p, src, sizeof(cplx) * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+  Arena::Mark mk = c->arena.mark();
+  check_finite(c, dst.c(), n, what);
+  c->arena.reset(mk);
+}
+
+void check_freqs(int n, const double* omega, const double* gamma) {
+  REQUIRE(n >= 0, CCLR_EINVAL, "negative count");
+  if (n == 0) return;
+  REQUIRE(omega && gamma, CCLR_EINVAL, "null frequency array");
+  for (int k = 0; k < n; ++k) {
+    REQUIRE(std::isfinite(omega[k]) && std::isfinite(gamma[k]), CCLR_EINVAL, "non-finite frequency");
+    REQUIRE(gamma[k] >= 0.0, CCLR_EINVAL, "negative damping gamma");
+  }
+}
+
+VecSet packed_buf(cclr_ctx* c, int n) {
+  VecSet v;
+  v.s = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(n * c->ns()));
+  v.d = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(n * c->nd()));
+  v.n = n;
+  return v;
+}
+
+// full (r1[n][o][v], r2[n][o][o][v][v]) -> packed
+void pack_in(cclr_ctx* c, int n, const cclr_c64* r1, const cclr_c64* r2, const VecSet& out, const char* what) {
+  check_ptr(r1, what);
+  check_ptr(r2, what);
+  const i64 oovv = (i64)c->o * c->o * c->v * c->v;
+  launch_pack_full(n, c->o, c->v, (const cplx*)r1, (const cplx*)r2, out.s, out.d, c->stream);
+  check_finite(c, out.s, n * c->ns(), what);
+  check_finite(c, out.d, n * c->nd(), what);
+  (void)oovv;
+}
+
+void unpack_out(cclr_ctx* c, const VecSet& in, cclr_c64* s1, cclr_c64* s2, const char* what) {
+  check_ptr(s1, what);
+  check_ptr(s2, what);
+  launch_unpack(in.n, c->o, c->v, in.s, in.d, (cplx*)s1, (cplx*)s2, c->stream);
+}
+
+void require_t(cclr_ctx* c) {
+  REQUIRE(c->have_H, CCLR_ESTATE, "cclr_set_hamiltonian has not been called");
+  REQUIRE(c->have_t, CCLR_ESTATE, "cclr_set_amplitudes has not been called");
+}
+
+int solve_lambda_impl(cclr_ctx* c, cclr_solve_info* info) {
+  require_t(c);
+  Arena::Mark mk = c->arena.mark();
+  VecSet rhs = packed_buf(c, 1);
+  // eta0: singles F^i_a, doubles <ij||ab>
+  HIPCHK(hipMemcpyAsync(rhs.s, c->Fov.p, sizeof(cplx) * (size_t)c->ns(), hipMemcpyDeviceToDevice, c->stream));
+  launch_pack_full(1, c->o, c->v, c->Fov.c(), c->Voovv.c(), rhs.s, rhs.d, c->stream);
+  c->lam_s.alloc(c, sizeof(cplx) * (size_t)c->ns());
+  c->lam_d.alloc(c, sizeof(cplx) * (size_t)c->nd());
+  VecSet x{c->lam_s.c(), c->lam_d.c(), 1};
+  const cplx z0 = cx(0.0);
+  const int rc = davidson(c, CCLR_LEFT, 1, &z0, rhs, x, info);
+  c->arena.reset(mk);
+  c->have_lam = true;
+  return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int cclr_default_options(cclr_options* opt) {
+  if (!opt) return CCLR_EINVAL;
+  opt->prec = CCLR_FP64;
+  opt->tol = 1e-10;
+  opt->maxiter = 500;
+  opt->max_subspace = 48;
+  opt->device_mem_cap = 0;
+  opt->hip_stream = nullptr;
+  return CCLR_OK;
+}
+
+int cclr_create(int o, int v, const cclr_options* opt, cclr_ctx** out) {
+  return guarded(nullptr, [&]() -> int {
+    REQUIRE(out, CCLR_EINVAL, "null output pointer");
+    *out = nullptr;
+    REQUIRE(o >= 2 && v >= 2, CCLR_EINVAL, "need o >= 2 and v >= 2");
+    REQUIRE((i64)o * o * v * v < (1ll << 40), CCLR_EINVAL, "problem too large");
+    cclr_ctx* c = new cclr_ctx();
+    c->o = o;
+    c->v = v;
+    if (opt) c->opt = *opt;
+    else cclr_default_options(&c->opt);
+    if (c->opt.prec != CCLR_FP64) {
+      delete c;
+      throw CclrError(CCLR_EINVAL, "only CCLR_FP64 arithmetic is available");
+    }
+    if (!(c->opt.tol > 0.0) || c->opt.maxiter < 1 || c->opt.max_subspace < 4 || c->opt.max_subspace > 120) {
+      delete c;
+      throw CclrError(CCLR_EINVAL, "invalid options (tol > 0, maxiter >= 1, 4 <= max_subspace <= 120)");
+    }
+    c->stream = (hipStream_t)c->opt.hip_stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+      delete c;
+      throw CclrError(CCLR_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    c->arena.ctx = c;
+    *out = c;
+    return CCLR_OK;
+  });
+}
+
+int cclr_destroy(cclr_ctx* c) {
+  if (!c) return CCLR_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return CCLR_OK;
+}
+
+const char* cclr_last_error(const cclr_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int cclr_set_hamiltonian(cclr_ctx* c, const cclr_c64* f, const cclr_c64* oooo, const cclr_c64* ooov,
+                         const cclr_c64* oovv, const cclr_c64* ovov, const cclr_c64* ovvv, const cclr_c64* vvvv) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    const i64 o = c->o, v = c->v, n = o + v;
+    c->have_H = c->have_t = c->have_lam = false;
+    copy_in(c, c->f, f, n * n, "f");
+    copy_in(c, c->Voooo, oooo, o * o * o * o, "oooo");
+    copy_in(c, c->Vooov, ooov, o * o * o * v, "ooov");
+    copy_in(c, c->Voovv, oovv, o * o * v * v, "oovv");
+    copy_in(c, c->Vovov, ovov, o * v * o * v, "ovov");
+    copy_in(c, c->Vovvv, ovvv, o * v * v * v, "ovvv");
+    copy_in(c, c->Vvvvv, vvvv, v * v * v * v, "vvvv");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->have_H = true;
+    return CCLR_OK;
+  });
+}
+
+int cclr_set_amplitudes(cclr_ctx* c, const cclr_c64* t1, const cclr_c64* t2) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    REQUIRE(c->have_H, CCLR_ESTATE, "cclr_set_hamiltonian has not been called");
+    const i64 o = c->o, v = c->v;
+    c->have_t = c->have_lam = false;
+    copy_in(c, c->t1, t1, o * v, "t1");
+    copy_in(c, c->t2, t2, o * o * v * v, "t2");
+    build_intermediates(c);
+    c->have_t = true;
+    return CCLR_OK;
+  });
+}
+
+static int jacobian(cclr_ctx* c, int side, int nvec, const double* omega, const double* gamma, const cclr_c64* r1,
+                    const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2) {
+  return guarded(c, [&]() -> int {
+    require_t(c);
+    check_freqs(nvec, omega, gamma);
+    if (nvec == 0) return CCLR_OK;
+    Arena::Mark mk = c->arena.mark();
+    VecSet in = packed_buf(c, nvec), out = packed_buf(c, nvec);
+    pack_in(c, nvec, r1, r2, in, side == CCLR_RIGHT ? "r" : "l");
+    std::vector<cplx> z(nvec);
+    for (int k = 0; k < nvec; ++k) z[k] = cx(omega[k], gamma[k]);
+    cplx* zd = (cplx*)c->arena.get(sizeof(cplx) * nvec);
+    HIPCHK(hipMemcpyAsync(zd, z.data(), sizeof(cplx) * nvec, hipMemcpyHostToDevice, c->stream));
+    if (side == CCLR_RIGHT) sigma_right(c, in, out, zd);
+    else sigma_left(c, in, out, zd);
+    unpack_out(c, out, s1, s2, "output");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->arena.reset(mk);
+    return CCLR_OK;
+  });
+}
+
+int cclr_jacobian_right(cclr_ctx* c, int nvec, const double* omega, const double* gamma, const cclr_c64* r1,
+                        const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2) {
+  if (!c) return CCLR_EINVAL;
+  return jacobian(c, CCLR_RIGHT, nvec, omega, gamma, r1, r2, s1, s2);
+}
+
+int cclr_jacobian_left(cclr_ctx* c, int nvec, const double* omega, const double* gamma, const cclr_c64* l1,
+                       const cclr_c64* l2, cclr_c64* s1, cclr_c64* s2) {
+  if (!c) return CCLR_EINVAL;
+  return jacobian(c, CCLR_LEFT, nvec, omega, gamma, l1, l2, s1, s2);
+}
+
+int cclr_solve_damped(cclr_ctx* c, int side, int nrhs, const double* omega, const double* gamma, const cclr_c64* b1,
+                      const cclr_c64* b2, cclr_c64* x1, cclr_c64* x2, cclr_solve_info* info) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    require_t(c);
+    REQUIRE(side == CCLR_RIGHT || side == CCLR_LEFT, CCLR_EINVAL, "side must be CCLR_RIGHT or CCLR_LEFT");
+    check_freqs(nrhs, omega, gamma);
+    if (nrhs == 0) return CCLR_OK;
+    Arena::Mark mk = c->arena.mark();
+    VecSet rhs = packed_buf(c, nrhs), x = packed_buf(c, nrhs);
+    pack_in(c, nrhs, b1, b2, rhs, "b");
+    std::vector<cplx> z(nrhs);
+    for (int k = 0; k < nrhs; ++k) z[k] = cx(omega[k], gamma[k]);
+    const int rc = davidson(c, side, nrhs, z.data(), rhs, x, info);
+    unpack_out(c, x, x1, x2, "x");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->arena.reset(mk);
+    return rc;
+  });
+}
+
+int cclr_solve_lambda(cclr_ctx* c, cclr_solve_info* info) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int { return solve_lambda_impl(c, info); });
+}
+
+int cclr_get_lambda(const cclr_ctx* cc, cclr_c64* l1, cclr_c64* l2) {
+  cclr_ctx* c = const_cast<cclr_ctx*>(cc);
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    REQUIRE(c->have_lam, CCLR_ESTATE, "no lambda in the context");
+    VecSet l{c->lam_s.c(), c->lam_d.c(), 1};
+    unpack_out(c, l, l1, l2, "lambda");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CCLR_OK;
+  });
+}
+
+int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
+                           const double* gamma, cclr_c64* out, cclr_solve_info* info) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    auto t0 = std::chrono::steady_clock::now();
+    require_t(c);
+    REQUIRE(nx >= 1 && X && out, CCLR_EINVAL, "need nx >= 1 perturbations and an output array");
+    check_freqs(nfreq, omega, gamma);
+    const i64 n = c->o + c->v, ov = c->ns(), nd = c->nd();
+    for (int p = 0; p < nx; ++p) {
+      check_ptr(X[p], "X");
+      Arena::Mark mk = c->arena.mark();
+      check_finite(c, (const cplx*)X[p], n * n, "X");
+      c->arena.reset(mk);
+    }
+    cclr_solve_info linfo{};
+    long nsig = 0;
+    int rc = CCLR_OK;
+    if (!c->have_lam) {
+      rc = solve_lambda_impl(c, &linfo);
+      nsig += linfo.nsigma;
+      if (rc < 0) return rc;
+    }
+    Arena::Mark mk = c->arena.mark();
+    // property vectors
+    VecSet xi = packed_buf(c, nx), eta = packed_buf(c, nx);
+    for (int p = 0; p < nx; ++p) {
+      VecSet a{xi.s + p * ov, xi.d + p * nd, 1}, b{eta.s + p * ov, eta.d + p * nd, 1};
+      build_xi(c, (const cplx*)X[p], a);
+      build_eta(c, (const cplx*)X[p], b);
+    }
+    // distinct solve frequencies: z, -z, conj z, -conj z for every requested z
+    std::vector<std::complex<double>> fr;
+    auto fid = [&](std::complex<double> w) {
+      for (size_t k = 0; k < fr.size(); ++k)
+        if (fr[k] == w) return (int)k;
+      fr.push_back(w);
+      return (int)fr.size() - 1;
+    };
+    std::vector<int> idz(nfreq), idmz(nfreq), idcz(nfreq), idmcz(nfreq);
+    for (int w = 0; w < nfreq; ++w) {
+      const std::complex<double> z(omega[w], gamma[w]);
+      idz[w] = fid(z);
+      idmz[w] = fid(-z);
+      idcz[w] = fid(std::conj(z));
+      idmcz[w] = fid(-std::conj(z));
+    }
+    const int nf = (int)fr.size();
+    const int nr = nf * nx;  // right-hand side (f, p) at index f*nx + p
+    VecSet rhs = packed_buf(c, nr), sol = packed_buf(c, nr);
+    std::vector<cplx> zr(nr);
+    for (int f = 0; f < nf; ++f)
+      for (int p = 0; p < nx; ++p) {
+        const int r = f * nx + p;
+        zr[r] = cx(fr[f].real(), fr[f].imag());
+        HIPCHK(hipMemcpyAsync(rhs.s + r * ov, xi.s + p * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(rhs.d + r * nd, xi.d + p * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, c->stream));
+      }
+    cclr_solve_info sinfo{};
+    const int rs = davidson(c, CCLR_RIGHT, nr, zr.data(), rhs, sol, &sinfo);
+    nsig += sinfo.nsigma;
+    // Hessian products for every solution (all frequencies appear as an X-side frequency)
+    VecSet tf = packed_buf(c, nr);
+    hessian_product(c, sol, tf);
+    // bilinear products
+    auto vs = [&](const VecSet& s, int k) { return std::make_pair(s.s + k * ov, s.d + k * nd); };
+    std::vector<const cplx*> hx_s, hx_d, hy_s, hy_d;
+    auto add = [&](std::pair<cplx*, cplx*> a, std::pair<cplx*, cplx*> b) {
+      hx_s.push_back(a.first), hx_d.push_back(a.second), hy_s.push_back(b.first), hy_d.push_back(b.second);
+      return (int)hx_s.size() - 1;
+    };
+    std::map<std::pair<int, int>, int> eta_t, tf_t;  // (p, r) -> pair index
+    for (int p = 0; p < nx; ++p)
+      for (int r = 0; r < nr; ++r) eta_t[{p, r}] = add(vs(eta, p), vs(sol, r));
+    for (int r1 = 0; r1 < nr; ++r1)
+      for (int r2 = 0; r2 < nr; ++r2) tf_t[{r1, r2}] = add(vs(tf, r1), vs(sol, r2));
+    const int np = (int)hx_s.size();
+    const cplx** pd = (const cplx**)c->arena.get(sizeof(cplx*) * 4 * np);
+    std::vector<const cplx*> all;
+    all.insert(all.end(), hx_s.begin(), hx_s.end());
+    all.insert(all.end(), hx_d.begin(), hx_d.end());
+    all.insert(all.end(), hy_s.begin(), hy_s.end());
+    all.insert(all.end(), hy_d.begin(), hy_d.end());
+    HIPCHK(hipMemcpyAsync(pd, all.data(), sizeof(cplx*) * 4 * np, hipMemcpyHostToDevice, c->stream));
+    cplx* partial = (cplx*)c->arena.get(sizeof(cplx) * (size_t)np * 256);
+    cplx* dots = (cplx*)c->arena.get(sizeof(cplx) * np);
+    launch_bdot(np, pd, pd + np, pd + 2 * np, pd + 3 * np, ov, nd, partial, dots, c->stream);
+    std::vector<cplx> hd(np);
+    HIPCHK(hipMemcpyAsync(hd.data(), dots, sizeof(cplx) * np, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    auto C = [&](int k) { return std::complex<double>(hd[k].x, hd[k].y); };
+    // g_pq(z) = eta^p t^q(z) + eta^q t^p(-z) + F t^p(-z) t^q(z)
+    auto g = [&](int p, int q, int fz, int fmz) {
+      const int rq = fz * nx + q, rpm = fmz * nx + p;
+      return C(eta_t[{p, rq}]) + C(eta_t[{q, rpm}]) + C(tf_t[{rpm, rq}]);
+    };
+    for (int w = 0; w < nfreq; ++w)
+      for (int p = 0; p < nx; ++p)
+        for (int q = 0; q < nx; ++q) {
+          const std::complex<double> val = 0.5 * (g(p, q, idz[w], idmz[w]) + std::conj(g(p, q, idmcz[w], idcz[w])));
+          out[((i64)w * nx + p) * nx + q] = cclr_c64{val.real(), val.imag()};
+        }
+    c->arena.reset(mk);
+    if (info) {
+      info->iters = std::max(sinfo.iters, linfo.iters);
+      info->converged = sinfo.converged && (linfo.iters == 0 || linfo.converged);
+      info->resnorm = std::max(sinfo.resnorm, linfo.resnorm);
+      info->nsigma = nsig;
+      info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV) return CCLR_ENOTCONV;
+    return CCLR_OK;
+  });
+}
+
+}  // extern "C"

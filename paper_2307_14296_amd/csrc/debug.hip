@@ -1,0 +1,81 @@
+// Internal test hooks (include/cclr_debug.h).
+#include <cstring>
+
+#include "../../include/cclr_debug.h"
+#include "internal.h"
+
+extern "C" {
+
+int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long sAb, long long sAm, long long sAk,
+                   int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn, int conjB, cclr_c64* C,
+                   long long sCb, long long sCm, long long sCn, double ar, double ai, int beta) {
+  try {
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    g.A = (const cplx*)A; g.sAb = sAb; g.sAm = sAm; g.sAk = sAk; g.conjA = conjA;
+    g.B = (const cplx*)B; g.sBb = sBb; g.sBk = sBk; g.sBn = sBn; g.conjB = conjB;
+    g.C = (cplx*)C; g.sCb = sCb; g.sCm = sCm; g.sCn = sCn;
+    g.ar = ar; g.ai = ai; g.beta = beta;
+    launch_zgemm(g, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+    return CCLR_OK;
+  } catch (const CclrError& e) {
+    return e.code;
+  }
+}
+
+static Ten dten(const cclr_c64* p, const char* l, const long long* dims) {
+  Ten t;
+  t.p = (cplx*)p;
+  t.nd = (int)strlen(l);
+  i64 s = 1;
+  for (int d = t.nd - 1; d >= 0; --d) {
+    t.dim[d] = dims[d];
+    t.st[d] = s;
+    s *= dims[d];
+  }
+  return t;
+}
+
+int cclr_dbg_contract(cclr_ctx* c, double ar, double ai, const cclr_c64* A, const char* la, const long long* adims,
+                      const cclr_c64* B, const char* lb, const long long* bdims, cclr_c64* C, const char* lc,
+                      const long long* cdims) {
+  if (!c) return CCLR_EINVAL;
+  try {
+    contract(c, cx(ar, ai), dten(A, la, adims), la, dten(B, lb, bdims), lb, dten(C, lc, cdims), lc, true);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CCLR_OK;
+  } catch (const CclrError& e) {
+    c->err = e.what();
+    return e.code;
+  }
+}
+
+int cclr_dbg_get(cclr_ctx* c, const char* name, cclr_c64* dst, long long* count) {
+  if (!c || !name) return CCLR_EINVAL;
+  DevBuf* b = nullptr;
+  const std::string n(name);
+  if (n == "Foo") b = &c->Foo;
+  else if (n == "Fvv") b = &c->Fvv;
+  else if (n == "Fov") b = &c->Fov;
+  else if (n == "Woooo") b = &c->Woooo;
+  else if (n == "Wovvo") b = &c->Wovvo;
+  else if (n == "Wbar") b = &c->Wbar;
+  else if (n == "Wooov") b = &c->Wooov;
+  else if (n == "Wvovv") b = &c->Wvovv;
+  else if (n == "Wovoo") b = &c->Wovoo;
+  else if (n == "Wvvvo") b = &c->Wvvvo;
+  else if (n == "Wvvvv") b = &c->Wvvvv;
+  else if (n == "Wp") b = &c->Wp;
+  else if (n == "diag") b = &c->diag;
+  if (!b) {
+    c->err = "unknown intermediate " + n;
+    return CCLR_EINVAL;
+  }
+  if (count) *count = (long long)(b->bytes / sizeof(cplx));
+  if (dst && b->p) {
+    if (hipMemcpy(dst, b->p, b->bytes, hipMemcpyDeviceToDevice) != hipSuccess) return CCLR_EHIP;
+  }
+  return CCLR_OK;
+}
+}

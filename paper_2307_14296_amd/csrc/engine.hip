@@ -1,0 +1,410 @@
+// Device memory management, tensor views and the contraction engine.
+//
+// contract() evaluates C[lc] += alpha * sum A[la] B[lb] by classifying the
+// labels (batch: in A, B and C; M: A and C; N: B and C; K: A and B), viewing
+// each operand as a strided [batch][M][K] / [batch][K][N] / [batch][M][N]
+// matrix when its axes can be merged, and copying it into a packed
+// temporary otherwise.  The product itself runs on the FP64-MFMA complex
+// GEMM kernel.
+#include <algorithm>
+#include <cstring>
+
+#include "internal.h"
+
+// ------------------------------------------------------------ allocation
+void DevBuf::alloc(cclr_ctx* c, size_t nbytes) {
+  release();
+  if (nbytes == 0) return;
+  if (c->opt.device_mem_cap && c->allocated + nbytes > c->opt.device_mem_cap)
+    throw CclrError(CCLR_ENOMEM, "device memory cap exceeded (" + std::to_string(c->allocated + nbytes) +
+                                     " > " + std::to_string(c->opt.device_mem_cap) + " bytes)");
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw CclrError(CCLR_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
+  }
+  ctx = c;
+  bytes = nbytes;
+  c->allocated += nbytes;
+}
+
+void DevBuf::release() {
+  if (p) {
+    (void)hipFree(p);
+    if (ctx) ctx->allocated -= bytes;
+  }
+  p = nullptr;
+  bytes = 0;
+}
+
+Arena::~Arena() {
+  for (auto* b : chunks) delete b;
+}
+
+void* Arena::get(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (!chunks.empty() && used.back() + bytes <= chunks.back()->bytes) {
+    void* p = (char*)chunks.back()->p + used.back();
+    used.back() += bytes;
+    return p;
+  }
+  DevBuf* b = new DevBuf();
+  try {
+    b->alloc(ctx, std::max(bytes, chunk_bytes));
+  } catch (...) {
+    delete b;
+    throw;
+  }
+  chunks.push_back(b);
+  used.push_back(bytes);
+  return b->p;
+}
+
+Arena::Mark Arena::mark() const { return {chunks.size(), used.empty() ? 0 : used.back()}; }
+
+void Arena::reset(Mark m) {
+  // chunks allocated after the mark are kept for reuse but emptied
+  for (size_t k = m.nchunks; k < chunks.size(); ++k) used[k] = 0;
+  if (m.nchunks > 0) used[m.nchunks - 1] = m.top;
+  // fold: drop empty trailing chunks so the next get() reuses the last live one
+  while (chunks.size() > m.nchunks && chunks.size() > 0 && used.back() == 0 && chunks.size() > 1) {
+    // keep one spare chunk around to avoid allocation churn
+    if (chunks.size() == m.nchunks + 1) break;
+    delete chunks.back();
+    chunks.pop_back();
+    used.pop_back();
+  }
+}
+
+// ------------------------------------------------------------------ views
+Ten ten(cplx* p, std::initializer_list<i64> dims) {
+  Ten t;
+  t.p = p;
+  t.nd = (int)dims.size();
+  int d = 0;
+  for (i64 x : dims) t.dim[d++] = x;
+  i64 s = 1;
+  for (d = t.nd - 1; d >= 0; --d) {
+    t.st[d] = s;
+    s *= t.dim[d];
+  }
+  return t;
+}
+
+Ten ten(const DevBuf& b, std::initializer_list<i64> dims) { return ten(b.c(), dims); }
+
+Ten reorder(const Ten& t, const char* from, const char* to) {
+  Ten r = t;
+  const int n = t.nd;
+  REQUIRE((int)strlen(from) == n && (int)strlen(to) == n, CCLR_EINVAL, "reorder: label count");
+  for (int d = 0; d < n; ++d) {
+    const char* q = strchr(from, to[d]);
+    REQUIRE(q, CCLR_EINVAL, "reorder: unknown label");
+    const int s = (int)(q - from);
+    r.dim[d] = t.dim[s];
+    r.st[d] = t.st[s];
+  }
+  return r;
+}
+
+Ten scaled(const Ten& t, double re, double im) {
+  Ten r = t;
+  const double nr = t.sr * re - t.si * im, ni = t.sr * im + t.si * re;
+  r.sr = nr;
+  r.si = ni;
+  return r;
+}
+
+Ten conjugated(const Ten& t) {
+  // conj(s * conj?(x)) = conj(s) * conj(conj?(x))
+  Ten r = t;
+  r.conj = !t.conj;
+  r.si = -t.si;
+  return r;
+}
+
+Ten tmp(cclr_ctx* c, std::initializer_list<i64> dims) {
+  i64 n = 1;
+  for (i64 x : dims) n *= x;
+  cplx* p = (cplx*)c->arena.get(sizeof(cplx) * (size_t)std::max<i64>(n, 1));
+  return ten(p, dims);
+}
+
+void tzero(cclr_ctx* c, const Ten& t) {
+  // only contiguous tensors are zeroed in one sweep
+  i64 n = t.size();
+  bool contig = true;
+  i64 s = 1;
+  for (int d = t.nd - 1; d >= 0; --d) {
+    if (t.dim[d] != 1 && t.st[d] != s) contig = false;
+    s *= t.dim[d];
+  }
+  if (contig) {
+    launch_fill(t.p, n, cx(0.0), c->stream);
+    return;
+  }
+  CopyArgs a{};
+  a.nd = t.nd;
+  for (int d = 0; d < t.nd; ++d) {
+    a.dim[d] = t.dim[d];
+    a.sd[d] = t.st[d];
+    a.ss[d] = 0;
+  }
+  // alpha = 0 writes zeros without reading the source
+  a.dst = t.p;
+  a.src = t.p;
+  a.ar = 0.0;
+  a.ai = 0.0;
+  a.conj = 0;
+  a.acc = 0;
+  a.total = n;
+  launch_tcopy(a, c->stream);
+}
+
+// -------------------------------------------------------- copy / permute
+static int lpos(const char* l, char ch) {
+  const char* q = strchr(l, ch);
+  return q ? (int)(q - l) : -1;
+}
+
+void tcopy(cclr_ctx* c, const Ten& dst, const char* ld, const Ten& src, const char* ls, cplx alpha,
+           bool accumulate) {
+  const int n = dst.nd;
+  REQUIRE((int)strlen(ld) == n && (int)strlen(ls) == src.nd && src.nd == n, CCLR_EINVAL, "tcopy: labels");
+  REQUIRE(!dst.conj && dst.sr == 1.0 && dst.si == 0.0, CCLR_EINVAL, "tcopy: scaled destination");
+  CopyArgs a{};
+  a.nd = n;
+  i64 total = 1;
+  for (int d = 0; d < n; ++d) {
+    const int s = lpos(ls, ld[d]);
+    REQUIRE(s >= 0 && src.dim[s] == dst.dim[d], CCLR_EINVAL, std::string("tcopy: label/dim mismatch ") + ld + " <- " + ls);
+    a.dim[d] = dst.dim[d];
+    a.sd[d] = dst.st[d];
+    a.ss[d] = src.st[s];
+    total *= dst.dim[d];
+  }
+  // alpha * s * op(x)
+  a.ar = alpha.x * src.sr - alpha.y * src.si;
+  a.ai = alpha.x * src.si + alpha.y * src.sr;
+  a.conj = src.conj ? 1 : 0;
+  a.acc = accumulate ? 1 : 0;
+  a.dst = dst.p;
+  a.src = src.p;
+  a.total = total;
+  launch_tcopy(a, c->stream);
+}
+
+// ---------------------------------------------------------------- engine
+namespace {
+struct Group {
+  std::string labels;
+  i64 size = 1;
+  i64 stride = 0;
+  bool ok = true;
+};
+
+// View the axes `g` (in this order) of tensor t with labels l as one merged
+// axis.  Succeeds if consecutive axes are nested with matching strides.
+Group merge(const Ten& t, const char* l, const std::string& g) {
+  Group r;
+  r.labels = g;
+  if (g.empty()) return r;
+  i64 size = 1;
+  i64 expect = -1;
+  for (int q = (int)g.size() - 1; q >= 0; --q) {
+    const int d = lpos(l, g[q]);
+    const i64 dim = t.dim[d], st = t.st[d];
+    if (dim == 1) continue;
+    if (expect < 0) {
+      r.stride = st;
+    } else if (st != expect) {
+      r.ok = false;
+    }
+    expect = st * dim;
+    size *= dim;
+  }
+  r.size = size;
+  if (expect < 0) r.stride = 0;
+  return r;
+}
+
+i64 labsize(const Ten& t, const char* l, char ch) { return t.dim[lpos(l, ch)]; }
+}  // namespace
+
+void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& B, const char* lb, const Ten& C,
+              const char* lc, bool accumulate) {
+  REQUIRE((int)strlen(la) == A.nd && (int)strlen(lb) == B.nd && (int)strlen(lc) == C.nd, CCLR_EINVAL,
+          std::string("contract: label count ") + la + "," + lb + "->" + lc);
+  REQUIRE(!C.conj && C.sr == 1.0 && C.si == 0.0, CCLR_EINVAL, "contract: scaled output");
+  std::string Lb, Lm, Ln, Lk;
+  for (const char* p = lc; *p; ++p) {
+    const bool inA = lpos(la, *p) >= 0, inB = lpos(lb, *p) >= 0;
+    REQUIRE(inA || inB, CCLR_EINVAL, std::string("contract: output label not in inputs: ") + lc);
+    if (inA && inB) Lb += *p;
+    else if (inA) Lm += *p;
+    else Ln += *p;
+  }
+  for (const char* p = la; *p; ++p) {
+    if (lpos(lc, *p) < 0) {
+      REQUIRE(lpos(lb, *p) >= 0, CCLR_EINVAL, std::string("contract: unsummed label ") + la);
+      Lk += *p;
+    }
+  }
+  for (const char* p = lb; *p; ++p)
+    if (lpos(lc, *p) < 0) REQUIRE(lpos(la, *p) >= 0, CCLR_EINVAL, std::string("contract: unsummed label ") + lb);
+  // sizes must agree
+  auto chk = [&](const std::string& g) {
+    for (char ch : g) {
+      i64 s = -1;
+      if (lpos(la, ch) >= 0) s = labsize(A, la, ch);
+      if (lpos(lb, ch) >= 0) REQUIRE(s < 0 || labsize(B, lb, ch) == s, CCLR_EINVAL, "contract: size mismatch");
+      if (lpos(lc, ch) >= 0 && s >= 0) REQUIRE(labsize(C, lc, ch) == s, CCLR_EINVAL, "contract: size mismatch");
+    }
+  };
+  chk(Lb), chk(Lm), chk(Ln), chk(Lk);
+
+  Arena::Mark mk = c->arena.mark();
+  // ---- A as [b][m][k]
+  Group Ab = merge(A, la, Lb), Am = merge(A, la, Lm), Ak = merge(A, la, Lk);
+  Ten Aw = A;
+  std::string law = la;
+  if (!(Ab.ok && Am.ok && Ak.ok)) {
+    std::string nl = Lb + Lm + Lk;
+    Ten T = tmp(c, {1});
+    // allocate contiguous buffer
+    i64 n = 1;
+    for (char ch : nl) n *= labsize(A, la, ch);
+    T.p = (cplx*)c->arena.get(sizeof(cplx) * (size_t)n);
+    T.nd = (int)nl.size();
+    i64 s = 1;
+    for (int d = T.nd - 1; d >= 0; --d) {
+      T.dim[d] = labsize(A, la, nl[d]);
+      T.st[d] = s;
+      s *= T.dim[d];
+    }
+    tcopy(c, T, nl.c_str(), A, la, cx(1.0), false);
+    Aw = T;
+    law = nl;
+    Ab = merge(Aw, law.c_str(), Lb), Am = merge(Aw, law.c_str(), Lm), Ak = merge(Aw, law.c_str(), Lk);
+  }
+  // ---- B as [b][k][n]
+  Group Bb = merge(B, lb, Lb), Bk = merge(B, lb, Lk), Bn = merge(B, lb, Ln);
+  Ten Bw = B;
+  std::string lbw = lb;
+  if (!(Bb.ok && Bk.ok && Bn.ok)) {
+    std::string nl = Lb + Lk + Ln;
+    i64 n = 1;
+    for (char ch : nl) n *= labsize(B, lb, ch);
+    Ten T;
+    T.p = (cplx*)c->arena.get(sizeof(cplx) * (size_t)n);
+    T.nd = (int)nl.size();
+    i64 s = 1;
+    for (int d = T.nd - 1; d >= 0; --d) {
+      T.dim[d] = labsize(B, lb, nl[d]);
+      T.st[d] = s;
+      s *= T.dim[d];
+    }
+    tcopy(c, T, nl.c_str(), B, lb, cx(1.0), false);
+    Bw = T;
+    lbw = nl;
+    Bb = merge(Bw, lbw.c_str(), Lb), Bk = merge(Bw, lbw.c_str(), Lk), Bn = merge(Bw, lbw.c_str(), Ln);
+  }
+  // ---- C as [b][m][n]
+  Group Cb = merge(C, lc, Lb), Cm = merge(C, lc, Lm), Cn = merge(C, lc, Ln);
+  // a copied operand already carries its scale and conjugation
+  const double sr = Aw.sr * Bw.sr - Aw.si * Bw.si, si = Aw.sr * Bw.si + Aw.si * Bw.sr;
+  const cplx al = cx(alpha.x * sr - alpha.y * si, alpha.x * si + alpha.y * sr);
+
+  GemmArgs g{};
+  g.M = (int)Am.size;
+  g.N = (int)Bn.size;
+  g.K = (int)Ak.size;
+  g.batch = (int)Ab.size;
+  g.A = Aw.p; g.sAb = Ab.stride; g.sAm = Am.stride; g.sAk = Ak.stride; g.conjA = Aw.conj;
+  g.B = Bw.p; g.sBb = Bb.stride; g.sBk = Bk.stride; g.sBn = Bn.stride; g.conjB = Bw.conj;
+  REQUIRE(Am.size < (1ll << 31) && Bn.size < (1ll << 31) && Ak.size < (1ll << 31) && Ab.size < 65536, CCLR_EINVAL,
+          "contract: dimension too large for one GEMM");
+
+  if (Cb.ok && Cm.ok && Cn.ok) {
+    g.C = C.p; g.sCb = Cb.stride; g.sCm = Cm.stride; g.sCn = Cn.stride;
+    g.ar = al.x; g.ai = al.y; g.beta = accumulate ? 1 : 0;
+    if (g.K == 0) {
+      if (!accumulate) tzero(c, C);
+    } else {
+      launch_zgemm(g, c->stream);
+    }
+  } else {
+    std::string nl = Lb + Lm + Ln;
+    i64 n = 1;
+    for (char ch : nl) n *= labsize(C, lc, ch);
+    Ten T;
+    T.p = (cplx*)c->arena.get(sizeof(cplx) * (size_t)n);
+    T.nd = (int)nl.size();
+    i64 s = 1;
+    for (int d = T.nd - 1; d >= 0; --d) {
+      T.dim[d] = labsize(C, lc, nl[d]);
+      T.st[d] = s;
+      s *= T.dim[d];
+    }
+    g.C = T.p;
+    g.sCb = g.M * (i64)g.N;
+    g.sCm = g.N;
+    g.sCn = 1;
+    g.ar = al.x; g.ai = al.y; g.beta = 0;
+    launch_zgemm(g, c->stream);
+    tcopy(c, C, lc, T, nl.c_str(), cx(1.0), accumulate);
+  }
+  c->arena.reset(mk);
+}
+
+// -------------------------------------------------------- integral views
+Ten fblk(cclr_ctx* c, const char* kinds) {
+  const int o = c->o, n = c->o + c->v;
+  Ten t = ten(c->f.c(), {(i64)n, (i64)n});
+  i64 off = (kinds[0] == 'o' ? 0 : o) * (i64)n + (kinds[1] == 'o' ? 0 : o);
+  t.p += off;
+  t.dim[0] = kinds[0] == 'o' ? o : c->v;
+  t.dim[1] = kinds[1] == 'o' ? o : c->v;
+  return t;
+}
+
+Ten Vblk(cclr_ctx* c, const char* kinds) {
+  const i64 o = c->o, v = c->v;
+  auto sz = [&](char k) { return k == 'o' ? o : v; };
+  std::string bra(kinds, 2), ket(kinds + 2, 2);
+  double sign = 1.0;
+  // labels track axis identity: requested axes are "pqrs"
+  std::string lab = "pqrs";
+  if (bra == "vo") { bra = "ov"; sign = -sign; std::swap(lab[0], lab[1]); }
+  if (ket == "vo") { ket = "ov"; sign = -sign; std::swap(lab[2], lab[3]); }
+  auto rank = [](const std::string& s) { return s == "oo" ? 0 : (s == "ov" ? 1 : 2); };
+  Ten base;
+  std::string baselab;
+  bool cj = false;
+  auto blk = [&](const std::string& k) -> DevBuf& {
+    if (k == "oooo") return c->Voooo;
+    if (k == "ooov") return c->Vooov;
+    if (k == "oovv") return c->Voovv;
+    if (k == "ovov") return c->Vovov;
+    if (k == "ovvv") return c->Vovvv;
+    if (k == "vvvv") return c->Vvvvv;
+    throw CclrError(CCLR_EINVAL, "Vblk: no block " + k);
+  };
+  if (rank(bra) <= rank(ket)) {
+    std::string k = bra + ket;
+    base = ten(blk(k), {sz(k[0]), sz(k[1]), sz(k[2]), sz(k[3])});
+    baselab = lab;  // base axes carry labels lab[0..3]
+  } else {
+    std::string k = ket + bra;
+    base = ten(blk(k), {sz(k[0]), sz(k[1]), sz(k[2]), sz(k[3])});
+    // V[pqrs] = conj(Vbase[rspq]): base axes are (r, s, p, q) of the request
+    baselab = std::string() + lab[2] + lab[3] + lab[0] + lab[1];
+    cj = true;
+  }
+  Ten r = reorder(base, baselab.c_str(), "pqrs");
+  r.conj = cj;
+  r.sr = sign;
+  r.si = 0.0;
+  return r;
+}

@@ -1,0 +1,134 @@
+// Property-independent Hbar intermediates (SI, "EOM-EE sigma-vectors and
+// intermediates": eqs. F_im, F_ea, F_me, W_ijmn, W_mbej, W_iemn, W_efam,
+// W_efab, barW_mbej, W_mnie, W_amef and tau).  Stored unpacked with
+// W[p][q][r][s] = W^pq_rs (bra pq, ket rs) and F[p][q] = F^p_q; W^ef_ab is
+// also kept packed (a>b, e>f) for the particle-particle ladder.
+//
+// Sign/index readings of the printed equations (each decided by second-
+// quantization brute force on random complex data): F^a_e is the Hbar
+// element with bra a and ket e; W_iemn carries -F^i_f t^ef_mn; W_efam
+// carries -P(ef) V^en_ag t^gf_mn.
+#include "internal.h"
+
+void launch_pack_vvvv(int v, const cplx* W, cplx* Wp, hipStream_t s);
+void launch_diag(int o, int v, const cplx* Foo, const cplx* Fvv, cplx* diag, hipStream_t s);
+
+void build_intermediates(cclr_ctx* c) {
+  const i64 o = c->o, v = c->v;
+  Arena::Mark mk = c->arena.mark();
+  const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
+  Ten t1 = ten(c->t1, {o, v});
+  Ten t2 = ten(c->t2, {o, o, v, v});
+  // tau^ab_ij = t^ab_ij + t^a_i t^b_j - t^b_i t^a_j
+  Ten tau = tmp(c, {o, o, v, v});
+  tcopy(c, tau, "ijab", t2, "ijab", one, false);
+  contract(c, one, t1, "ia", t1, "jb", tau, "ijab");
+  contract(c, mone, t1, "ib", t1, "ja", tau, "ijab");
+
+  auto alloc = [&](DevBuf& b, i64 n) {
+    b.alloc(c, sizeof(cplx) * (size_t)n);
+    launch_fill(b.c(), n, cx(0.0), c->stream);
+  };
+  alloc(c->Foo, o * o);
+  alloc(c->Fvv, v * v);
+  alloc(c->Fov, o * v);
+  alloc(c->Woooo, o * o * o * o);
+  alloc(c->Wovvo, o * v * v * o);
+  alloc(c->Wbar, o * v * v * o);
+  alloc(c->Wooov, o * o * o * v);
+  alloc(c->Wvovv, v * o * v * v);
+  alloc(c->Wovoo, o * v * o * o);
+  alloc(c->Wvvvo, v * v * v * o);
+  alloc(c->Wvvvv, v * v * v * v);
+
+  Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
+  Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o}), Wbar = ten(c->Wbar, {o, v, v, o});
+  Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
+  Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o}), Wvvvv = ten(c->Wvvvv, {v, v, v, v});
+  Ten Voovv = Vblk(c, "oovv");
+
+  // F^i_m = f^i_m + f^i_e t^e_m + V^in_me t^e_n + 1/2 V^in_ef tau^ef_mn
+  tcopy(c, Foo, "im", fblk(c, "oo"), "im", one);
+  contract(c, one, fblk(c, "ov"), "ie", t1, "me", Foo, "im");
+  contract(c, one, Vblk(c, "ooov"), "inme", t1, "ne", Foo, "im");
+  contract(c, half, Voovv, "inef", tau, "mnef", Foo, "im");
+  // F^a_e = f^a_e - f^m_e t^a_m + V^am_ef t^f_m - 1/2 V^mn_ef tau^af_mn
+  tcopy(c, Fvv, "ae", fblk(c, "vv"), "ae", one);
+  contract(c, mone, fblk(c, "ov"), "me", t1, "ma", Fvv, "ae");
+  contract(c, one, Vblk(c, "vovv"), "amef", t1, "mf", Fvv, "ae");
+  contract(c, mhalf, Voovv, "mnef", tau, "mnaf", Fvv, "ae");
+  // F^m_e = f^m_e + V^mn_ef t^f_n
+  tcopy(c, Fov, "me", fblk(c, "ov"), "me", one);
+  contract(c, one, Voovv, "mnef", t1, "nf", Fov, "me");
+  // W^ij_mn = V^ij_mn + P(mn) V^ij_en t^e_m + 1/2 V^ij_ef tau^ef_mn
+  tcopy(c, Woooo, "ijmn", Vblk(c, "oooo"), "ijmn", one);
+  {
+    Ten w = tmp(c, {o, o, o, o});
+    contract(c, one, Vblk(c, "oovo"), "ijen", t1, "me", w, "ijmn", false);
+    tcopy(c, Woooo, "ijmn", w, "ijmn", one);
+    tcopy(c, Woooo, "ijmn", w, "ijnm", mone);
+  }
+  contract(c, half, Voovv, "ijef", tau, "mnef", Woooo, "ijmn");
+  // W^mb_ej = V^mb_ej + V^mb_ef t^f_j - V^mn_ej t^b_n - V^mn_ef (t^fb_jn + t^f_j t^b_n)
+  tcopy(c, Wovvo, "mbej", Vblk(c, "ovvo"), "mbej", one);
+  contract(c, one, Vblk(c, "ovvv"), "mbef", t1, "jf", Wovvo, "mbej");
+  contract(c, mone, Vblk(c, "oovo"), "mnej", t1, "nb", Wovvo, "mbej");
+  {
+    Ten w = tmp(c, {o, o, v, v});  // t^fb_jn + t^f_j t^b_n, labels jnfb
+    tcopy(c, w, "jnfb", t2, "jnfb", one, false);
+    contract(c, one, t1, "jf", t1, "nb", w, "jnfb");
+    contract(c, mone, Voovv, "mnef", w, "jnfb", Wovvo, "mbej");
+  }
+  // barW^mb_ej = V^mb_ej - V^mn_ef t^bf_nj
+  tcopy(c, Wbar, "mbej", Vblk(c, "ovvo"), "mbej", one);
+  contract(c, mone, Voovv, "mnef", t2, "njbf", Wbar, "mbej");
+  // W^mn_ie = V^mn_ie + t^f_i V^mn_fe
+  tcopy(c, Wooov, "mnie", Vblk(c, "ooov"), "mnie", one);
+  contract(c, one, t1, "if", Voovv, "mnfe", Wooov, "mnie");
+  // W^am_ef = V^am_ef - V^nm_ef t^a_n
+  tcopy(c, Wvovv, "amef", Vblk(c, "vovv"), "amef", one);
+  contract(c, mone, Voovv, "nmef", t1, "na", Wvovv, "amef");
+  // W^ef_ab = V^ef_ab - P(ef) V^mf_ab t^e_m + 1/2 V^mn_ab tau^ef_mn
+  tcopy(c, Wvvvv, "efab", Vblk(c, "vvvv"), "efab", one);
+  {
+    Ten w = tmp(c, {v, v, v, v});
+    contract(c, one, Vblk(c, "ovvv"), "mfab", t1, "me", w, "efab", false);
+    tcopy(c, Wvvvv, "efab", w, "efab", mone);
+    tcopy(c, Wvvvv, "efab", w, "feab", one);
+  }
+  contract(c, half, Voovv, "mnab", tau, "mnef", Wvvvv, "efab");
+  // W^ie_mn = V^ie_mn - F^i_f t^ef_mn - W^io_mn t^e_o + 1/2 V^ie_fg tau^fg_mn
+  //          + P(mn) barW^ie_fn t^f_m + P(mn) V^io_mf t^ef_no
+  tcopy(c, Wovoo, "iemn", Vblk(c, "ovoo"), "iemn", one);
+  contract(c, mone, Fov, "if", t2, "mnef", Wovoo, "iemn");
+  contract(c, mone, Woooo, "iomn", t1, "oe", Wovoo, "iemn");
+  contract(c, half, Vblk(c, "ovvv"), "iefg", tau, "mnfg", Wovoo, "iemn");
+  {
+    Ten w = tmp(c, {o, v, o, o});
+    contract(c, one, Wbar, "iefn", t1, "mf", w, "iemn", false);
+    contract(c, one, Vblk(c, "ooov"), "iomf", t2, "noef", w, "iemn");
+    tcopy(c, Wovoo, "iemn", w, "iemn", one);
+    tcopy(c, Wovoo, "iemn", w, "ienm", mone);
+  }
+  // W^ef_am = V^ef_am - P(ef) V^en_ag t^gf_mn + W^ef_ag t^g_m + F^n_a t^ef_mn
+  //          + 1/2 V^no_am tau^ef_no - P(ef) barW^nf_am t^e_n
+  tcopy(c, Wvvvo, "efam", Vblk(c, "vvvo"), "efam", one);
+  {
+    Ten w = tmp(c, {v, v, v, o});
+    contract(c, mone, Vblk(c, "vovv"), "enag", t2, "mngf", w, "efam", false);
+    contract(c, mone, Wbar, "nfam", t1, "ne", w, "efam");
+    tcopy(c, Wvvvo, "efam", w, "efam", one);
+    tcopy(c, Wvvvo, "efam", w, "feam", mone);
+  }
+  contract(c, one, Wvvvv, "efag", t1, "mg", Wvvvo, "efam");
+  contract(c, one, Fov, "na", t2, "mnef", Wvvvo, "efam");
+  contract(c, half, Vblk(c, "oovo"), "noam", tau, "noef", Wvvvo, "efam");
+
+  // packed ladder operator and preconditioner diagonal
+  c->Wp.alloc(c, sizeof(cplx) * (size_t)(c->V2() * c->V2()));
+  launch_pack_vvvv((int)v, c->Wvvvv.c(), c->Wp.c(), c->stream);
+  c->diag.alloc(c, sizeof(cplx) * (size_t)(c->ns() + c->nd()));
+  launch_diag((int)o, (int)v, c->Foo.c(), c->Fvv.c(), c->diag.c(), c->stream);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->arena.reset(mk);
+}

@@ -1,0 +1,174 @@
+// Internal declarations of libcclr: context, device buffers, tensor views,
+// the contraction engine and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+#include <stdexcept>
+
+#include "../../include/cclr.h"
+
+typedef double2 cplx;
+typedef long long i64;
+
+// ------------------------------------------------------------------ errors
+struct CclrError : public std::runtime_error {
+  int code;
+  CclrError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e__ = (expr);                                                          \
+    if (e__ != hipSuccess)                                                            \
+      throw CclrError(CCLR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
+  } while (0)
+
+#define REQUIRE(cond, code, msg) \
+  do {                           \
+    if (!(cond)) throw CclrError(code, msg); \
+  } while (0)
+
+// ------------------------------------------------------- device memory
+struct cclr_ctx;
+
+// RAII device allocation accounted against the context's cap.
+struct DevBuf {
+  cclr_ctx* ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(cclr_ctx* c, size_t nbytes);
+  void release();
+  cplx* c() const { return (cplx*)p; }
+};
+
+// Bump allocator for temporaries; grows by whole new chunks, reset by marks.
+struct Arena {
+  cclr_ctx* ctx = nullptr;
+  std::vector<DevBuf*> chunks;
+  std::vector<size_t> used;
+  size_t chunk_bytes = size_t(256) << 20;
+  ~Arena();
+  void* get(size_t bytes);
+  struct Mark { size_t nchunks, top; };
+  Mark mark() const;
+  void reset(Mark m);
+};
+
+// ----------------------------------------------------------- tensor views
+// A strided complex tensor (up to 6 dims).  When read, an element is
+// scale * (conj ? conj(x) : x).
+struct Ten {
+  cplx* p = nullptr;
+  int nd = 0;
+  i64 dim[6] = {0, 0, 0, 0, 0, 0};
+  i64 st[6] = {0, 0, 0, 0, 0, 0};
+  bool conj = false;
+  double sr = 1.0, si = 0.0;
+  i64 size() const {
+    i64 s = 1;
+    for (int d = 0; d < nd; ++d) s *= dim[d];
+    return s;
+  }
+};
+
+Ten ten(cplx* p, std::initializer_list<i64> dims);      // contiguous row-major
+Ten ten(const DevBuf& b, std::initializer_list<i64> dims);
+// Reorder the axes of a view: `from` names the axes of t, `to` the new order.
+Ten reorder(const Ten& t, const char* from, const char* to);
+Ten scaled(const Ten& t, double re, double im = 0.0);
+Ten conjugated(const Ten& t);
+
+// ------------------------------------------------------------- kernels
+struct GemmArgs {
+  int M, N, K, batch;
+  const cplx* A; i64 sAb, sAm, sAk; int conjA;
+  const cplx* B; i64 sBb, sBk, sBn; int conjB;
+  cplx* C; i64 sCb, sCm, sCn;
+  double ar, ai;   // alpha
+  int beta;        // 0: C = alpha*AB, 1: C += alpha*AB
+};
+void launch_zgemm(const GemmArgs& g, hipStream_t s);
+
+struct CopyArgs {
+  int nd;
+  i64 dim[6], sd[6], ss[6];
+  cplx* dst;
+  const cplx* src;
+  double ar, ai;
+  int conj;
+  int acc;
+  i64 total;
+};
+void launch_tcopy(const CopyArgs& a, hipStream_t s);
+void launch_fill(cplx* p, i64 n, cplx val, hipStream_t s);
+
+// packed excitation-vector sets: singles s[k][o*v], doubles d[k][O2][V2]
+struct VecSet {
+  cplx* s = nullptr;
+  cplx* d = nullptr;
+  int n = 0;
+};
+
+void launch_unpack(int nvec, int o, int v, const cplx* s, const cplx* d, cplx* r1, cplx* r2, hipStream_t st);
+void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cplx* s, cplx* d, hipStream_t st);
+// out(packed) += X0 + P(ab)Xa + P(ij)Xi + P(ab)P(ij)Xai  (any X may be null),
+// singles out += S1; then out -= z_k * r_k  (z may be null).
+void launch_pack_sigma(int nvec, int o, int v, const cplx* X0, const cplx* Xa, const cplx* Xi, const cplx* Xai,
+                       const cplx* S1, cplx* outs, cplx* outd, const cplx* zk, const cplx* rs, const cplx* rd,
+                       hipStream_t st);
+
+// ------------------------------------------------------------ context
+struct cclr_ctx {
+  int o = 0, v = 0;
+  cclr_options opt{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  size_t allocated = 0;
+  int device = 0;
+
+  // inputs
+  DevBuf f, Voooo, Vooov, Voovv, Vovov, Vovvv, Vvvvv, t1, t2;
+  bool have_H = false, have_t = false, have_lam = false;
+  // intermediates (unpacked, W[p][q][r][s] = W^pq_rs)
+  DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo, Wvvvv;
+  DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f
+  DevBuf diag;       // Fock-like diagonal for preconditioning: singles then doubles (packed)
+  DevBuf lam_s, lam_d;  // lambda, packed
+  Arena arena;
+
+  i64 O2() const { return (i64)o * (o - 1) / 2; }
+  i64 V2() const { return (i64)v * (v - 1) / 2; }
+  i64 ns() const { return (i64)o * v; }
+  i64 nd() const { return O2() * V2(); }
+};
+
+// integral block views (any kinds string, e.g. "vovv"), derived by symmetry
+Ten Vblk(cclr_ctx* c, const char* kinds);
+Ten fblk(cclr_ctx* c, const char* kinds);
+
+// ------------------------------------------------------ contraction engine
+// C[lc] (+)= alpha * sum A[la] B[lb]  (labels: one char per axis)
+void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& B, const char* lb,
+              const Ten& C, const char* lc, bool accumulate = true);
+// dst[ld] (+)= alpha * src[ls]   (ls a permutation of ld)
+void tcopy(cclr_ctx* c, const Ten& dst, const char* ld, const Ten& src, const char* ls, cplx alpha,
+           bool accumulate = true);
+void tzero(cclr_ctx* c, const Ten& t);
+Ten tmp(cclr_ctx* c, std::initializer_list<i64> dims);
+
+inline cplx cx(double r, double i = 0.0) { return make_double2(r, i); }
+
+// ------------------------------------------------------------ schedule
+void build_intermediates(cclr_ctx* c);
+// sigma for nvec packed vectors in `in` -> `out` (packed); z per vector (may be null)
+void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_dev);
+void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_dev);

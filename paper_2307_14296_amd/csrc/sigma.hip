@@ -1,0 +1,139 @@
+// Right and left EOM-EE sigma vectors (SI, eqs. sigma_sin-ee,
+// sigma_double-ee, sigma_sin-ee-left, sigma_double-ee-left) on packed
+// vector sets.
+//
+// The doubles of every term are accumulated unsymmetrized into four groups
+// (no permutation operator, P(ab), P(ij), P(ab)P(ij)); the antisymmetrizers
+// are applied once, while packing the i>j, a>b result.  The particle-
+// particle ladder 1/2 W^ab_ef r^ef_ij is evaluated directly on packed pairs:
+// sigma[IJ][AB] = sum_EF r[IJ][EF] W[AB][EF]  (right) and
+// sigma[IJ][AB] = sum_EF l[IJ][EF] W[EF][AB]  (left), with e>f so the 1/2
+// is absorbed.  Readings applied: the right-singles ring element is W^ma_ei;
+// the left doubles carry -P(ab) l^m_a W^ij_mb, P(ij) l^i_e W^ej_ab and
+// 1/2 l^ij_ef W^ef_ab.
+#include "internal.h"
+
+namespace {
+struct Acc {
+  Ten X0, Xa, Xi, Xai, S1, R1, R2;
+};
+
+Acc prepare(cclr_ctx* c, const VecSet& in) {
+  const i64 o = c->o, v = c->v, k = in.n;
+  Acc a;
+  a.R1 = ten(in.s, {k, o, v});
+  a.R2 = tmp(c, {k, o, o, v, v});
+  launch_unpack((int)k, (int)o, (int)v, in.s, in.d, nullptr, a.R2.p, c->stream);
+  a.X0 = tmp(c, {k, o, o, v, v});
+  a.Xa = tmp(c, {k, o, o, v, v});
+  a.Xi = tmp(c, {k, o, o, v, v});
+  a.Xai = tmp(c, {k, o, o, v, v});
+  a.S1 = tmp(c, {k, o, v});
+  for (Ten* t : {&a.X0, &a.Xa, &a.Xi, &a.Xai, &a.S1}) launch_fill(t->p, t->size(), cx(0.0), c->stream);
+  return a;
+}
+
+void ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
+  const i64 V2 = c->V2(), O2 = c->O2();
+  GemmArgs g{};
+  g.M = (int)(O2 * in.n);
+  g.N = (int)V2;
+  g.K = (int)V2;
+  g.batch = 1;
+  g.A = in.d; g.sAb = 0; g.sAm = V2; g.sAk = 1; g.conjA = 0;
+  g.B = c->Wp.c(); g.sBb = 0; g.conjB = 0;
+  if (right) { g.sBk = 1; g.sBn = V2; }
+  else { g.sBk = V2; g.sBn = 1; }
+  g.C = out.d; g.sCb = 0; g.sCm = V2; g.sCn = 1;
+  g.ar = 1.0; g.ai = 0.0; g.beta = 0;
+  launch_zgemm(g, c->stream);
+}
+}  // namespace
+
+void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z) {
+  const i64 o = c->o, v = c->v, nv = in.n;
+  Arena::Mark mk = c->arena.mark();
+  const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
+  Acc a = prepare(c, in);
+  Ten t2 = ten(c->t2, {o, o, v, v});
+  Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
+  Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
+  Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
+  Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
+  // singles
+  contract(c, one, Fvv, "ae", a.R1, "kie", a.S1, "kia");
+  contract(c, mone, Foo, "mi", a.R1, "kma", a.S1, "kia");
+  contract(c, one, Fov, "me", a.R2, "kmiea", a.S1, "kia");
+  contract(c, one, Wovvo, "maei", a.R1, "kme", a.S1, "kia");
+  contract(c, half, Wvovv, "amef", a.R2, "kimef", a.S1, "kia");
+  contract(c, half, Wooov, "mnie", a.R2, "kmnea", a.S1, "kia");
+  // doubles
+  contract(c, mone, Wovoo, "mbij", a.R1, "kma", a.Xa, "kijab");
+  contract(c, one, Wvvvo, "abej", a.R1, "kie", a.Xi, "kijab");
+  {
+    Ten Y = tmp(c, {nv, v, v});  // W^bm_fe r^e_m
+    contract(c, one, Wvovv, "bmfe", a.R1, "kme", Y, "kbf", false);
+    contract(c, one, t2, "ijaf", Y, "kbf", a.Xa, "kijab");
+    Ten Z = tmp(c, {nv, o, o});  // W^nm_je r^e_m
+    contract(c, one, Wooov, "nmje", a.R1, "kme", Z, "knj", false);
+    contract(c, mone, t2, "inab", Z, "knj", a.Xi, "kijab");
+  }
+  contract(c, one, Fvv, "be", a.R2, "kijae", a.Xa, "kijab");
+  contract(c, mone, Foo, "mj", a.R2, "kimab", a.Xi, "kijab");
+  contract(c, half, Woooo, "mnij", a.R2, "kmnab", a.X0, "kijab");
+  contract(c, one, Wovvo, "mbej", a.R2, "kimae", a.Xai, "kijab");
+  {
+    Ten Voovv = Vblk(c, "oovv");
+    Ten Q = tmp(c, {nv, v, v});  // V^nm_fe r^ea_mn
+    contract(c, one, Voovv, "nmfe", a.R2, "kmnea", Q, "kfa", false);
+    contract(c, mhalf, t2, "ijfb", Q, "kfa", a.Xa, "kijab");
+    Ten P = tmp(c, {nv, o, o});  // V^nm_fe r^fe_im
+    contract(c, one, Voovv, "nmfe", a.R2, "kimfe", P, "kni", false);
+    contract(c, mhalf, t2, "jnba", P, "kni", a.Xi, "kijab");
+  }
+  ladder(c, in, out, true);
+  launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
+  launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
+                    c->stream);
+  c->arena.reset(mk);
+}
+
+void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z) {
+  const i64 o = c->o, v = c->v, nv = in.n;
+  Arena::Mark mk = c->arena.mark();
+  const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
+  Acc a = prepare(c, in);
+  Ten t2 = ten(c->t2, {o, o, v, v});
+  Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
+  Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
+  Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
+  Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
+  Ten Voovv = Vblk(c, "oovv");
+  // G^e_a = -1/2 l^mn_af t^ef_mn ; G^i_m = 1/2 l^in_ef t^ef_mn  (SI, eqs. G_ea, G_mi)
+  Ten Gvv = tmp(c, {nv, v, v}), Goo = tmp(c, {nv, o, o});
+  contract(c, mhalf, a.R2, "kmnaf", t2, "mnef", Gvv, "kea", false);
+  contract(c, half, a.R2, "kinef", t2, "mnef", Goo, "kim", false);
+  // singles
+  contract(c, one, a.R1, "kie", Fvv, "ea", a.S1, "kia");
+  contract(c, mone, a.R1, "kma", Foo, "im", a.S1, "kia");
+  contract(c, half, a.R2, "kimef", Wvvvo, "efam", a.S1, "kia");
+  contract(c, mhalf, a.R2, "kmnae", Wovoo, "iemn", a.S1, "kia");
+  contract(c, mone, Gvv, "kfe", Wvovv, "eifa", a.S1, "kia");
+  contract(c, mone, Goo, "knm", Wooov, "mina", a.S1, "kia");
+  contract(c, one, a.R1, "kme", Wovvo, "ieam", a.S1, "kia");
+  // doubles
+  contract(c, one, a.R2, "kijae", Fvv, "eb", a.Xa, "kijab");
+  contract(c, mone, a.R2, "kimab", Foo, "jm", a.Xi, "kijab");
+  contract(c, half, a.R2, "kmnab", Woooo, "ijmn", a.X0, "kijab");
+  contract(c, one, a.R2, "kimae", Wovvo, "jebm", a.Xai, "kijab");
+  contract(c, one, Voovv, "ijae", Gvv, "keb", a.Xa, "kijab");
+  contract(c, mone, a.R1, "kma", Wooov, "ijmb", a.Xa, "kijab");
+  contract(c, mone, Voovv, "imab", Goo, "kjm", a.Xi, "kijab");
+  contract(c, one, a.R1, "kie", Wvovv, "ejab", a.Xi, "kijab");
+  contract(c, one, a.R1, "kia", Fov, "jb", a.Xai, "kijab");
+  ladder(c, in, out, false);
+  launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
+  launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
+                    c->stream);
+  c->arena.reset(mk);
+}

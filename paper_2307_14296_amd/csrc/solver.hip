@@ -1,0 +1,456 @@
+// Davidson-type subspace solver for the damped response and Lambda
+// equations (SI, "Davidson scheme for solving first-order response
+// equation"), device resident in FP64.
+//
+// Per right-hand side: orthonormal trial vectors b_j and their transforms
+// s_j = (A - z) b_j (or b_j (A - z) for the left problem).  The projected
+// system G' beta = -C' with G'_ij = <b_i, s_j>, C'_j = <b_j, xi> is solved by
+// LU with partial pivoting on the device; the residual is
+// R = sum_j beta_j s_j + xi; the correction (z - D)^-1 R is orthogonalized
+// against {b} by classical Gram-Schmidt applied twice and appended.  The
+// start vector is the unit vector on the largest |xi| component.  When the
+// subspace is full it restarts from the current solution.  All right-hand
+// sides advance in lockstep so each Jacobian transform is batched.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+
+namespace {
+constexpr int kThreads = 256;
+constexpr int kChunks = 512;
+
+// vector (r, j) of a set with R slots per right-hand side
+struct VS {
+  cplx* s;
+  cplx* d;
+  int R;
+};
+
+__device__ __forceinline__ const cplx* vs_s(const VS& v, int r, int j, i64 ov) { return v.s + ((i64)r * v.R + j) * ov; }
+__device__ __forceinline__ const cplx* vs_d(const VS& v, int r, int j, i64 nd) { return v.d + ((i64)r * v.R + j) * nd; }
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ cplx cconjmul(cplx a, cplx b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+
+__device__ cplx block_sum(cplx v) {
+  __shared__ double sr[kThreads], si[kThreads];
+  sr[threadIdx.x] = v.x;
+  si[threadIdx.x] = v.y;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  cplx out = make_double2(sr[0], si[0]);
+  __syncthreads();
+  return out;
+}
+
+// partial[(a*nj + j)*kChunks + chunk] = sum over chunk of conj(X[r][xj0+j]) * Y[r][yj],  r = act[a]
+__global__ __launch_bounds__(kThreads) void k_gram(VS X, int xj0, int nj, VS Y, int yj, const int* act, i64 ov, i64 nd,
+                                                   cplx* partial) {
+  const int a = blockIdx.z, j = blockIdx.y, chunk = blockIdx.x;
+  const int r = act[a];
+  const cplx* xs = vs_s(X, r, xj0 + j, ov);
+  const cplx* xd = vs_d(X, r, xj0 + j, nd);
+  const cplx* ys = vs_s(Y, r, yj, ov);
+  const cplx* yd = vs_d(Y, r, yj, nd);
+  const i64 n = ov + nd;
+  const i64 per = (n + kChunks - 1) / kChunks;
+  const i64 lo = chunk * per, hi = min(n, lo + per);
+  cplx acc = make_double2(0.0, 0.0);
+  for (i64 e = lo + threadIdx.x; e < hi; e += kThreads) {
+    const cplx x = e < ov ? xs[e] : xd[e - ov];
+    const cplx y = e < ov ? ys[e] : yd[e - ov];
+    const cplx p = cconjmul(x, y);
+    acc.x += p.x;
+    acc.y += p.y;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[((i64)a * nj + j) * kChunks + chunk] = acc;
+}
+
+// out[r*ld + col0 + j] = sum of the chunk partials (conjugated if cj)
+__global__ __launch_bounds__(kThreads) void k_reduce(const cplx* partial, int nj, const int* act, cplx* out, int ld,
+                                                     int col0, int cj) {
+  const int p = blockIdx.x;
+  cplx acc = make_double2(0.0, 0.0);
+  for (int k = threadIdx.x; k < kChunks; k += kThreads) {
+    acc.x += partial[(i64)p * kChunks + k].x;
+    acc.y += partial[(i64)p * kChunks + k].y;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) {
+    const int a = p / nj, j = p % nj;
+    if (cj) acc.y = -acc.y;
+    out[(i64)act[a] * ld + col0 + j] = acc;
+  }
+}
+
+// out[r][oj] = (acc ? out : 0) + sign * sum_j coef[r][j] X[r][xj0 + j] + (use_y ? Y[r][yj] : 0)
+__global__ __launch_bounds__(kThreads) void k_lincomb(VS out, int oj, VS X, int xj0, int nj, const cplx* coef, int ldc,
+                                                      double sign, VS Y, int yj, int use_y, int acc_out,
+                                                      const int* act, i64 ov, i64 nd) {
+  __shared__ cplx c[128];
+  const int a = blockIdx.y, r = act[a];
+  for (int j = threadIdx.x; j < nj; j += kThreads) {
+    const cplx t = coef[(i64)r * ldc + j];
+    c[j] = make_double2(sign * t.x, sign * t.y);
+  }
+  __syncthreads();
+  const i64 n = ov + nd;
+  cplx* os = (cplx*)vs_s(out, r, oj, ov);
+  cplx* od = (cplx*)vs_d(out, r, oj, nd);
+  for (i64 e = (i64)blockIdx.x * kThreads + threadIdx.x; e < n; e += (i64)gridDim.x * kThreads) {
+    cplx y = make_double2(0.0, 0.0);
+    if (acc_out) y = e < ov ? os[e] : od[e - ov];
+    for (int j = 0; j < nj; ++j) {
+      const cplx x = e < ov ? vs_s(X, r, xj0 + j, ov)[e] : vs_d(X, r, xj0 + j, nd)[e - ov];
+      const cplx p = cmul(c[j], x);
+      y.x += p.x;
+      y.y += p.y;
+    }
+    if (use_y) {
+      const cplx x = e < ov ? vs_s(Y, r, yj, ov)[e] : vs_d(Y, r, yj, nd)[e - ov];
+      y.x += x.x;
+      y.y += x.y;
+    }
+    if (e < ov) os[e] = y;
+    else od[e - ov] = y;
+  }
+}
+
+// out[r][oj] = X[r][xj] * f,  f = 1/(z_r - D) (mode 0) or 1/sqrt(Re nrm2[r]) (mode 1)
+__global__ __launch_bounds__(kThreads) void k_scale(VS out, int oj, VS X, int xj, const cplx* z, const cplx* diag,
+                                                    const cplx* nrm2, int mode, const int* act, i64 ov, i64 nd) {
+  const int a = blockIdx.y, r = act[a];
+  const i64 n = ov + nd;
+  cplx* os = (cplx*)vs_s(out, r, oj, ov);
+  cplx* od = (cplx*)vs_d(out, r, oj, nd);
+  const cplx* xs = vs_s(X, r, xj, ov);
+  const cplx* xd = vs_d(X, r, xj, nd);
+  const double f = mode == 1 ? 1.0 / sqrt(nrm2[r].x) : 0.0;
+  for (i64 e = (i64)blockIdx.x * kThreads + threadIdx.x; e < n; e += (i64)gridDim.x * kThreads) {
+    const cplx x = e < ov ? xs[e] : xd[e - ov];
+    cplx y;
+    if (mode == 0) {
+      const cplx dd = diag[e];
+      const cplx w = make_double2(z[r].x - dd.x, z[r].y - dd.y);
+      const double den = w.x * w.x + w.y * w.y;
+      y = make_double2((x.x * w.x + x.y * w.y) / den, (x.y * w.x - x.x * w.y) / den);
+    } else {
+      y = make_double2(x.x * f, x.y * f);
+    }
+    if (e < ov) os[e] = y;
+    else od[e - ov] = y;
+  }
+}
+
+// unit vector on the largest |X[r]| entry (first index on ties); one block per right-hand side
+__global__ __launch_bounds__(kThreads) void k_pivot(VS out, VS X, const int* act, i64 ov, i64 nd) {
+  const int a = blockIdx.x, r = act[a];
+  const cplx* xs = vs_s(X, r, 0, ov);
+  const cplx* xd = vs_d(X, r, 0, nd);
+  const i64 n = ov + nd;
+  double best = -1.0;
+  i64 bi = 0;
+  for (i64 e = threadIdx.x; e < n; e += kThreads) {
+    const cplx x = e < ov ? xs[e] : xd[e - ov];
+    const double m = x.x * x.x + x.y * x.y;
+    if (m > best) { best = m; bi = e; }
+  }
+  __shared__ double sb[kThreads];
+  __shared__ i64 si[kThreads];
+  sb[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double ob = sb[threadIdx.x + s];
+      const i64 oi = si[threadIdx.x + s];
+      if (ob > sb[threadIdx.x] || (ob == sb[threadIdx.x] && oi < si[threadIdx.x])) {
+        sb[threadIdx.x] = ob;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const i64 p = si[0];
+  cplx* os = (cplx*)vs_s(out, r, 0, ov);
+  cplx* od = (cplx*)vs_d(out, r, 0, nd);
+  for (i64 e = threadIdx.x; e < n; e += kThreads) {
+    const cplx y = make_double2(e == p ? 1.0 : 0.0, 0.0);
+    if (e < ov) os[e] = y;
+    else od[e - ov] = y;
+  }
+}
+
+// Solve G[r] beta[r] = -C[r] (order m, leading dim ld) by Gaussian
+// elimination with partial pivoting; one block per active right-hand side.
+// W is scratch [nact][ld][ld+1].
+__global__ __launch_bounds__(kThreads) void k_small_solve(const cplx* G, const cplx* C, int m, int ld, cplx* W,
+                                                          cplx* beta, int* singular, const int* act) {
+  const int a = blockIdx.x, r = act[a];
+  const int lw = ld + 1;
+  cplx* M = W + (i64)a * ld * lw;
+  for (int e = threadIdx.x; e < m * (m + 1); e += kThreads) {
+    const int i = e / (m + 1), j = e % (m + 1);
+    cplx x = j < m ? G[((i64)r * ld + i) * ld + j] : C[(i64)r * ld + i];
+    if (j == m) { x.x = -x.x; x.y = -x.y; }
+    M[i * lw + j] = x;
+  }
+  __syncthreads();
+  __shared__ int piv;
+  for (int k = 0; k < m; ++k) {
+    if (threadIdx.x == 0) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k; i < m; ++i) {
+        const cplx x = M[i * lw + k];
+        const double mag = x.x * x.x + x.y * x.y;
+        if (mag > best) { best = mag; bi = i; }
+      }
+      piv = bi;
+      if (best == 0.0) singular[r] = 1;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k)
+      for (int j = threadIdx.x; j <= m; j += kThreads) {
+        const cplx t = M[k * lw + j];
+        M[k * lw + j] = M[p * lw + j];
+        M[p * lw + j] = t;
+      }
+    __syncthreads();
+    const cplx d = M[k * lw + k];
+    const double den = d.x * d.x + d.y * d.y;
+    const int w = m - k;  // columns k+1 .. m (m = right-hand side column)
+    for (int e = threadIdx.x; e < (m - k - 1) * w; e += kThreads) {
+      const int i = k + 1 + e / w, j = k + 1 + e % w;
+      const cplx lik = M[i * lw + k];
+      const cplx f = make_double2((lik.x * d.x + lik.y * d.y) / den, (lik.y * d.x - lik.x * d.y) / den);
+      const cplx mkj = M[k * lw + j];
+      M[i * lw + j].x -= f.x * mkj.x - f.y * mkj.y;
+      M[i * lw + j].y -= f.x * mkj.y + f.y * mkj.x;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int i = m - 1; i >= 0; --i) {
+      cplx s = M[i * lw + m];
+      for (int j = i + 1; j < m; ++j) {
+        const cplx b = beta[(i64)r * ld + j];
+        const cplx g = M[i * lw + j];
+        s.x -= g.x * b.x - g.y * b.y;
+        s.y -= g.x * b.y + g.y * b.x;
+      }
+      const cplx d = M[i * lw + i];
+      const double den = d.x * d.x + d.y * d.y;
+      beta[(i64)r * ld + i] = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+    }
+  }
+}
+
+// G[r][row q][j] = vals[r][j] (as_row) or G[r][j][col q] = vals[r][j]
+__global__ void k_put(const cplx* vals, int nj, cplx* G, int ld, int q, int as_row, const int* act) {
+  const int r = act[blockIdx.x];
+  for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+    const cplx x = vals[(i64)r * ld + j];
+    if (as_row) G[((i64)r * ld + q) * ld + j] = x;
+    else G[((i64)r * ld + j) * ld + q] = x;
+  }
+}
+
+unsigned vgrid(i64 n) {
+  i64 g = (n + kThreads - 1) / kThreads;
+  if (g > 2048) g = 2048;
+  return (unsigned)std::max<i64>(g, 1);
+}
+}  // namespace
+
+// --------------------------------------------------------------- driver
+int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
+             cclr_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  const i64 ov = c->ns(), nd = c->nd(), n = ov + nd;
+  const int ms = std::max(4, std::min(c->opt.max_subspace, 120));
+  hipStream_t st = c->stream;
+  Arena::Mark mk = c->arena.mark();
+  auto vbuf = [&](int nvec) {
+    VecSet v;
+    v.s = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * ov));
+    v.d = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * nd));
+    v.n = nvec;
+    return v;
+  };
+  VecSet Bv = vbuf(nr * ms), Sv = vbuf(nr * ms), Rv = vbuf(nr), Ev = vbuf(nr), Xin = vbuf(nr), Xout = vbuf(nr);
+  const VS B{Bv.s, Bv.d, ms}, S{Sv.s, Sv.d, ms}, R{Rv.s, Rv.d, 1}, E{Ev.s, Ev.d, 1};
+  const VS XI{rhs.s, rhs.d, 1}, XO{xout.s, xout.d, 1}, T{Xout.s, Xout.d, 1};
+  cplx* G = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms * ms);
+  cplx* Cp = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms);
+  cplx* beta = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms);
+  cplx* coef = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms);
+  cplx* tmpv = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms);
+  cplx* W = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms * (ms + 1));
+  cplx* partial = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms * kChunks);
+  int* act_d = (int*)c->arena.get(sizeof(int) * nr);
+  int* sing_d = (int*)c->arena.get(sizeof(int) * nr);
+  cplx* z_d = (cplx*)c->arena.get(sizeof(cplx) * nr);     // by right-hand side
+  cplx* za_d = (cplx*)c->arena.get(sizeof(cplx) * nr);    // by active position (for the transform)
+  launch_fill(G, (i64)nr * ms * ms, cx(0.0), st);
+  HIPCHK(hipMemsetAsync(sing_d, 0, sizeof(int) * nr, st));
+  HIPCHK(hipMemcpyAsync(z_d, zh, sizeof(cplx) * nr, hipMemcpyHostToDevice, st));
+
+  int na = 0;
+  // out[r*ld + col0 + j] = <X[r][xj0+j], Y[r][yj]> for active r
+  auto gram = [&](VS X, int xj0, int nj, VS Y, int yj, cplx* out, int ld, int col0, int cj) {
+    if (nj <= 0 || na <= 0) return;
+    hipLaunchKernelGGL(k_gram, dim3(kChunks, nj, na), dim3(kThreads), 0, st, X, xj0, nj, Y, yj, act_d, ov, nd,
+                       partial);
+    hipLaunchKernelGGL(k_reduce, dim3(na * nj), dim3(kThreads), 0, st, partial, nj, act_d, out, ld, col0, cj);
+  };
+  auto lincomb = [&](VS out, int oj, VS X, int xj0, int nj, const cplx* cf, int ldc, double sign, VS Y, int yj,
+                     int use_y, int acc) {
+    hipLaunchKernelGGL(k_lincomb, dim3(vgrid(n), na), dim3(kThreads), 0, st, out, oj, X, xj0, nj, cf, ldc, sign, Y,
+                       yj, use_y, acc, act_d, ov, nd);
+  };
+  auto scale = [&](VS out, int oj, VS X, int xj, const cplx* nrm2, int mode) {
+    hipLaunchKernelGGL(k_scale, dim3(vgrid(n), na), dim3(kThreads), 0, st, out, oj, X, xj, z_d, c->diag.c(), nrm2,
+                       mode, act_d, ov, nd);
+  };
+  auto fetch = [&](const cplx* src, std::vector<cplx>& h, int ld) {
+    h.resize((size_t)nr * ld);
+    HIPCHK(hipMemcpyAsync(h.data(), src, sizeof(cplx) * (size_t)nr * ld, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  };
+  std::vector<int> act;
+  auto set_active = [&](const std::vector<int>& a2) {
+    act = a2;
+    na = (int)act.size();
+    if (!na) return;
+    HIPCHK(hipMemcpyAsync(act_d, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
+    std::vector<cplx> za(na);
+    for (int a = 0; a < na; ++a) za[a] = zh[act[a]];
+    HIPCHK(hipMemcpyAsync(za_d, za.data(), sizeof(cplx) * na, hipMemcpyHostToDevice, st));
+  };
+
+  std::vector<int> all(nr);
+  for (int r = 0; r < nr; ++r) all[r] = r;
+  set_active(all);
+  std::vector<cplx> hv;
+  gram(XI, 0, 1, XI, 0, tmpv, 1, 0, 0);
+  fetch(tmpv, hv, 1);
+  std::vector<double> xinorm(nr), res(nr, 0.0);
+  std::vector<int> msub(nr, 0), done(nr, 0);
+  for (int r = 0; r < nr; ++r) {
+    xinorm[r] = std::sqrt(hv[r].x);
+    if (xinorm[r] == 0.0) done[r] = 1;  // x = 0
+  }
+  launch_fill(xout.s, (i64)nr * ov, cx(0.0), st);
+  launch_fill(xout.d, (i64)nr * nd, cx(0.0), st);
+  {
+    std::vector<int> a2;
+    for (int r = 0; r < nr; ++r)
+      if (!done[r]) a2.push_back(r);
+    set_active(a2);
+  }
+  if (na) hipLaunchKernelGGL(k_pivot, dim3(na), dim3(kThreads), 0, st, B, XI, act_d, ov, nd);
+
+  int j = 0;  // slot of the newest trial vector, shared by the active right-hand sides
+  int iters = 0;
+  long nsigma = 0;
+  auto sigma = (side == CCLR_RIGHT) ? sigma_right : sigma_left;
+  const int maxit = std::max(1, c->opt.maxiter);
+  while (na > 0) {
+    // batched transform of the newest trial vectors
+    for (int a = 0; a < na; ++a) {
+      const int r = act[a];
+      HIPCHK(hipMemcpyAsync(Xin.s + a * ov, Bv.s + ((i64)r * ms + j) * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(Xin.d + a * nd, Bv.d + ((i64)r * ms + j) * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, st));
+    }
+    VecSet vin = Xin, vout = Xout;
+    vin.n = vout.n = na;
+    sigma(c, vin, vout, za_d);
+    nsigma += na;
+    for (int a = 0; a < na; ++a) {
+      const int r = act[a];
+      HIPCHK(hipMemcpyAsync(Sv.s + ((i64)r * ms + j) * ov, Xout.s + a * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(Sv.d + ((i64)r * ms + j) * nd, Xout.d + a * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, st));
+    }
+    ++iters;
+    // extend the projected matrix by column j, row j and C'_j
+    gram(B, 0, j + 1, S, j, tmpv, ms, 0, 0);  // <b_i, s_j>
+    hipLaunchKernelGGL(k_put, dim3(na), dim3(128), 0, st, tmpv, j + 1, G, ms, j, 0, act_d);
+    if (j > 0) {
+      gram(S, 0, j, B, j, tmpv, ms, 0, 1);    // conj <s_i, b_j> = <b_j, s_i>
+      hipLaunchKernelGGL(k_put, dim3(na), dim3(128), 0, st, tmpv, j, G, ms, j, 1, act_d);
+    }
+    gram(B, j, 1, XI, 0, Cp, ms, j, 0);       // C'_j = <b_j, xi>
+    const int m = j + 1;
+    hipLaunchKernelGGL(k_small_solve, dim3(na), dim3(kThreads), 0, st, G, Cp, m, ms, W, beta, sing_d, act_d);
+    // residual R = sum_i beta_i s_i + xi and its norm
+    lincomb(R, 0, S, 0, m, beta, ms, 1.0, XI, 0, 1, 0);
+    gram(R, 0, 1, R, 0, tmpv, 1, 0, 0);
+    fetch(tmpv, hv, 1);
+    std::vector<int> still;
+    for (int a = 0; a < na; ++a) {
+      const int r = act[a];
+      res[r] = std::sqrt(std::max(hv[r].x, 0.0)) / xinorm[r];
+      msub[r] = m;
+      if (res[r] <= c->opt.tol || !std::isfinite(res[r])) done[r] = 1;
+      else still.push_back(r);
+    }
+    if (still.empty() || iters >= maxit) break;
+    set_active(still);
+    // correction (z - D)^-1 R
+    scale(E, 0, R, 0, nullptr, 0);
+    int nj = m;
+    if (m == ms) {
+      // restart from the current solution: b0 = x/|x|, s0 = (sum beta s)/|x|
+      lincomb(XO, 0, B, 0, m, beta, ms, 1.0, XO, 0, 0, 0);
+      lincomb(T, 0, S, 0, m, beta, ms, 1.0, T, 0, 0, 0);
+      gram(XO, 0, 1, XO, 0, tmpv, 1, 0, 0);
+      scale(B, 0, XO, 0, tmpv, 1);
+      scale(S, 0, T, 0, tmpv, 1);
+      gram(B, 0, 1, S, 0, tmpv, ms, 0, 0);
+      hipLaunchKernelGGL(k_put, dim3(na), dim3(128), 0, st, tmpv, 1, G, ms, 0, 0, act_d);
+      gram(B, 0, 1, XI, 0, Cp, ms, 0, 0);
+      nj = 1;
+    }
+    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+      gram(B, 0, nj, E, 0, coef, ms, 0, 0);
+      lincomb(E, 0, B, 0, nj, coef, ms, -1.0, E, 0, 0, 1);
+    }
+    gram(E, 0, 1, E, 0, tmpv, 1, 0, 0);
+    j = nj;
+    scale(B, j, E, 0, tmpv, 1);
+  }
+  // solutions x_r = sum_i beta_i b_i over each right-hand side's final subspace
+  for (int r = 0; r < nr; ++r) {
+    if (msub[r] == 0) continue;
+    std::vector<int> one{r};
+    set_active(one);
+    lincomb(XO, 0, B, 0, msub[r], beta, ms, 1.0, XO, 0, 0, 0);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  c->arena.reset(mk);
+  int conv = 1;
+  double mx = 0.0;
+  for (int r = 0; r < nr; ++r) {
+    mx = std::max(mx, res[r]);
+    if (!(res[r] <= c->opt.tol)) conv = 0;
+  }
+  if (info) {
+    info->iters = iters;
+    info->resnorm = mx;
+    info->converged = conv;
+    info->nsigma = nsigma;
+    info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return conv ? CCLR_OK : CCLR_ENOTCONV;
+}

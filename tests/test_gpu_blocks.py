@@ -1,0 +1,150 @@
+"""Building blocks of the GPU library against plain numpy on the same inputs:
+the complex FP64-MFMA GEMM (layouts, ragged tiles, conjugation, alpha,
+accumulate), the contraction engine on the index patterns the schedule uses,
+and every Hbar intermediate against the oracle's."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import small_problem
+from oracle import cclr_ref as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _cc():
+    import paper_2307_14296_amd as cc
+    L = cc.lib()
+    LL = ctypes.c_longlong
+    P = ctypes.c_void_p
+    L.cclr_dbg_zgemm.argtypes = [ctypes.c_int] * 4 + [P, LL, LL, LL, ctypes.c_int, P, LL, LL, LL, ctypes.c_int,
+                                                       P, LL, LL, LL, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    L.cclr_dbg_contract.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_char_p, ctypes.POINTER(LL),
+                                    P, ctypes.c_char_p, ctypes.POINTER(LL), P, ctypes.c_char_p, ctypes.POINTER(LL)]
+    L.cclr_dbg_get.argtypes = [P, ctypes.c_char_p, P, ctypes.POINTER(LL)]
+    return cc, L
+
+
+def crand(rng, *shape):
+    return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(torch.complex128).cuda()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+GEMM_CASES = [
+    (16, 16, 4, False, False), (64, 64, 16, False, False), (1, 1, 1, False, False), (17, 33, 5, True, False),
+    (100, 70, 40, False, True), (130, 3, 129, True, True), (5, 200, 66, False, False),
+]
+
+
+@pytest.mark.parametrize("M,N,K,ta,tb", GEMM_CASES)
+def test_zgemm(gpu, M, N, K, ta, tb):
+    cc, L = _cc()
+    rng = np.random.default_rng(M * 1000 + N * 10 + K)
+    A = crand(rng, M, K)
+    B = crand(rng, K, N)
+    C0 = crand(rng, M, N)
+    alpha = 0.7 - 0.3j
+    for conjA, conjB, beta in [(0, 0, 0), (1, 0, 1), (0, 1, 1), (1, 1, 0)]:
+        Ad = dev(A.T.copy() if ta else A)
+        Bd = dev(B.T.copy() if tb else B)
+        Cd = dev(C0)
+        sAm, sAk = (1, M) if ta else (K, 1)
+        sBk, sBn = (1, K) if tb else (N, 1)
+        rc = L.cclr_dbg_zgemm(M, N, K, 1, Ad.data_ptr(), 0, sAm, sAk, conjA, Bd.data_ptr(), 0, sBk, sBn, conjB,
+                              Cd.data_ptr(), 0, N, 1, alpha.real, alpha.imag, beta)
+        assert rc == 0
+        a = A.conj() if conjA else A
+        b = B.conj() if conjB else B
+        ref = alpha * (a @ b) + (C0 if beta else 0)
+        got = Cd.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (conjA, conjB, beta)
+
+
+def test_zgemm_batched_and_transposed_output(gpu):
+    cc, L = _cc()
+    rng = np.random.default_rng(5)
+    nb, M, N, K = 3, 37, 21, 19
+    A = crand(rng, nb, M, K)
+    B = crand(rng, nb, K, N)
+    Cd = dev(np.zeros((nb, N, M)))
+    Ad, Bd = dev(A), dev(B)
+    rc = L.cclr_dbg_zgemm(M, N, K, nb, Ad.data_ptr(), M * K, K, 1, 0, Bd.data_ptr(), K * N, N, 1, 0,
+                          Cd.data_ptr(), M * N, 1, M, 1.0, 0.0, 0)
+    assert rc == 0
+    ref = np.einsum("bmk,bkn->bnm", A, B)
+    assert np.abs(Cd.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+CONTRACT_CASES = [
+    ("ae", "kie", "kia", dict(a=5, e=5, k=2, i=3)),
+    ("mbej", "kimae", "kijab", dict(m=3, b=5, e=5, j=3, k=2, i=3, a=5)),
+    ("maei", "kme", "kia", dict(m=3, a=5, e=5, i=3, k=2)),
+    ("amef", "kimef", "kia", dict(a=5, m=3, e=5, f=5, k=2, i=3)),
+    ("mnie", "kmnea", "kia", dict(m=3, n=3, i=3, e=5, a=5, k=2)),
+    ("ijaf", "kbf", "kijab", dict(i=3, j=3, a=5, f=5, k=2, b=5)),
+    ("inef", "mnef", "im", dict(i=3, n=3, e=5, f=5, m=3)),
+    ("ia", "jb", "ijab", dict(i=3, a=5, j=3, b=5)),
+    ("efag", "mg", "efam", dict(e=5, f=5, a=5, g=5, m=3)),
+    ("kmnaf", "mnef", "kea", dict(k=2, m=3, n=3, a=5, f=5, e=5)),
+]
+
+
+@pytest.mark.parametrize("la,lb,lc,sz", CONTRACT_CASES, ids=[f"{a},{b}->{c}" for a, b, c, _ in CONTRACT_CASES])
+def test_contract(gpu, la, lb, lc, sz):
+    cc, L = _cc()
+    rng = np.random.default_rng(len(la) * 7 + len(lb))
+    A = crand(rng, *[sz[ch] for ch in la])
+    B = crand(rng, *[sz[ch] for ch in lb])
+    C = crand(rng, *[sz[ch] for ch in lc])
+    ctx = cc.cclr_create(2, 2)
+    try:
+        LL = ctypes.c_longlong
+        dims = lambda x: (LL * x.ndim)(*x.shape)  # noqa: E731
+        Ad, Bd, Cd = dev(A), dev(B), dev(C)
+        alpha = -0.5 + 0.25j
+        rc = L.cclr_dbg_contract(ctx, alpha.real, alpha.imag, Ad.data_ptr(), la.encode(), dims(A), Bd.data_ptr(),
+                                 lb.encode(), dims(B), Cd.data_ptr(), lc.encode(), dims(C))
+        assert rc == 0, cc.cclr_last_error(ctx)
+        ref = C + alpha * np.einsum(f"{la},{lb}->{lc}", A, B)
+        assert np.abs(Cd.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        cc.cclr_destroy(ctx)
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (3, 5)])
+def test_intermediates(gpu, o, v):
+    from gen import synth as s
+    cc, L = _cc()
+    pb, Vf, f, H, t1, t2 = small_problem(o, v)
+    hb = O.hbar(H, t1, t2)
+    ctx = cc.cclr_create(o, v)
+    try:
+        keep = [dev(H.f)] + [dev(H.blocks[k]) for k in s.CANONICAL_BLOCKS]
+        cc.cclr_set_hamiltonian(ctx, *keep)
+        tt = [dev(t1), dev(t2)]
+        cc.cclr_set_amplitudes(ctx, *tt)
+        bad = []
+        for name, ref in hb.items():
+            n = ctypes.c_longlong()
+            assert L.cclr_dbg_get(ctx, name.encode(), None, ctypes.byref(n)) == 0
+            out = torch.empty(n.value, dtype=torch.complex128, device="cuda")
+            assert L.cclr_dbg_get(ctx, name.encode(), out.data_ptr(), None) == 0
+            got = out.cpu().numpy().reshape(ref.shape)
+            err = np.abs(got - ref).max() / max(1e-300, np.abs(ref).max())
+            print(f"intermediate {name}: rel err {err:.2e}", flush=True)
+            if not err < 1e-12:
+                bad.append((name, err))
+        assert not bad, bad
+    finally:
+        cc.cclr_destroy(ctx)
