@@ -1,0 +1,236 @@
+"""Benchmark of the CCSD linear-response hot path on one MI355X.
+
+Workload (default): o = 20 occupied, v = 200 virtual spin orbitals, complex
+FP64, synthetic MP2-seeded inputs from the seeded generators; three Hermitian
+dipole perturbations at z = 0.0774 + 0.005i.  One step is one pass of the
+whole hot path: the Hbar intermediate build, the Lambda solve, the damped
+response solves for every perturbation at z, -z, z*, -z* (batched Davidson,
+one right Jacobian transform per right-hand side per iteration), the
+Hessian products and the response-function assembly.
+
+The JSON line reports whole-job Jacobian transforms per second, the
+roofline position of the dominant kernel (the packed particle-particle
+ladder GEMM on FP64 MFMA, timed with HIP events on the library's stream),
+and the CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
+PEAK_HBM_GBS = 8000.0
+
+
+def sigma_flops(o: int, v: int) -> dict:
+    """Algorithmic flops of one right Jacobian transform on packed pairs
+    (8 real flops per complex multiply-add), by term group."""
+    O2, V2 = o * (o - 1) // 2, v * (v - 1) // 2
+    ov = o * v
+    f = {
+        "ladder": 8.0 * O2 * V2 * V2,                 # 1/2 W^ab_ef r^ef_ij
+        "ring": 8.0 * ov * ov * ov,                   # P(ab)P(ij) W^mb_ej r^ae_im
+        "hole": 8.0 * V2 * O2 * O2,                   # 1/2 W^mn_ij r^ab_mn
+        "o2v3": 8.0 * (v * o * (o * V2) + V2 * o * v * o + 3 * (O2 * v * v * v) + v * v * o * v),
+        "o3v2": 8.0 * (3 * o * o * o * v * v + 2 * O2 * o * v * v),
+    }
+    f["total"] = sum(f.values())
+    return f
+
+
+def make_inputs(o, v, seed, device):
+    import torch
+    from gen import synth as s
+    pb = s.Problem(o, v, seed)
+    with torch.no_grad():
+        f = s.fock(pb, device)
+        V = s.integral_blocks(pb, device, chunk=8)
+        t1 = s.t1_amplitudes(pb, device)
+        t2 = s.t2_amplitudes(pb, V["oovv"], device)
+        X = [s.dipole(pb, k, device) for k in range(3)]
+    return pb, f, V, t1, t2, X
+
+
+def cpu_baseline(seconds_target=15.0):
+    """Oracle right Jacobian transform timed on the host (bounded sample)."""
+    import numpy as np
+    from gen import synth as s
+    from oracle import cclr_ref as O
+    o, v = 10, 80
+    pb = s.Problem(o, v, 1)
+    inst = s.instance(pb)
+    H = O.Hamiltonian(o, v, inst["f"].numpy(), {k: x.numpy() for k, x in inst["V"].items()})
+    cc = O.CCLR(H, inst["t1"].numpy(), inst["t2"].numpy())
+    r = [x.numpy() for x in s.excitation_vector(pb, 0)]
+    cc.right(*r, 0.1)  # warm-up
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds_target or n < 2:
+        cc.right(*r, 0.1)
+        n += 1
+    dt = (time.perf_counter() - t0) / n
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(x.get("num_threads", 1)) for x in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    f_small = sigma_flops(o, v)["total"]
+    f_big = sigma_flops(20, 200)["total"]
+    return {
+        "value": (1.0 / dt) * (f_small / f_big),
+        "unit": "Jacobian transforms/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"oracle right Jacobian transform (numpy einsum, FP64 complex) at o=10, v=80: {n} calls, "
+                   f"{dt:.3f} s each; rate scaled to o=20, v=200 by the algorithmic-flop ratio "
+                   f"{f_small:.3e}/{f_big:.3e}"),
+    }
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--o", type=int, default=20)
+    ap.add_argument("--v", type=int, default=200)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--omega", type=float, default=0.0774)
+    ap.add_argument("--gamma", type=float, default=0.005)
+    ap.add_argument("--mode", choices=["response", "sigma"], default="response")
+    ap.add_argument("--nvec", type=int, default=12, help="vectors per transform call in --mode sigma")
+    ap.add_argument("--max-subspace", type=int, default=24)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent response solves would shard across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2307_14296_amd as cc
+    from gen import synth as s
+
+    L = cc.lib()
+    L.cclr_dbg_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.cclr_dbg_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    o, v = args.o, args.v
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    pb, f, V, t1, t2, X = make_inputs(o, v, args.seed, dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    log(f"inputs generated on the GPU in {t_gen:.1f} s")
+    opt = cc.cclr_default_options()
+    opt.max_subspace = args.max_subspace
+    opt.tol = args.tol
+    ctx = cc.cclr_create(o, v, opt)
+    cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+    del V
+    torch.cuda.empty_cache()
+    log("Hamiltonian copied into the context")
+    z = complex(args.omega, args.gamma)
+    extra = {}
+
+    if args.mode == "sigma":
+        tb = time.perf_counter()
+        cc.cclr_set_amplitudes(ctx, t1, t2)
+        log(f"intermediates built in {time.perf_counter() - tb:.2f} s")
+        n = args.nvec
+        r1 = torch.zeros((n, o, v), dtype=torch.complex128, device=dev)
+        r2 = torch.zeros((n, o, o, v, v), dtype=torch.complex128, device=dev)
+        for k in range(n):
+            a, b = s.excitation_vector(pb, k, dev)
+            r1[k], r2[k] = a, b
+        s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
+        om, ga = [z.real] * n, [z.imag] * n
+
+        def step():
+            cc.cclr_jacobian_right(ctx, om, ga, r1, r2, s1, s2)
+            return n
+    else:
+        def step():
+            cc.cclr_set_amplitudes(ctx, t1, t2)
+            rc, out, info = cc.cclr_response_function(ctx, X, [z.real], [z.imag])
+            extra["alpha_xx_yy_zz"] = [complex(-out[0][p][p]) for p in range(3)]
+            extra["solver"] = info.as_dict()
+            extra["rc"] = rc
+            return info.nsigma
+
+    for k in range(args.warmup):
+        tw = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warm-up step {k} done in {time.perf_counter() - tw:.2f} s")
+    L.cclr_dbg_profile(ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ntr = 0
+    for k in range(args.steps):
+        ntr += step()
+        torch.cuda.synchronize()
+        log(f"timed step {k} done ({time.perf_counter() - t0:.2f} s so far)")
+    dt = time.perf_counter() - t0
+    nl, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+    L.cclr_dbg_profile_read(ctx, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
+    L.cclr_dbg_profile(ctx, 0)
+    cc.cclr_destroy(ctx)
+
+    achieved = fl.value / (ms.value * 1e-3) / 1e12 if ms.value > 0 else 0.0
+    sf = sigma_flops(o, v)
+    roofline = {
+        "bound": "mfma",
+        "kernel": "k_zgemm (packed particle-particle ladder)",
+        "achieved": round(achieved, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+        "traffic": None,
+        "launches": nl.value,
+        "avg_launch_ms": round(ms.value / max(1, nl.value), 4),
+        "flop_per_launch": fl.value / max(1, nl.value),
+    }
+    line = {
+        "metric": "Jacobian transforms/s (whole response-function job, o=20 v=200)",
+        "value": ntr / dt,
+        "unit": "Jacobian transforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128 (f64)",
+        "data": "synthetic (seeded generators: MP2-seeded amplitudes, random antisymmetrized integrals)",
+        "config": {"workload": f"CCSD-LR {args.mode} o={o} v={v} complex128, 3 dipoles, z={z}",
+                   "o": o, "v": v, "mode": args.mode, "transforms": ntr,
+                   "tflops_algorithmic_sigma": round(ntr * sf["total"] / dt / 1e12, 3),
+                   "input_generation_s": round(t_gen, 2)},
+        "roofline": roofline,
+    }
+    line["config"].update({k: (str(v_) if isinstance(v_, complex) else v_) for k, v_ in extra.items()
+                           if k != "alpha_xx_yy_zz"})
+    if "alpha_xx_yy_zz" in extra:
+        line["config"]["alpha_diag"] = [[a.real, a.imag] for a in extra["alpha_xx_yy_zz"]]
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

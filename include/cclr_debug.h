@@ -30,6 +30,15 @@ int cclr_dbg_contract(cclr_ctx* ctx, double alpha_re, double alpha_im, const ccl
  * (dst may be NULL to query the count only). */
 int cclr_dbg_get(cclr_ctx* ctx, const char* name, cclr_c64* dst, long long* count);
 
+/* Enable (1) or disable (0) event timing of the particle-particle ladder
+ * GEMM launches; enabling clears earlier records. */
+int cclr_dbg_profile(cclr_ctx* ctx, int enable);
+
+/* Launch count, summed duration (ms, from HIP events on the context's
+ * stream) and summed algorithmic flops (8 per complex multiply-add) of the
+ * ladder GEMM launches recorded since profiling was enabled. */
+int cclr_dbg_profile_read(cclr_ctx* ctx, long long* launches, double* ms, double* flops);
+
 #ifdef __cplusplus
 }
 #endif

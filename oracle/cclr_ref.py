@@ -367,7 +367,7 @@ class CCLR:
             e[k] = 0.0
         return M
 
-    def solve(self, side, rhs, z, method="dense", tol=1e-13, maxiter=2000):
+    def solve(self, side, rhs, z, method="dense", tol=1e-12, maxiter=2000):
         """RIGHT: (A - z) x = -rhs ;  LEFT: x (A - z) = -rhs.  Vectors as (x1, x2)."""
         b = -pack(*rhs)
         o, v = self.o, self.v

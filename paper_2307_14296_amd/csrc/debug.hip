@@ -78,4 +78,37 @@ int cclr_dbg_get(cclr_ctx* c, const char* name, cclr_c64* dst, long long* count)
   }
   return CCLR_OK;
 }
+
+static void clear_prof(cclr_ctx* c) {
+  for (auto& e : c->prof_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  c->prof_events.clear();
+  c->prof_flops.clear();
+}
+
+int cclr_dbg_profile(cclr_ctx* c, int enable) {
+  if (!c) return CCLR_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  clear_prof(c);
+  c->prof = enable != 0;
+  return CCLR_OK;
+}
+
+int cclr_dbg_profile_read(cclr_ctx* c, long long* launches, double* ms, double* flops) {
+  if (!c) return CCLR_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return CCLR_EHIP;
+  double t = 0.0, f = 0.0;
+  for (size_t k = 0; k < c->prof_events.size(); ++k) {
+    float x = 0.f;
+    if (hipEventElapsedTime(&x, c->prof_events[k].first, c->prof_events[k].second) != hipSuccess) return CCLR_EHIP;
+    t += x;
+    f += c->prof_flops[k];
+  }
+  if (launches) *launches = (long long)c->prof_events.size();
+  if (ms) *ms = t;
+  if (flops) *flops = f;
+  return CCLR_OK;
+}
 }

@@ -13,6 +13,7 @@
 
 // ------------------------------------------------------------ allocation
 void DevBuf::alloc(cclr_ctx* c, size_t nbytes) {
+  if (p && nbytes == bytes && ctx == c) return;  // same size: keep the allocation
   release();
   if (nbytes == 0) return;
   if (c->opt.device_mem_cap && c->allocated + nbytes > c->opt.device_mem_cap)
@@ -44,10 +45,14 @@ Arena::~Arena() {
 
 void* Arena::get(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
-  if (!chunks.empty() && used.back() + bytes <= chunks.back()->bytes) {
-    void* p = (char*)chunks.back()->p + used.back();
-    used.back() += bytes;
-    return p;
+  while (cur < chunks.size()) {
+    if (used[cur] + bytes <= chunks[cur]->bytes) {
+      void* p = (char*)chunks[cur]->p + used[cur];
+      used[cur] += bytes;
+      return p;
+    }
+    if (cur + 1 < chunks.size()) ++cur;
+    else break;
   }
   DevBuf* b = new DevBuf();
   try {
@@ -58,19 +63,22 @@ void* Arena::get(size_t bytes) {
   }
   chunks.push_back(b);
   used.push_back(bytes);
+  cur = chunks.size() - 1;
   return b->p;
 }
 
-Arena::Mark Arena::mark() const { return {chunks.size(), used.empty() ? 0 : used.back()}; }
+Arena::Mark Arena::mark() const { return {cur, chunks.empty() ? 0 : used[cur]}; }
 
 void Arena::reset(Mark m) {
-  // chunks allocated after the mark are kept for reuse but emptied
-  for (size_t k = m.nchunks; k < chunks.size(); ++k) used[k] = 0;
-  if (m.nchunks > 0) used[m.nchunks - 1] = m.top;
-  // fold: drop empty trailing chunks so the next get() reuses the last live one
-  while (chunks.size() > m.nchunks && chunks.size() > 0 && used.back() == 0 && chunks.size() > 1) {
-    // keep one spare chunk around to avoid allocation churn
-    if (chunks.size() == m.nchunks + 1) break;
+  for (size_t k = m.chunk + 1; k < chunks.size(); ++k) used[k] = 0;
+  if (!chunks.empty()) used[m.chunk] = m.top;
+  cur = m.chunk;
+}
+
+void Arena::trim() {
+  // free every chunk after the active one that holds nothing
+  (void)hipDeviceSynchronize();
+  while (chunks.size() > cur + 1 && used.back() == 0) {
     delete chunks.back();
     chunks.pop_back();
     used.pop_back();
@@ -332,7 +340,7 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
     if (g.K == 0) {
       if (!accumulate) tzero(c, C);
     } else {
-      launch_zgemm(g, c->stream);
+      run_gemm(c, g);
     }
   } else {
     std::string nl = Lb + Lm + Ln;
@@ -352,10 +360,42 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
     g.sCm = g.N;
     g.sCn = 1;
     g.ar = al.x; g.ai = al.y; g.beta = 0;
-    launch_zgemm(g, c->stream);
+    run_gemm(c, g);
     tcopy(c, C, lc, T, nl.c_str(), cx(1.0), accumulate);
   }
   c->arena.reset(mk);
+}
+
+// GEMM dispatch: products whose output covers too few 64x64 tiles to occupy
+// the 256 compute units split the reduction into chunks that write partial
+// products to a workspace, summed in a fixed order afterwards.
+void run_gemm(cclr_ctx* c, const GemmArgs& g) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  const i64 tiles = (i64)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+  if (g.batch == 1 && tiles < 512 && g.K >= 512) {
+    i64 S = std::min<i64>((1024 + tiles - 1) / tiles, g.K / 256);
+    S = std::max<i64>(S, 2);
+    i64 kc = (g.K + S - 1) / S;
+    kc = (kc + 15) / 16 * 16;
+    S = (g.K + kc - 1) / kc;
+    Arena::Mark mk = c->arena.mark();
+    cplx* W = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(S * g.M * (i64)g.N));
+    GemmArgs h = g;
+    h.kchunk = (int)kc;
+    h.batch = (int)S;
+    h.C = W;
+    h.sCb = (i64)g.M * g.N;
+    h.sCm = g.N;
+    h.sCn = 1;
+    h.ar = 1.0;
+    h.ai = 0.0;
+    h.beta = 0;
+    launch_zgemm(h, c->stream);
+    launch_splitk_reduce((int)S, g.M, g.N, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
+    c->arena.reset(mk);
+    return;
+  }
+  launch_zgemm(g, c->stream);
 }
 
 // -------------------------------------------------------- integral views

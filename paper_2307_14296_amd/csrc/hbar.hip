@@ -124,6 +124,11 @@ void build_intermediates(cclr_ctx* c) {
   contract(c, one, Fov, "na", t2, "mnef", Wvvvo, "efam");
   contract(c, half, Vblk(c, "oovo"), "noam", tau, "noef", Wvvvo, "efam");
 
+  // ring operators in GEMM-ready layouts
+  c->WR.alloc(c, sizeof(cplx) * (size_t)(o * v * o * v));
+  c->WL.alloc(c, sizeof(cplx) * (size_t)(o * v * o * v));
+  tcopy(c, ten(c->WR, {o, v, o, v}), "jbme", Wovvo, "mbej", one, false);
+  tcopy(c, ten(c->WL, {o, v, o, v}), "mejb", Wovvo, "jebm", one, false);
   // packed ladder operator and preconditioner diagonal
   c->Wp.alloc(c, sizeof(cplx) * (size_t)(c->V2() * c->V2()));
   launch_pack_vvvv((int)v, c->Wvvvv.c(), c->Wp.c(), c->stream);
@@ -131,4 +136,5 @@ void build_intermediates(cclr_ctx* c) {
   launch_diag((int)o, (int)v, c->Foo.c(), c->Fvv.c(), c->diag.c(), c->stream);
   HIPCHK(hipStreamSynchronize(c->stream));
   c->arena.reset(mk);
+  c->arena.trim();  // the v^4 temporaries of the build are not needed again
 }

@@ -50,17 +50,21 @@ struct DevBuf {
   cplx* c() const { return (cplx*)p; }
 };
 
-// Bump allocator for temporaries; grows by whole new chunks, reset by marks.
+// Bump allocator for temporaries.  Chunks are kept for reuse after a reset
+// (device allocation is slow and synchronizing); trim() releases the unused
+// ones at a quiet point.
 struct Arena {
   cclr_ctx* ctx = nullptr;
   std::vector<DevBuf*> chunks;
   std::vector<size_t> used;
+  size_t cur = 0;
   size_t chunk_bytes = size_t(256) << 20;
   ~Arena();
   void* get(size_t bytes);
-  struct Mark { size_t nchunks, top; };
+  struct Mark { size_t chunk, top; };
   Mark mark() const;
   void reset(Mark m);
+  void trim();
 };
 
 // ----------------------------------------------------------- tensor views
@@ -95,8 +99,14 @@ struct GemmArgs {
   cplx* C; i64 sCb, sCm, sCn;
   double ar, ai;   // alpha
   int beta;        // 0: C = alpha*AB, 1: C += alpha*AB
+  int kchunk;      // > 0: blockIdx.z is a K split covering [z*kchunk, (z+1)*kchunk) (batch must be 1)
 };
 void launch_zgemm(const GemmArgs& g, hipStream_t s);
+// C[m][n] = (beta ? C : 0) + alpha * sum_s W[s][m][n]
+void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
+                          int beta, hipStream_t s);
+// GEMM with automatic K splitting when the output has too few tiles to fill the GPU
+void run_gemm(cclr_ctx* c, const GemmArgs& g);
 
 struct CopyArgs {
   int nd;
@@ -119,12 +129,15 @@ struct VecSet {
 };
 
 void launch_unpack(int nvec, int o, int v, const cplx* s, const cplx* d, cplx* r1, cplx* r2, hipStream_t st);
+// packed doubles -> ring layout rr[k][i][a][m][e] = r^ae_im
+void launch_unpack_ring(int nvec, int o, int v, const cplx* d, cplx* rr, hipStream_t st);
 void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cplx* s, cplx* d, hipStream_t st);
 // out(packed) += X0 + P(ab)Xa + P(ij)Xi + P(ab)P(ij)Xai  (any X may be null),
-// singles out += S1; then out -= z_k * r_k  (z may be null).
+// singles out += S1; then out -= z_k * r_k  (z may be null).  X0, Xa, Xi are
+// [k][i][j][a][b]; Xai is [k][i][j][a][b], or [k][i][a][j][b] if xai_ring.
 void launch_pack_sigma(int nvec, int o, int v, const cplx* X0, const cplx* Xa, const cplx* Xi, const cplx* Xai,
                        const cplx* S1, cplx* outs, cplx* outd, const cplx* zk, const cplx* rs, const cplx* rd,
-                       hipStream_t st);
+                       hipStream_t st, bool xai_ring = false);
 
 // ------------------------------------------------------------ context
 struct cclr_ctx {
@@ -141,9 +154,14 @@ struct cclr_ctx {
   // intermediates (unpacked, W[p][q][r][s] = W^pq_rs)
   DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo, Wvvvv;
   DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f
+  DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
   DevBuf diag;       // Fock-like diagonal for preconditioning: singles then doubles (packed)
   DevBuf lam_s, lam_d;  // lambda, packed
   Arena arena;
+  // optional timing of the particle-particle ladder GEMM launches
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  std::vector<double> prof_flops;
 
   i64 O2() const { return (i64)o * (o - 1) / 2; }
   i64 V2() const { return (i64)v * (v - 1) / 2; }

@@ -22,8 +22,13 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   const i64 bz = blockIdx.z;
-  const cplx* __restrict__ A = g.A + bz * g.sAb;
-  const cplx* __restrict__ B = g.B + bz * g.sBb;
+  int kbeg = 0, kend = g.K;
+  if (g.kchunk > 0) {
+    kbeg = (int)bz * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+  }
+  const cplx* __restrict__ A = g.A + (g.kchunk > 0 ? 0 : bz * g.sAb);
+  const cplx* __restrict__ B = g.B + (g.kchunk > 0 ? 0 : bz * g.sBb);
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const bool a_kfast = (g.sAk == 1);
   const bool b_nfast = (g.sBn == 1);
@@ -37,7 +42,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
       accI[i][j] = d4{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < g.K; k0 += GBK) {
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int e = tid + r * 256;
@@ -46,7 +51,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
       else { mm = e % GBM; kk = e / GBM; }
       const int gm = m0 + mm, gk = k0 + kk;
       cplx x = make_double2(0.0, 0.0);
-      if (gm < g.M && gk < g.K) x = A[(i64)gm * g.sAm + (i64)gk * g.sAk];
+      if (gm < g.M && gk < kend) x = A[(i64)gm * g.sAm + (i64)gk * g.sAk];
       sAr[kk][mm] = x.x;
       sAi[kk][mm] = g.conjA ? -x.y : x.y;
     }
@@ -58,7 +63,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
       else { kk = e % GBK; nn = e / GBK; }
       const int gn = n0 + nn, gk = k0 + kk;
       cplx x = make_double2(0.0, 0.0);
-      if (gn < g.N && gk < g.K) x = B[(i64)gk * g.sBk + (i64)gn * g.sBn];
+      if (gn < g.N && gk < kend) x = B[(i64)gk * g.sBk + (i64)gn * g.sBn];
       sBr[kk][nn] = x.x;
       sBi[kk][nn] = g.conjB ? -x.y : x.y;
     }
@@ -101,6 +106,168 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
           cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
           if (g.beta) {
             cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
+__global__ __launch_bounds__(256) void k_splitk_reduce(int S, int M, int N, const cplx* __restrict__ W,
+                                                       cplx* __restrict__ C, i64 sCm, i64 sCn, double ar, double ai,
+                                                       int beta) {
+  const i64 total = (i64)M * N, stride = (i64)gridDim.x * blockDim.x;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < S; ++q) {
+      const cplx w = W[(i64)q * total + e];
+      sr += w.x;
+      si += w.y;
+    }
+    const i64 m = e / N, n = e % N;
+    cplx y = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+    cplx* dst = C + m * sCm + n * sCn;
+    if (beta) {
+      const cplx o = *dst;
+      y.x += o.x;
+      y.y += o.y;
+    }
+    *dst = y;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pipelined complex GEMM.  Same contract as k_zgemm; specialised on the
+// operand layouts (which index is unit-stride in A and in B).  The next
+// K-tile is fetched into registers while the MFMAs consume the current one
+// from LDS; LDS is double buffered so each K-tile costs one barrier.
+// Four waves in a 2x2 arrangement, each owning a (BM/2)x(BN/2) sub-tile.
+// --------------------------------------------------------------------------
+template <int BM, int BN, bool AK, bool BNF>
+__global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  __shared__ double sA[2][2][BK][BM + 1];
+  __shared__ double sB[2][2][BK][BN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const i64 bz = blockIdx.z;
+  int kbeg = 0, kend = g.K;
+  if (g.kchunk > 0) {
+    kbeg = (int)bz * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+  }
+  const cplx* __restrict__ A = g.A + (g.kchunk > 0 ? 0 : bz * g.sAb);
+  const cplx* __restrict__ B = g.B + (g.kchunk > 0 ? 0 : bz * g.sBb);
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+
+  cplx ra[LA], rb[LB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[r] = (gm < g.M && gk < kend) ? A[(i64)gm * g.sAm + (i64)gk * g.sAk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      const int gn = n0 + nn, gk = k0 + kk;
+      rb[r] = (gn < g.N && gk < kend) ? B[(i64)gk * g.sBk + (i64)gn * g.sBn] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      sA[buf][0][kk][mm] = ra[r].x;
+      sA[buf][1][kk][mm] = sa * ra[r].y;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      sB[buf][0][kk][nn] = rb[r].x;
+      sB[buf][1][kk][nn] = sb * rb[r].y;
+    }
+  };
+
+  d4 accR[FM][FN], accI[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      accR[i][j] = d4{0, 0, 0, 0};
+      accI[i][j] = d4{0, 0, 0, 0};
+    }
+
+  gload(kbeg);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double ar[FM], ai[FM], br[FN], bi[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        ar[i] = sA[buf][0][kk][wm + i * 16 + (lane & 15)];
+        ai[i] = sA[buf][1][kk][wm + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        br[j] = sB[buf][0][kk][wn + j * 16 + (lane & 15)];
+        bi[j] = sB[buf][1][kk][wn + j * 16 + (lane & 15)];
+      }
+      // independent products first, dependent second halves after them
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+        }
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  cplx* __restrict__ C = g.C + bz * g.sCb;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            const cplx o = *dst;
             y.x += o.x;
             y.y += o.y;
           }
@@ -168,6 +335,30 @@ __global__ __launch_bounds__(256) void k_unpack(int nvec, int o, int v, const cp
   }
 }
 
+// packed doubles -> ring layout rr[k][i][a][m][e] = r^ae_im
+__global__ __launch_bounds__(256) void k_unpack_ring(int nvec, int o, int v, const cplx* __restrict__ d,
+                                                     cplx* __restrict__ rr) {
+  const i64 ov = (i64)o * v, O2 = (i64)o * (o - 1) / 2, V2 = (i64)v * (v - 1) / 2;
+  const i64 total = (i64)nvec * ov * ov;
+  const i64 stride = (i64)gridDim.x * blockDim.x;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    i64 r = e;
+    const int ee = r % v; r /= v;
+    const int m = r % o; r /= o;
+    const int a = r % v; r /= v;
+    const int i = r % o; r /= o;
+    const i64 k = r;
+    cplx x = make_double2(0.0, 0.0);
+    if (i != m && a != ee) {
+      const int ih = i > m ? i : m, il = i > m ? m : i;
+      const int ah = a > ee ? a : ee, al = a > ee ? ee : a;
+      x = d[k * O2 * V2 + pair_index(ih, il) * V2 + pair_index(ah, al)];
+      if ((i > m) != (a > ee)) { x.x = -x.x; x.y = -x.y; }
+    }
+    rr[e] = x;
+  }
+}
+
 // full -> packed (takes the i>j, a>b entries)
 __global__ __launch_bounds__(256) void k_pack_full(int nvec, int o, int v, const cplx* __restrict__ r1,
                                                    const cplx* __restrict__ r2, cplx* __restrict__ s,
@@ -202,7 +393,7 @@ __global__ __launch_bounds__(256) void k_pack_sigma(int nvec, int o, int v, cons
                                                     const cplx* __restrict__ Xai, const cplx* __restrict__ S1,
                                                     cplx* __restrict__ outs, cplx* __restrict__ outd,
                                                     const cplx* __restrict__ zk, const cplx* __restrict__ rs,
-                                                    const cplx* __restrict__ rd) {
+                                                    const cplx* __restrict__ rd, int xai_ring) {
   const i64 ov = (i64)o * v, O2 = (i64)o * (o - 1) / 2, V2 = (i64)v * (v - 1) / 2;
   const i64 nd = O2 * V2;
   const i64 total = (i64)nvec * (ov + nd);
@@ -243,7 +434,10 @@ __global__ __launch_bounds__(256) void k_pack_sigma(int nvec, int o, int v, cons
       y.x += t.x - u.x; y.y += t.y - u.y;
     }
     if (Xai) {
-      const cplx t = Xai[at(i, j, a, b)], u = Xai[at(i, j, b, a)], w = Xai[at(j, i, a, b)], x = Xai[at(j, i, b, a)];
+      auto ar = [&](int ii, int jj, int aa, int bb) -> i64 {
+        return xai_ring ? base + (((i64)ii * v + aa) * o + jj) * v + bb : at(ii, jj, aa, bb);
+      };
+      const cplx t = Xai[ar(i, j, a, b)], u = Xai[ar(i, j, b, a)], w = Xai[ar(j, i, a, b)], x = Xai[ar(j, i, b, a)];
       y.x += t.x - u.x - w.x + x.x; y.y += t.y - u.y - w.y + x.y;
     }
     if (zk) {
@@ -271,6 +465,34 @@ void launch_zgemm(const GemmArgs& g, hipStream_t s) {
     }
     return;
   }
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  // large outputs: 128x64 tiles; otherwise 64x64
+  const bool big = (i64)g.M * g.N * g.batch >= (i64)128 * 64 * 1024;
+  if (big) {
+    dim3 grid((g.M + 127) / 128, (g.N + 63) / 64, g.batch);
+    if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<128, 64, true, true>), grid, dim3(256), 0, s, g);
+    else if (ak) hipLaunchKernelGGL((k_zgemm_p<128, 64, true, false>), grid, dim3(256), 0, s, g);
+    else if (bn) hipLaunchKernelGGL((k_zgemm_p<128, 64, false, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_zgemm_p<128, 64, false, false>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((g.M + 63) / 64, (g.N + 63) / 64, g.batch);
+    if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<64, 64, true, true>), grid, dim3(256), 0, s, g);
+    else if (ak) hipLaunchKernelGGL((k_zgemm_p<64, 64, true, false>), grid, dim3(256), 0, s, g);
+    else if (bn) hipLaunchKernelGGL((k_zgemm_p<64, 64, false, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_zgemm_p<64, 64, false, false>), grid, dim3(256), 0, s, g);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
+                          int beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((i64)M * N)), dim3(256), 0, s, S, M, N, W, C, sCm, sCn, ar, ai,
+                     beta);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_zgemm_simple(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
   hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
   HIPCHK(hipGetLastError());
@@ -303,10 +525,16 @@ void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cp
 
 void launch_pack_sigma(int nvec, int o, int v, const cplx* X0, const cplx* Xa, const cplx* Xi, const cplx* Xai,
                        const cplx* S1, cplx* outs, cplx* outd, const cplx* zk, const cplx* rs, const cplx* rd,
-                       hipStream_t st) {
+                       hipStream_t st, bool xai_ring) {
   const i64 total = (i64)nvec * ((i64)o * v + (i64)o * (o - 1) / 2 * ((i64)v * (v - 1) / 2));
   hipLaunchKernelGGL(k_pack_sigma, dim3(grid_for(total)), dim3(256), 0, st, nvec, o, v, X0, Xa, Xi, Xai, S1, outs,
-                     outd, zk, rs, rd);
+                     outd, zk, rs, rd, xai_ring ? 1 : 0);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_unpack_ring(int nvec, int o, int v, const cplx* d, cplx* rr, hipStream_t st) {
+  const i64 total = (i64)nvec * o * v * o * v;
+  hipLaunchKernelGGL(k_unpack_ring, dim3(grid_for(total)), dim3(256), 0, st, nvec, o, v, d, rr);
   HIPCHK(hipGetLastError());
 }
 

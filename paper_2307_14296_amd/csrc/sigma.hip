@@ -27,10 +27,33 @@ Acc prepare(cclr_ctx* c, const VecSet& in) {
   a.X0 = tmp(c, {k, o, o, v, v});
   a.Xa = tmp(c, {k, o, o, v, v});
   a.Xi = tmp(c, {k, o, o, v, v});
-  a.Xai = tmp(c, {k, o, o, v, v});
+  // P(ab)P(ij) group in the ring layout [k][i][a][j][b], seen through a kijab view
+  a.Xai = reorder(tmp(c, {k, o, v, o, v}), "kiajb", "kijab");
   a.S1 = tmp(c, {k, o, v});
-  for (Ten* t : {&a.X0, &a.Xa, &a.Xi, &a.Xai, &a.S1}) launch_fill(t->p, t->size(), cx(0.0), c->stream);
+  for (Ten* t : {&a.X0, &a.Xa, &a.Xi, &a.S1}) launch_fill(t->p, t->size(), cx(0.0), c->stream);
   return a;
+}
+
+// Ring term  Z[(k,i,a),(j,b)] = sum_(m,e) R[(k,i,a),(m,e)] W[(m,e),(j,b)]  written into the
+// [k][i][a][j][b] accumulator (first writer: overwrites).  Right: W^mb_ej r^ae_im;
+// left: l^im_ae W^je_bm.
+void ring(cclr_ctx* c, const VecSet& in, const Ten& Xai, bool right) {
+  const i64 o = c->o, v = c->v, ov = o * v, nv = in.n;
+  Arena::Mark mk = c->arena.mark();
+  cplx* rr = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nv * ov * ov));
+  launch_unpack_ring((int)nv, (int)o, (int)v, in.d, rr, c->stream);
+  GemmArgs g{};
+  g.M = (int)(nv * ov);
+  g.N = (int)ov;
+  g.K = (int)ov;
+  g.batch = 1;
+  g.A = rr; g.sAm = ov; g.sAk = 1;
+  if (right) { g.B = c->WR.c(); g.sBk = 1; g.sBn = ov; }
+  else { g.B = c->WL.c(); g.sBk = ov; g.sBn = 1; }
+  g.C = Xai.p; g.sCm = ov; g.sCn = 1;
+  g.ar = 1.0; g.ai = 0.0; g.beta = 0;
+  run_gemm(c, g);
+  c->arena.reset(mk);
 }
 
 void ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
@@ -46,7 +69,18 @@ void ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
   else { g.sBk = V2; g.sBn = 1; }
   g.C = out.d; g.sCb = 0; g.sCm = V2; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-  launch_zgemm(g, c->stream);
+  if (c->prof) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, c->stream));
+    launch_zgemm(g, c->stream);
+    HIPCHK(hipEventRecord(e1, c->stream));
+    c->prof_events.push_back({e0, e1});
+    c->prof_flops.push_back(8.0 * (double)g.M * (double)g.N * (double)g.K);
+  } else {
+    launch_zgemm(g, c->stream);
+  }
 }
 }  // namespace
 
@@ -81,7 +115,7 @@ void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z
   contract(c, one, Fvv, "be", a.R2, "kijae", a.Xa, "kijab");
   contract(c, mone, Foo, "mj", a.R2, "kimab", a.Xi, "kijab");
   contract(c, half, Woooo, "mnij", a.R2, "kmnab", a.X0, "kijab");
-  contract(c, one, Wovvo, "mbej", a.R2, "kimae", a.Xai, "kijab");
+  ring(c, in, a.Xai, true);
   {
     Ten Voovv = Vblk(c, "oovv");
     Ten Q = tmp(c, {nv, v, v});  // V^nm_fe r^ea_mn
@@ -94,7 +128,7 @@ void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z
   ladder(c, in, out, true);
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
-                    c->stream);
+                    c->stream, true);
   c->arena.reset(mk);
 }
 
@@ -125,7 +159,7 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   contract(c, one, a.R2, "kijae", Fvv, "eb", a.Xa, "kijab");
   contract(c, mone, a.R2, "kimab", Foo, "jm", a.Xi, "kijab");
   contract(c, half, a.R2, "kmnab", Woooo, "ijmn", a.X0, "kijab");
-  contract(c, one, a.R2, "kimae", Wovvo, "jebm", a.Xai, "kijab");
+  ring(c, in, a.Xai, false);
   contract(c, one, Voovv, "ijae", Gvv, "keb", a.Xa, "kijab");
   contract(c, mone, a.R1, "kma", Wooov, "ijmb", a.Xa, "kijab");
   contract(c, mone, Voovv, "imab", Goo, "kjm", a.Xi, "kijab");
@@ -134,6 +168,6 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   ladder(c, in, out, false);
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
-                    c->stream);
+                    c->stream, true);
   c->arena.reset(mk);
 }

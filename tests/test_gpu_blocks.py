@@ -97,6 +97,9 @@ CONTRACT_CASES = [
     ("ia", "jb", "ijab", dict(i=3, a=5, j=3, b=5)),
     ("efag", "mg", "efam", dict(e=5, f=5, a=5, g=5, m=3)),
     ("kmnaf", "mnef", "kea", dict(k=2, m=3, n=3, a=5, f=5, e=5)),
+    # tiny output, long reduction: exercises the split-K path
+    ("inef", "mnef", "im", dict(i=3, n=40, e=30, f=31, m=5)),
+    ("kimfe", "nmfe", "kni", dict(k=2, i=4, m=9, f=60, e=61, n=7)),
 ]
 
 

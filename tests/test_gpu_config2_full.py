@@ -1,0 +1,134 @@
+"""Parity at the benchmark-adjacent sizes.
+
+* o=10, v=80 (seed 1): right/left transforms against the oracle computed in
+  the test, and the 3x3 response tensor at z = 0 and z = 0.08 + 0.004i against
+  tests/golden/alpha_o10v80.json (written by tests/golden/make_golden.py from
+  the oracle alone, preconditioned GMRES).
+* o=20, v=200 in the benchmark's launch configuration (inputs generated on
+  the GPU by the seeded generators, 12 vectors per call): properties that hold
+  at any size — the bilinear transpose identity <l, A r> = <l A, r> between
+  the right and left transforms, antisymmetry of the outputs, and agreement
+  of a batched call with single-vector calls.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gen import synth as s
+from helpers import config_problem, rel, vec
+from oracle import cclr_ref as O
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(torch.complex128).cuda()
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_14296_amd as cc
+    pb, inst, H, t1, t2 = config_problem(10, 80, 1)
+    ref = O.CCLR(H, t1, t2)
+    op = cc.cclr_default_options()
+    op.tol = 1e-12
+    ctx = cc.cclr_create(10, 80, op)
+    keep = [dev(H.f)] + [dev(H.blocks[k]) for k in s.CANONICAL_BLOCKS] + [dev(t1), dev(t2)]
+    cc.cclr_set_hamiltonian(ctx, *keep[:7])
+    cc.cclr_set_amplitudes(ctx, *keep[7:])
+    yield cc, ctx, pb, ref
+    cc.cclr_destroy(ctx)
+
+
+def test_sigma_o10v80(cfg2):
+    cc, ctx, pb, ref = cfg2
+    o, v = 10, 80
+    xs = [vec(pb, k) for k in range(3)]
+    zs = [0.08 + 0.004j, 0.0, -0.3 + 0.1j]
+    r1, r2 = dev(np.stack([x[0] for x in xs])), dev(np.stack([x[1] for x in xs]))
+    for fn, side in ((cc.cclr_jacobian_right, ref.right), (cc.cclr_jacobian_left, ref.left)):
+        s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
+        fn(ctx, [z.real for z in zs], [z.imag for z in zs], r1, r2, s1, s2)
+        for k, (x, z) in enumerate(zip(xs, zs)):
+            e = rel((s1[k].cpu().numpy(), s2[k].cpu().numpy()), side(*x, z))
+            print(f"o10v80 {fn.__name__} z={z}: rel err {e:.2e}", flush=True)
+            assert e < 1e-10
+
+
+def test_response_o10v80_vs_golden(cfg2):
+    cc, ctx, pb, ref = cfg2
+    path = os.path.join(HERE, "golden", "alpha_o10v80.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    gold = json.load(open(path))
+    Xs = [dev(s.dipole(pb, k).numpy()) for k in range(3)]
+    for zkey, vals in gold["values"].items():
+        z = complex(zkey)
+        g = np.array([[complex(a, b) for a, b in row] for row in vals])
+        rc, out, info = cc.cclr_response_function(ctx, Xs, [z.real], [z.imag])
+        e = np.linalg.norm(out[0] - g) / np.linalg.norm(g)
+        print(f"o10v80 response z={z}: rel err {e:.2e}, iters {info.iters}", flush=True)
+        assert rc == 0 and e < 1e-10
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_14296_amd as cc
+    o, v = 20, 200
+    pb = s.Problem(o, v, 3)
+    d = torch.device("cuda")
+    with torch.no_grad():
+        f = s.fock(pb, d)
+        V = s.integral_blocks(pb, d, chunk=8)
+        t1 = s.t1_amplitudes(pb, d)
+        t2 = s.t2_amplitudes(pb, V["oovv"], d)
+    ctx = cc.cclr_create(o, v)
+    cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+    del V
+    torch.cuda.empty_cache()
+    cc.cclr_set_amplitudes(ctx, t1, t2)
+    yield cc, ctx, pb
+    cc.cclr_destroy(ctx)
+
+
+def _vecs(pb, ks):
+    d = torch.device("cuda")
+    r = [s.excitation_vector(pb, k, d) for k in ks]
+    return torch.stack([a for a, _ in r]).contiguous(), torch.stack([b for _, b in r]).contiguous()
+
+
+def _bdot(x1, x2, y1, y2):
+    """bilinear product over unique excitations"""
+    return (x1 * y1).sum() + 0.25 * (x2 * y2).sum()
+
+
+def test_full_size_transpose_identity_and_batching(full):
+    cc, ctx, pb = full
+    n = 12
+    r1, r2 = _vecs(pb, range(n))
+    l1, l2 = _vecs(pb, range(20, 20 + n))
+    z = [0.0774] * n, [0.005] * n
+    s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
+    u1, u2 = torch.empty_like(l1), torch.empty_like(l2)
+    cc.cclr_jacobian_right(ctx, *z, r1, r2, s1, s2)
+    cc.cclr_jacobian_left(ctx, *z, l1, l2, u1, u2)
+    for k in range(n):
+        a = _bdot(l1[k], l2[k], s1[k], s2[k]).item()
+        b = _bdot(u1[k], u2[k], r1[k], r2[k]).item()
+        print(f"o20v200 transpose identity k={k}: {abs(a - b) / abs(a):.2e}", flush=True)
+        assert abs(a - b) <= 1e-11 * abs(a)
+    assert torch.equal(s2, -s2.transpose(1, 2)) and torch.equal(s2, -s2.transpose(3, 4))
+    # one vector at a time gives the same result (different GEMM tiling, same arithmetic)
+    for k in (0, n - 1):
+        t1_, t2_ = torch.empty_like(r1[:1]), torch.empty_like(r2[:1])
+        cc.cclr_jacobian_right(ctx, [0.0774], [0.005], r1[k:k + 1].contiguous(), r2[k:k + 1].contiguous(), t1_, t2_)
+        e = (torch.linalg.norm(t2_[0] - s2[k]) / torch.linalg.norm(s2[k])).item()
+        assert e < 1e-13, e
