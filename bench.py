@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--max-subspace", type=int, default=24)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false",
+                    help="skip the mixed-precision (FP32 products + FP64 refinement) run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -127,68 +129,88 @@ def main():
     L.cclr_dbg_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.cclr_dbg_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.cclr_dbg_set_sigma_prec.argtypes = [ctypes.c_void_p, ctypes.c_int]
     o, v = args.o, args.v
     dev = torch.device("cuda:0")
-    t_gen = time.perf_counter()
-    pb, f, V, t1, t2, X = make_inputs(o, v, args.seed, dev)
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
-    log(f"inputs generated on the GPU in {t_gen:.1f} s")
-    opt = cc.cclr_default_options()
-    opt.max_subspace = args.max_subspace
-    opt.tol = args.tol
-    ctx = cc.cclr_create(o, v, opt)
-    cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
-    del V
-    torch.cuda.empty_cache()
-    log("Hamiltonian copied into the context")
     z = complex(args.omega, args.gamma)
-    extra = {}
 
-    if args.mode == "sigma":
-        tb = time.perf_counter()
-        cc.cclr_set_amplitudes(ctx, t1, t2)
-        log(f"intermediates built in {time.perf_counter() - tb:.2f} s")
-        n = args.nvec
-        r1 = torch.zeros((n, o, v), dtype=torch.complex128, device=dev)
-        r2 = torch.zeros((n, o, o, v, v), dtype=torch.complex128, device=dev)
-        for k in range(n):
-            a, b = s.excitation_vector(pb, k, dev)
-            r1[k], r2[k] = a, b
-        s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
-        om, ga = [z.real] * n, [z.imag] * n
-
-        def step():
-            cc.cclr_jacobian_right(ctx, om, ga, r1, r2, s1, s2)
-            return n
-    else:
-        def step():
+    def run(prec):
+        """Time args.steps steps with the given arithmetic; returns a dict."""
+        t_gen = time.perf_counter()
+        pb, f, V, t1, t2, X = make_inputs(o, v, args.seed, dev)
+        torch.cuda.synchronize()
+        t_gen = time.perf_counter() - t_gen
+        log(f"[{prec}] inputs generated on the GPU in {t_gen:.1f} s")
+        opt = cc.cclr_default_options()
+        opt.max_subspace = args.max_subspace
+        opt.tol = args.tol
+        opt.prec = {"fp64": cc.CCLR_FP64, "fp32": cc.CCLR_FP32}[prec]
+        ctx = cc.cclr_create(o, v, opt)
+        cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+        del V
+        torch.cuda.empty_cache()
+        log(f"[{prec}] Hamiltonian copied into the context")
+        res = {"input_generation_s": round(t_gen, 2)}
+        if args.mode == "sigma":
+            tb = time.perf_counter()
             cc.cclr_set_amplitudes(ctx, t1, t2)
-            rc, out, info = cc.cclr_response_function(ctx, X, [z.real], [z.imag])
-            extra["alpha_xx_yy_zz"] = [complex(-out[0][p][p]) for p in range(3)]
-            extra["solver"] = info.as_dict()
-            extra["rc"] = rc
-            return info.nsigma
+            log(f"[{prec}] intermediates built in {time.perf_counter() - tb:.2f} s")
+            n = args.nvec
+            r1 = torch.zeros((n, o, v), dtype=torch.complex128, device=dev)
+            r2 = torch.zeros((n, o, o, v, v), dtype=torch.complex128, device=dev)
+            for k in range(n):
+                a, b = s.excitation_vector(pb, k, dev)
+                r1[k], r2[k] = a, b
+            s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
+            om, ga = [z.real] * n, [z.imag] * n
+            if prec != "fp64":
+                L.cclr_dbg_set_sigma_prec(ctx, opt.prec)
 
-    for k in range(args.warmup):
-        tw = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        log(f"warm-up step {k} done in {time.perf_counter() - tw:.2f} s")
-    L.cclr_dbg_profile(ctx, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ntr = 0
-    for k in range(args.steps):
-        ntr += step()
-        torch.cuda.synchronize()
-        log(f"timed step {k} done ({time.perf_counter() - t0:.2f} s so far)")
-    dt = time.perf_counter() - t0
-    nl, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
-    L.cclr_dbg_profile_read(ctx, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
-    L.cclr_dbg_profile(ctx, 0)
-    cc.cclr_destroy(ctx)
+            def step():
+                cc.cclr_jacobian_right(ctx, om, ga, r1, r2, s1, s2)
+                return n
+        else:
+            def step():
+                cc.cclr_set_amplitudes(ctx, t1, t2)
+                rc, out, info = cc.cclr_response_function(ctx, X, [z.real], [z.imag])
+                res["alpha"] = -out[0]
+                res["solver"] = info.as_dict()
+                res["rc"] = rc
+                return info.nsigma
 
+        for k in range(args.warmup):
+            tw = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            log(f"[{prec}] warm-up step {k} done in {time.perf_counter() - tw:.2f} s")
+        L.cclr_dbg_profile(ctx, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ntr = 0
+        for k in range(args.steps):
+            ntr += step()
+            torch.cuda.synchronize()
+            log(f"[{prec}] timed step {k} done ({time.perf_counter() - t0:.2f} s so far)")
+        dt = time.perf_counter() - t0
+        nl, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        L.cclr_dbg_profile_read(ctx, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
+        L.cclr_dbg_profile(ctx, 0)
+        cc.cclr_destroy(ctx)
+        del f, t1, t2, X
+        torch.cuda.empty_cache()
+        res.update({"transforms": ntr, "dt": dt, "nl": nl.value, "ms": ms.value, "fl": fl.value})
+        return res
+
+    main_res = run("fp64")
+    mixed = None
+    if args.mixed:
+        mixed = run("fp32")
+    ntr, dt = main_res["transforms"], main_res["dt"]
+    nl = ctypes.c_longlong(main_res["nl"])
+    ms = ctypes.c_double(main_res["ms"])
+    fl = ctypes.c_double(main_res["fl"])
+    t_gen = main_res["input_generation_s"]
+    extra = {k: main_res[k] for k in ("solver", "rc") if k in main_res}
     achieved = fl.value / (ms.value * 1e-3) / 1e12 if ms.value > 0 else 0.0
     sf = sigma_flops(o, v)
     roofline = {
@@ -222,10 +244,22 @@ def main():
                    "input_generation_s": round(t_gen, 2)},
         "roofline": roofline,
     }
-    line["config"].update({k: (str(v_) if isinstance(v_, complex) else v_) for k, v_ in extra.items()
-                           if k != "alpha_xx_yy_zz"})
-    if "alpha_xx_yy_zz" in extra:
-        line["config"]["alpha_diag"] = [[a.real, a.imag] for a in extra["alpha_xx_yy_zz"]]
+    line["config"].update(extra)
+    if "alpha" in main_res:
+        a = main_res["alpha"]
+        line["config"]["alpha_fp64"] = [[[x.real, x.imag] for x in row] for row in a]
+    if mixed is not None:
+        mx = {"prec": "fp32 ladder/ring products, FP64 refinement", "value": mixed["transforms"] / mixed["dt"],
+              "ms_per_step": 1e3 * mixed["dt"] / args.steps, "transforms": mixed["transforms"],
+              "job_speedup_vs_fp64": main_res["dt"] / mixed["dt"]}
+        if "alpha" in mixed:
+            import numpy as np
+            mx["alpha_rel_err_vs_fp64"] = float(np.linalg.norm(mixed["alpha"] - main_res["alpha"]) /
+                                                np.linalg.norm(main_res["alpha"]))
+            mx["solver"] = mixed.get("solver")
+        if mixed["ms"] > 0:
+            mx["ladder_tflops"] = round(mixed["fl"] / (mixed["ms"] * 1e-3) / 1e12, 3)
+        line["mixed_precision"] = mx
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline()

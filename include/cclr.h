@@ -150,6 +150,23 @@ int cclr_response_function(cclr_ctx* ctx, int nx, const cclr_c64* const* X,
                            int nfreq, const double* omega, const double* gamma,
                            cclr_c64* out, cclr_solve_info* info);
 
+/* Gradient of the response function with respect to the perturbation
+ * matrices (adjoint of cclr_response_function).  For the real scalar
+ *   L = Re sum_{w,p,q} conj(G[w][p][q]) * out[w][p][q]
+ * (G: HOST array nfreq*nx*nx, e.g. the output gradient handed down by an
+ * autograd engine) it writes dX[r] = dL/dRe X_r + i dL/dIm X_r into the nx
+ * DEVICE n x n matrices dX[r] (overwritten), treating every entry of X_r as
+ * independent.  The response function depends on X through xi^X and eta^X,
+ * which are linear in X (SI, "Linear response"); the adjoint of the damped
+ * solves is the left transform, so the gradient needs one left damped solve
+ * x (A - f) = -u per perturbation and frequency f in {z, -z, z*, -z*}
+ * (eq. "LR response equation_cpp", transposed) followed by one-particle
+ * transition densities of xi^X and eta^X.  Intermediates and solutions are
+ * recomputed, not stored by the forward call.  Gradients with respect to f
+ * and the integrals are not provided. */
+int cclr_response_backward(cclr_ctx* ctx, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
+                           const double* gamma, const cclr_c64* G, cclr_c64* const* dX, cclr_solve_info* info);
+
 /* Message describing the last error on ctx (or a creation error if ctx is
  * NULL); valid until the next call on the same context. */
 const char* cclr_last_error(const cclr_ctx* ctx);

@@ -39,6 +39,11 @@ int cclr_dbg_profile(cclr_ctx* ctx, int enable);
  * ladder GEMM launches recorded since profiling was enabled. */
 int cclr_dbg_profile_read(cclr_ctx* ctx, long long* launches, double* ms, double* flops);
 
+/* Arithmetic of the ladder and ring products used by subsequent
+ * cclr_jacobian_right/left calls on ctx (CCLR_FP64, CCLR_FP32, CCLR_BF16X3);
+ * the solvers set it themselves. */
+int cclr_dbg_set_sigma_prec(cclr_ctx* ctx, int prec);
+
 #ifdef __cplusplus
 }
 #endif

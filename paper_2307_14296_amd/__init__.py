@@ -26,7 +26,7 @@ CCLR_RIGHT, CCLR_LEFT = 0, 1
 EXPORTED = (
     "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_amplitudes",
     "cclr_jacobian_right", "cclr_jacobian_left", "cclr_solve_damped", "cclr_solve_lambda", "cclr_get_lambda",
-    "cclr_response_function", "cclr_last_error",
+    "cclr_response_function", "cclr_response_backward", "cclr_last_error",
 )
 
 
@@ -72,6 +72,8 @@ def lib():
     L.cclr_solve_lambda.argtypes = [P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_get_lambda.argtypes = [P, P, P]
     L.cclr_response_function.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(cclr_solve_info)]
+    L.cclr_response_backward.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(P),
+                                         ctypes.POINTER(cclr_solve_info)]
     L.cclr_last_error.argtypes = [P]
     L.cclr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -187,3 +189,60 @@ def cclr_response_function(ctx, X, omega, gamma):
                                       ctypes.c_void_p(out.ctypes.data), ctypes.byref(info))
     _check(ctx, rc, allow_notconv=True)
     return rc, out[:nf], info
+
+
+def cclr_response_backward(ctx, X, omega, gamma, G, dX):
+    """G: host array (nfreq, nx, nx) complex; dX: list of GPU complex128 (n, n) tensors (written)."""
+    import numpy as np
+    nx = len(X)
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.complex128))
+    ptrs = (ctypes.c_void_p * nx)(*[_ptr(x, "X").value for x in X])
+    dptrs = (ctypes.c_void_p * nx)(*[_ptr(d, "dX").value for d in dX])
+    info = cclr_solve_info()
+    rc = lib().cclr_response_backward(ctx, nx, ptrs, len(omega), _dbl(omega), _dbl(gamma),
+                                      ctypes.c_void_p(G.ctypes.data), dptrs, ctypes.byref(info))
+    _check(ctx, rc, allow_notconv=True)
+    return rc, info
+
+
+def response_function(ctx, X, omega, gamma):
+    """Differentiable <<X_p;X_q>>(omega + i gamma): returns a (nfreq, nx, nx)
+    complex128 tensor on the GPU; gradients flow to the perturbation
+    matrices X through cclr_response_backward."""
+    return _ResponseFunction.apply(ctx, list(omega), list(gamma), *X)
+
+
+def _autograd():
+    import torch
+
+    class ResponseFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, handle, omega, gamma, *X):
+            Xc = [x.detach().contiguous() for x in X]
+            rc, out, info = cclr_response_function(handle, Xc, omega, gamma)
+            fctx.handle, fctx.omega, fctx.gamma = handle, omega, gamma
+            fctx.save_for_backward(*Xc)
+            return torch.as_tensor(out, device=X[0].device)
+
+        @staticmethod
+        def backward(fctx, gout):
+            Xc = fctx.saved_tensors
+            dX = [torch.empty_like(x) for x in Xc]
+            cclr_response_backward(fctx.handle, list(Xc), fctx.omega, fctx.gamma,
+                                   gout.detach().cpu().numpy(), dX)
+            return (None, None, None, *dX)
+
+    return ResponseFunction
+
+
+class _Lazy:
+    _fn = None
+
+    @classmethod
+    def apply(cls, *a):
+        if cls._fn is None:
+            cls._fn = _autograd()
+        return cls._fn.apply(*a)
+
+
+_ResponseFunction = _Lazy

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <algorithm>
 #include <map>
 
 #include "internal.h"
@@ -10,11 +11,15 @@
 void launch_check_finite(const cplx* p, i64 n, int* flag, hipStream_t s);
 void launch_bdot(int npair, const cplx* const* xs, const cplx* const* xd, const cplx* const* ys,
                  const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s);
-int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
-             cclr_solve_info* info);
+int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
+                 cclr_solve_info* info);
 void build_xi(cclr_ctx* c, const cplx* X, const VecSet& out);
 void build_eta(cclr_ctx* c, const cplx* X, const VecSet& out);
 void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out);
+void density_xi(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
+void density_eta(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
+void launch_caxpy(i64 n, cplx a, const cplx* x, cplx* y, hipStream_t s);
+void launch_conj_inplace(i64 n, cplx* x, hipStream_t s);
 
 static thread_local std::string g_create_error;
 
@@ -122,7 +127,7 @@ int solve_lambda_impl(cclr_ctx* c, cclr_solve_info* info) {
   c->lam_d.alloc(c, sizeof(cplx) * (size_t)c->nd());
   VecSet x{c->lam_s.c(), c->lam_d.c(), 1};
   const cplx z0 = cx(0.0);
-  const int rc = davidson(c, CCLR_LEFT, 1, &z0, rhs, x, info);
+  const int rc = solve_system(c, CCLR_LEFT, 1, &z0, rhs, x, info);
   c->arena.reset(mk);
   c->have_lam = true;
   return rc;
@@ -153,9 +158,9 @@ int cclr_create(int o, int v, const cclr_options* opt, cclr_ctx** out) {
     c->v = v;
     if (opt) c->opt = *opt;
     else cclr_default_options(&c->opt);
-    if (c->opt.prec != CCLR_FP64) {
+    if (c->opt.prec != CCLR_FP64 && c->opt.prec != CCLR_FP32 && c->opt.prec != CCLR_BF16X3) {
       delete c;
-      throw CclrError(CCLR_EINVAL, "only CCLR_FP64 arithmetic is available");
+      throw CclrError(CCLR_EINVAL, "prec must be CCLR_FP64, CCLR_FP32 or CCLR_BF16X3");
     }
     if (!(c->opt.tol > 0.0) || c->opt.maxiter < 1 || c->opt.max_subspace < 4 || c->opt.max_subspace > 120) {
       delete c;
@@ -263,7 +268,7 @@ int cclr_solve_damped(cclr_ctx* c, int side, int nrhs, const double* omega, cons
     pack_in(c, nrhs, b1, b2, rhs, "b");
     std::vector<cplx> z(nrhs);
     for (int k = 0; k < nrhs; ++k) z[k] = cx(omega[k], gamma[k]);
-    const int rc = davidson(c, side, nrhs, z.data(), rhs, x, info);
+    const int rc = solve_system(c, side, nrhs, z.data(), rhs, x, info);
     unpack_out(c, x, x1, x2, "x");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->arena.reset(mk);
@@ -347,11 +352,24 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
         HIPCHK(hipMemcpyAsync(rhs.d + r * nd, xi.d + p * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, c->stream));
       }
     cclr_solve_info sinfo{};
-    const int rs = davidson(c, CCLR_RIGHT, nr, zr.data(), rhs, sol, &sinfo);
+    const int rs = solve_system(c, CCLR_RIGHT, nr, zr.data(), rhs, sol, &sinfo);
     nsig += sinfo.nsigma;
-    // Hessian products for every solution (all frequencies appear as an X-side frequency)
-    VecSet tf = packed_buf(c, nr);
-    hessian_product(c, sol, tf);
+    // Hessian products of the X-side solutions only: t^p(-z) and t^p(z*)
+    std::vector<int> xside_f;
+    for (int w = 0; w < nfreq; ++w)
+      for (int f : {idmz[w], idcz[w]})
+        if (std::find(xside_f.begin(), xside_f.end(), f) == xside_f.end()) xside_f.push_back(f);
+    const int ntf = (int)xside_f.size() * nx;
+    VecSet tfin = packed_buf(c, ntf), tfo = packed_buf(c, ntf);
+    std::map<int, int> tf_slot;  // solution index r -> Hessian-product slot
+    for (size_t q = 0; q < xside_f.size(); ++q)
+      for (int p = 0; p < nx; ++p) {
+        const int r = xside_f[q] * nx + p, k = (int)q * nx + p;
+        tf_slot[r] = k;
+        HIPCHK(hipMemcpyAsync(tfin.s + k * ov, sol.s + r * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(tfin.d + k * nd, sol.d + r * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, c->stream));
+      }
+    hessian_product(c, tfin, tfo);
     // bilinear products
     auto vs = [&](const VecSet& s, int k) { return std::make_pair(s.s + k * ov, s.d + k * nd); };
     std::vector<const cplx*> hx_s, hx_d, hy_s, hy_d;
@@ -362,8 +380,8 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
     std::map<std::pair<int, int>, int> eta_t, tf_t;  // (p, r) -> pair index
     for (int p = 0; p < nx; ++p)
       for (int r = 0; r < nr; ++r) eta_t[{p, r}] = add(vs(eta, p), vs(sol, r));
-    for (int r1 = 0; r1 < nr; ++r1)
-      for (int r2 = 0; r2 < nr; ++r2) tf_t[{r1, r2}] = add(vs(tf, r1), vs(sol, r2));
+    for (const auto& kv : tf_slot)
+      for (int r2 = 0; r2 < nr; ++r2) tf_t[{kv.first, r2}] = add(vs(tfo, kv.second), vs(sol, r2));
     const int np = (int)hx_s.size();
     const cplx** pd = (const cplx**)c->arena.get(sizeof(cplx*) * 4 * np);
     std::vector<const cplx*> all;
@@ -399,6 +417,122 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
       info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV) return CCLR_ENOTCONV;
+    return CCLR_OK;
+  });
+}
+
+int cclr_response_backward(cclr_ctx* c, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
+                           const double* gamma, const cclr_c64* Gh, cclr_c64* const* dX, cclr_solve_info* info) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    auto t0 = std::chrono::steady_clock::now();
+    require_t(c);
+    REQUIRE(nx >= 1 && X && dX && Gh, CCLR_EINVAL, "need perturbations, G and gradient outputs");
+    check_freqs(nfreq, omega, gamma);
+    const i64 n = c->o + c->v, ov = c->ns(), nd = c->nd();
+    for (int p = 0; p < nx; ++p) {
+      check_ptr(X[p], "X");
+      check_ptr(dX[p], "dX");
+    }
+    for (int k = 0; k < nfreq * nx * nx; ++k)
+      REQUIRE(std::isfinite(Gh[k].re) && std::isfinite(Gh[k].im), CCLR_EINVAL, "non-finite G");
+    cclr_solve_info linfo{}, sinfo{}, ainfo{};
+    long nsig = 0;
+    int rc = CCLR_OK;
+    if (!c->have_lam) {
+      rc = solve_lambda_impl(c, &linfo);
+      nsig += linfo.nsigma;
+      if (rc < 0) return rc;
+    }
+    Arena::Mark mk = c->arena.mark();
+    VecSet xi = packed_buf(c, nx), eta = packed_buf(c, nx);
+    for (int p = 0; p < nx; ++p) {
+      build_xi(c, (const cplx*)X[p], VecSet{xi.s + p * ov, xi.d + p * nd, 1});
+      build_eta(c, (const cplx*)X[p], VecSet{eta.s + p * ov, eta.d + p * nd, 1});
+    }
+    std::vector<std::complex<double>> fr;
+    auto fid = [&](std::complex<double> w) {
+      for (size_t k = 0; k < fr.size(); ++k)
+        if (fr[k] == w) return (int)k;
+      fr.push_back(w);
+      return (int)fr.size() - 1;
+    };
+    for (int w = 0; w < nfreq; ++w) {
+      const std::complex<double> z(omega[w], gamma[w]);
+      fid(z), fid(-z), fid(std::conj(z)), fid(-std::conj(z));
+    }
+    const int nf = (int)fr.size(), nr = nf * nx;
+    VecSet rhs = packed_buf(c, nr), sol = packed_buf(c, nr), tf = packed_buf(c, nr);
+    std::vector<cplx> zr(nr);
+    for (int f = 0; f < nf; ++f)
+      for (int p = 0; p < nx; ++p) {
+        const int r = f * nx + p;
+        zr[r] = cx(fr[f].real(), fr[f].imag());
+        HIPCHK(hipMemcpyAsync(rhs.s + r * ov, xi.s + p * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(rhs.d + r * nd, xi.d + p * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, c->stream));
+      }
+    const int rs = solve_system(c, CCLR_RIGHT, nr, zr.data(), rhs, sol, &sinfo);
+    nsig += sinfo.nsigma;
+    hessian_product(c, sol, tf);
+    // adjoint right-hand sides u[f][r] (left solves) and density vectors y[r] (eta densities)
+    VecSet U = packed_buf(c, nr), Y = packed_buf(c, nx);
+    launch_fill(U.s, nr * ov, cx(0.0), c->stream);
+    launch_fill(U.d, nr * nd, cx(0.0), c->stream);
+    launch_fill(Y.s, nx * ov, cx(0.0), c->stream);
+    launch_fill(Y.d, nx * nd, cx(0.0), c->stream);
+    auto axpy = [&](const VecSet& dst, int kd, const VecSet& src, int ks, std::complex<double> a) {
+      if (a == 0.0) return;
+      launch_caxpy(ov, cx(a.real(), a.imag()), src.s + ks * ov, dst.s + kd * ov, c->stream);
+      launch_caxpy(nd, cx(a.real(), a.imag()), src.d + ks * nd, dst.d + kd * nd, c->stream);
+    };
+    // L = Re sum conj(G) out, out = 1/2 [g(z) + conj g(-z*)]  =>  L = Re h,
+    // h = sum c1 g(z) + c2 g(-z*),  c1 = conj(G)/2,  c2 = G/2  (h holomorphic in X)
+    // g_pq(s) = eta^p t^q(s) + eta^q t^p(-s) + (F t^p(-s)) t^q(s)
+    for (int w = 0; w < nfreq; ++w) {
+      const std::complex<double> z(omega[w], gamma[w]);
+      for (int part = 0; part < 2; ++part) {
+        const std::complex<double> s_ = part == 0 ? z : -std::conj(z);
+        const int fs = fid(s_), fms = fid(-s_);
+        for (int p = 0; p < nx; ++p)
+          for (int q = 0; q < nx; ++q) {
+            const cclr_c64 g = Gh[((i64)w * nx + p) * nx + q];
+            const std::complex<double> cf = part == 0 ? 0.5 * std::complex<double>(g.re, -g.im)
+                                                      : 0.5 * std::complex<double>(g.re, g.im);
+            // eta^p . t^q(s): density of eta in X_p with vector t^q(s)
+            axpy(Y, p, sol, fs * nx + q, cf);
+            // eta^q . t^p(-s): density of eta in X_q with t^p(-s)
+            axpy(Y, q, sol, fms * nx + p, cf);
+            // t^q(s) = -(A - s)^-1 xi^q with coefficient vector eta^p + F t^p(-s): left solve at s for X_q
+            axpy(U, fs * nx + q, eta, p, cf);
+            axpy(U, fs * nx + q, tf, fms * nx + p, cf);
+            // t^p(-s) with coefficient vector eta^q + F t^q(s): left solve at -s for X_p
+            axpy(U, fms * nx + p, eta, q, cf);
+            axpy(U, fms * nx + p, tf, fs * nx + q, cf);
+          }
+      }
+    }
+    // left solves x (A - f) = -u  =>  u . t^X(f) = x . xi^X
+    VecSet xl = packed_buf(c, nr);
+    const int ra = solve_system(c, CCLR_LEFT, nr, zr.data(), U, xl, &ainfo);
+    nsig += ainfo.nsigma;
+    for (int r = 0; r < nx; ++r) launch_fill((cplx*)dX[r], n * n, cx(0.0), c->stream);
+    for (int f = 0; f < nf; ++f)
+      for (int r = 0; r < nx; ++r)
+        density_xi(c, VecSet{xl.s + (f * nx + r) * ov, xl.d + (f * nx + r) * nd, 1}, (cplx*)dX[r], cx(1.0));
+    for (int r = 0; r < nx; ++r)
+      density_eta(c, VecSet{Y.s + r * ov, Y.d + r * nd, 1}, (cplx*)dX[r], cx(1.0));
+    // dL/dRe X + i dL/dIm X = conj(dh/dX)
+    for (int r = 0; r < nx; ++r) launch_conj_inplace(n * n, (cplx*)dX[r], c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->arena.reset(mk);
+    if (info) {
+      info->iters = std::max(std::max(sinfo.iters, ainfo.iters), linfo.iters);
+      info->converged = sinfo.converged && ainfo.converged && (linfo.iters == 0 || linfo.converged);
+      info->resnorm = std::max(std::max(sinfo.resnorm, ainfo.resnorm), linfo.resnorm);
+      info->nsigma = nsig;
+      info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV || ra == CCLR_ENOTCONV) return CCLR_ENOTCONV;
     return CCLR_OK;
   });
 }

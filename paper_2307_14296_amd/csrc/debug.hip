@@ -111,4 +111,10 @@ int cclr_dbg_profile_read(cclr_ctx* c, long long* launches, double* ms, double* 
   if (flops) *flops = f;
   return CCLR_OK;
 }
+
+int cclr_dbg_set_sigma_prec(cclr_ctx* c, int prec) {
+  if (!c || (prec != CCLR_FP64 && prec != CCLR_FP32 && prec != CCLR_BF16X3)) return CCLR_EINVAL;
+  c->sigma_prec = prec;
+  return CCLR_OK;
+}
 }

@@ -102,6 +102,9 @@ struct GemmArgs {
   int kchunk;      // > 0: blockIdx.z is a K split covering [z*kchunk, (z+1)*kchunk) (batch must be 1)
 };
 void launch_zgemm(const GemmArgs& g, hipStream_t s);
+// the same product with FP32 (prec = CCLR_FP32) or split-BF16 (CCLR_BF16X3)
+// MFMA arithmetic and FP32 accumulation; operands and C stay complex128 in memory
+void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s);
 // C[m][n] = (beta ? C : 0) + alpha * sum_s W[s][m][n]
 void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
                           int beta, hipStream_t s);
@@ -158,6 +161,10 @@ struct cclr_ctx {
   DevBuf diag;       // Fock-like diagonal for preconditioning: singles then doubles (packed)
   DevBuf lam_s, lam_d;  // lambda, packed
   Arena arena;
+  // arithmetic of the ladder and ring products in the transforms being applied
+  // (CCLR_FP64 for the FP64 path and every true residual; opt.prec inside the
+  // low-precision inner solves)
+  int sigma_prec = CCLR_FP64;
   // optional timing of the particle-particle ladder GEMM launches
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

@@ -3,6 +3,8 @@
 #include "internal.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+// output row of v_mfma_f32_16x16x4_f32 for (lane, register)
+#define F32_ROW(lane, r) (4 * (r) + ((lane) >> 4))
 
 // --------------------------------------------------------------------------
 // Complex GEMM  C[b][m][n] (+)= alpha * sum_k A[b][m][k] * B[b][k][n]
@@ -138,11 +140,15 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int S, int M, int N, cons
 }
 
 // --------------------------------------------------------------------------
-// Pipelined complex GEMM.  Same contract as k_zgemm; specialised on the
-// operand layouts (which index is unit-stride in A and in B).  The next
-// K-tile is fetched into registers while the MFMAs consume the current one
-// from LDS; LDS is double buffered so each K-tile costs one barrier.
-// Four waves in a 2x2 arrangement, each owning a (BM/2)x(BN/2) sub-tile.
+// Pipelined complex GEMM with three real products per complex block (Gauss):
+//   k1 = (Ar + Ai) Br,  k2 = Ar (Bi - Br),  k3 = Ai (Br + Bi),
+//   Re C = k1 - k3,     Im C = k1 + k2.
+// Same contract as k_zgemm; specialised on the operand layouts (which index
+// is unit-stride in A and in B).  The LDS holds the three planes of each
+// operand; the next K-tile is fetched into registers while the MFMAs consume
+// the current one, and LDS is double buffered so each K-tile costs one
+// barrier.  Four waves in a 2x2 arrangement, each owning a (BM/2)x(BN/2)
+// sub-tile.
 // --------------------------------------------------------------------------
 template <int BM, int BN, bool AK, bool BNF>
 __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
@@ -150,8 +156,8 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-  __shared__ double sA[2][2][BK][BM + 1];
-  __shared__ double sB[2][2][BK][BN + 1];
+  __shared__ double sA[2][3][BK][BM + 1];  // Ar, Ai, Ar + Ai
+  __shared__ double sB[2][3][BK][BN + 1];  // Br, Bi - Br, Br + Bi
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const i64 bz = blockIdx.z;
@@ -190,26 +196,31 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
       const int e = tid + r * 256;
       const int mm = AK ? e / BK : e % BM;
       const int kk = AK ? e % BK : e / BM;
-      sA[buf][0][kk][mm] = ra[r].x;
-      sA[buf][1][kk][mm] = sa * ra[r].y;
+      const double re = ra[r].x, im = sa * ra[r].y;
+      sA[buf][0][kk][mm] = re;
+      sA[buf][1][kk][mm] = im;
+      sA[buf][2][kk][mm] = re + im;
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int e = tid + r * 256;
       const int nn = BNF ? e % BN : e / BK;
       const int kk = BNF ? e / BN : e % BK;
-      sB[buf][0][kk][nn] = rb[r].x;
-      sB[buf][1][kk][nn] = sb * rb[r].y;
+      const double re = rb[r].x, im = sb * rb[r].y;
+      sB[buf][0][kk][nn] = re;
+      sB[buf][1][kk][nn] = im - re;
+      sB[buf][2][kk][nn] = re + im;
     }
   };
 
-  d4 accR[FM][FN], accI[FM][FN];
+  d4 k1[FM][FN], k2[FM][FN], k3[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      accR[i][j] = d4{0, 0, 0, 0};
-      accI[i][j] = d4{0, 0, 0, 0};
+      k1[i][j] = d4{0, 0, 0, 0};
+      k2[i][j] = d4{0, 0, 0, 0};
+      k3[i][j] = d4{0, 0, 0, 0};
     }
 
   gload(kbeg);
@@ -222,31 +233,28 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + (lane >> 4);
-      double ar[FM], ai[FM], br[FN], bi[FN];
+      double ar[FM], ai[FM], as[FM], br[FN], bd[FN], bs[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        ar[i] = sA[buf][0][kk][wm + i * 16 + (lane & 15)];
-        ai[i] = sA[buf][1][kk][wm + i * 16 + (lane & 15)];
+        const int mm = wm + i * 16 + (lane & 15);
+        ar[i] = sA[buf][0][kk][mm];
+        ai[i] = sA[buf][1][kk][mm];
+        as[i] = sA[buf][2][kk][mm];
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        br[j] = sB[buf][0][kk][wn + j * 16 + (lane & 15)];
-        bi[j] = sB[buf][1][kk][wn + j * 16 + (lane & 15)];
+        const int nn = wn + j * 16 + (lane & 15);
+        br[j] = sB[buf][0][kk][nn];
+        bd[j] = sB[buf][1][kk][nn];
+        bs[j] = sB[buf][2][kk][nn];
       }
-      // independent products first, dependent second halves after them
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
-        }
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+          k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], br[j], k1[i][j], 0, 0, 0);
+          k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bd[j], k2[i][j], 0, 0, 0);
+          k3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bs[j], k3[i][j], 0, 0, 0);
         }
     }
     if (more) sstore(buf ^ 1);
@@ -263,7 +271,147 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
         const int m = m0 + wm + i * 16 + 4 * r + (lane >> 4);
         const int n = n0 + wn + j * 16 + (lane & 15);
         if (m < g.M && n < g.N) {
-          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          const double cr = k1[i][j][r] - k3[i][j][r], ci = k1[i][j][r] + k2[i][j][r];
+          cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            const cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
+// --------------------------------------------------------------------------
+// Low-precision complex GEMM: operands and C are complex128 in memory, the
+// products run on FP32 MFMA (v_mfma_f32_16x16x4_f32) with FP32 accumulation,
+// three real products per complex block as in k_zgemm_p.  Used for the
+// ladder and ring products inside the inner solves of the mixed-precision
+// path; residuals are always re-formed with the FP64 kernels.
+// --------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// row of the 16x16 f32 MFMA output held by lane `lane` in register r
+__device__ __forceinline__ int f32_out_row(int lane, int r) { return F32_ROW(lane, r); }
+
+template <int BM, int BN, bool AK, bool BNF>
+__global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  __shared__ float sA[2][3][BK][BM + 1];
+  __shared__ float sB[2][3][BK][BN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const i64 bz = blockIdx.z;
+  const int kbeg = 0, kend = g.K;
+  const cplx* __restrict__ A = g.A + bz * g.sAb;
+  const cplx* __restrict__ B = g.B + bz * g.sBb;
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const float sa = g.conjA ? -1.f : 1.f, sb = g.conjB ? -1.f : 1.f;
+  cplx ra[LA], rb[LB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[r] = (gm < g.M && gk < kend) ? A[(i64)gm * g.sAm + (i64)gk * g.sAk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      const int gn = n0 + nn, gk = k0 + kk;
+      rb[r] = (gn < g.N && gk < kend) ? B[(i64)gk * g.sBk + (i64)gn * g.sBn] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const float re = (float)ra[r].x, im = sa * (float)ra[r].y;
+      sA[buf][0][kk][mm] = re;
+      sA[buf][1][kk][mm] = im;
+      sA[buf][2][kk][mm] = (float)(ra[r].x + (double)sa * ra[r].y);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      const double re = rb[r].x, im = (double)sb * rb[r].y;
+      sB[buf][0][kk][nn] = (float)re;
+      sB[buf][1][kk][nn] = (float)(im - re);
+      sB[buf][2][kk][nn] = (float)(re + im);
+    }
+  };
+  f4 k1[FM][FN], k2[FM][FN], k3[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      k1[i][j] = f4{0, 0, 0, 0};
+      k2[i][j] = f4{0, 0, 0, 0};
+      k3[i][j] = f4{0, 0, 0, 0};
+    }
+  gload(kbeg);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      float ar[FM], ai[FM], as[FM], br[FN], bd[FN], bs[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int mm = wm + i * 16 + (lane & 15);
+        ar[i] = sA[buf][0][kk][mm];
+        ai[i] = sA[buf][1][kk][mm];
+        as[i] = sA[buf][2][kk][mm];
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int nn = wn + j * 16 + (lane & 15);
+        br[j] = sB[buf][0][kk][nn];
+        bd[j] = sB[buf][1][kk][nn];
+        bs[j] = sB[buf][2][kk][nn];
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          k1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[i], br[j], k1[i][j], 0, 0, 0);
+          k2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bd[j], k2[i][j], 0, 0, 0);
+          k3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], bs[j], k3[i][j], 0, 0, 0);
+        }
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  cplx* __restrict__ C = g.C + bz * g.sCb;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + f32_out_row(lane, r);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double cr = (double)k1[i][j][r] - (double)k3[i][j][r];
+          const double ci = (double)k1[i][j][r] + (double)k2[i][j][r];
           cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
           cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
           if (g.beta) {
@@ -491,6 +639,19 @@ void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, 
   HIPCHK(hipGetLastError());
 }
 
+void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  REQUIRE(g.kchunk == 0, CCLR_EINVAL, "low-precision GEMM: no K splitting");
+  REQUIRE(prec == CCLR_FP32, CCLR_EINVAL, "low-precision GEMM: only CCLR_FP32 is available");
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  dim3 grid((g.M + 127) / 128, (g.N + 63) / 64, g.batch);
+  if (ak && bn) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, true>), grid, dim3(256), 0, s, g);
+  else if (ak) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, false>), grid, dim3(256), 0, s, g);
+  else if (bn) hipLaunchKernelGGL((k_cgemm_f32<128, 64, false, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_cgemm_f32<128, 64, false, false>), grid, dim3(256), 0, s, g);
+  HIPCHK(hipGetLastError());
+}
+
 void launch_zgemm_simple(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
@@ -670,5 +831,30 @@ void launch_bdot(int npair, const cplx* const* xs, const cplx* const* xd, const 
   if (npair <= 0) return;
   hipLaunchKernelGGL(k_bdot, dim3(kDotChunks, npair), dim3(256), 0, s, xs, xd, ys, yd, ov, nd, partial);
   hipLaunchKernelGGL(k_bdot_reduce, dim3(npair), dim3(256), 0, s, partial, out);
+  HIPCHK(hipGetLastError());
+}
+
+namespace {
+__global__ __launch_bounds__(256) void k_caxpy(i64 n, cplx a, const cplx* __restrict__ x, cplx* __restrict__ y) {
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (i64)gridDim.x * blockDim.x) {
+    const cplx u = x[e];
+    y[e].x += a.x * u.x - a.y * u.y;
+    y[e].y += a.x * u.y + a.y * u.x;
+  }
+}
+__global__ __launch_bounds__(256) void k_conj(i64 n, cplx* x) {
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (i64)gridDim.x * blockDim.x) x[e].y = -x[e].y;
+}
+}  // namespace
+
+void launch_caxpy(i64 n, cplx a, const cplx* x, cplx* y, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_caxpy, dim3(grid_for(n)), dim3(256), 0, s, n, a, x, y);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_conj_inplace(i64 n, cplx* x, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_conj, dim3(grid_for(n)), dim3(256), 0, s, n, x);
   HIPCHK(hipGetLastError());
 }

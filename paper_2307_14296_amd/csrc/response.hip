@@ -292,3 +292,87 @@ void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
   finish(c, G, nv, out);
   c->arena.reset(mk);
 }
+
+// --------------------------------------------------------------------------
+// Adjoint pieces of the response function with respect to a perturbation X.
+// xi^X and eta^X are linear in X, so for a vector y the scalars y.xi^X and
+// eta^X.y are linear functionals of X; their gradients
+//   Dxi(y)[p][q]  = d (y . xi^X)  / d X[p][q]
+//   Deta(y)[p][q] = d (eta^X . y) / d X[p][q]
+// are one-particle "transition densities", obtained term by term from the
+// programmable expressions of xi^X and eta^X (SI, "Linear response").  Both
+// accumulate alpha * D into the n x n matrix D (device).
+// --------------------------------------------------------------------------
+namespace {
+Ten dblk(cplx* D, cclr_ctx* c, const char* kinds) { return xblk(D, c, kinds); }
+}  // namespace
+
+void density_xi(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha) {
+  const i64 o = c->o, v = c->v;
+  Arena::Mark mk = c->arena.mark();
+  auto mul = [&](double s) { return cx(alpha.x * s, alpha.y * s); };
+  Ten t1 = ten(c->t1, {o, v}), t2 = ten(c->t2, {o, o, v, v});
+  Ten y1 = ten(y.s, {o, v});
+  Ten y2 = tmp(c, {o, o, v, v});
+  launch_unpack(1, (int)o, (int)v, y.s, y.d, nullptr, y2.p, c->stream);
+  Ten Doo = dblk(D, c, "oo"), Dov = dblk(D, c, "ov"), Dvo = dblk(D, c, "vo"), Dvv = dblk(D, c, "vv");
+  // singles: X^a_i + X^a_e t^e_i - X^m_i t^a_m - (X^m_e t^e_i) t^a_m + X^m_e t^ae_im
+  tcopy(c, Dvo, "ai", y1, "ia", mul(1.0));
+  Ten U = tmp(c, {v, v});  // y_i^a t^e_i -> [a][e]
+  contract(c, cx(1.0), y1, "ia", t1, "ie", U, "ae", false);
+  tcopy(c, Dvv, "ae", U, "ae", mul(1.0));
+  contract(c, mul(-1.0), y1, "ia", t1, "ma", Doo, "mi");
+  contract(c, mul(-1.0), t1, "ma", U, "ae", Dov, "me");
+  contract(c, mul(1.0), y1, "ia", t2, "imae", Dov, "me");
+  // doubles (1/4 sum over unrestricted indices; P() doubles each term on antisymmetric y)
+  contract(c, mul(0.5), y2, "ijab", t2, "ijaf", Dvv, "bf");
+  contract(c, mul(-0.5), y2, "ijab", t2, "imab", Doo, "mj");
+  Ten W = tmp(c, {o, o});  // y^ij_ab t^ab_mj -> [i][m]
+  contract(c, cx(1.0), y2, "ijab", t2, "mjab", W, "im", false);
+  contract(c, mul(-0.5), W, "im", t1, "ie", Dov, "me");
+  Ten Q = tmp(c, {v, v});  // y^ij_ab t^fb_ij -> [a][f]
+  contract(c, cx(1.0), y2, "ijab", t2, "ijfb", Q, "af", false);
+  contract(c, mul(-0.5), t1, "ma", Q, "af", Dov, "mf");
+  c->arena.reset(mk);
+}
+
+void density_eta(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha) {
+  const i64 o = c->o, v = c->v;
+  Arena::Mark mk = c->arena.mark();
+  auto mul = [&](double s) { return cx(alpha.x * s, alpha.y * s); };
+  Ten t1 = ten(c->t1, {o, v}), t2 = ten(c->t2, {o, o, v, v});
+  Ten l1 = ten(c->lam_s, {o, v});
+  Ten l2 = tmp(c, {o, o, v, v});
+  launch_unpack(1, (int)o, (int)v, c->lam_s.c(), c->lam_d.c(), nullptr, l2.p, c->stream);
+  Ten y1 = ten(y.s, {o, v});
+  Ten y2 = tmp(c, {o, o, v, v});
+  launch_unpack(1, (int)o, (int)v, y.s, y.d, nullptr, y2.p, c->stream);
+  Ten Doo = dblk(D, c, "oo"), Dov = dblk(D, c, "ov"), Dvv = dblk(D, c, "vv");
+  // singles of eta^X
+  tcopy(c, Dov, "ia", y1, "ia", mul(1.0));
+  contract(c, mul(1.0), l1, "ie", y1, "ia", Dvv, "ea");
+  contract(c, mul(-1.0), l1, "ma", y1, "ia", Doo, "im");
+  Ten U = tmp(c, {o, o});  // t^e_m lambda^i_e -> [m][i]
+  contract(c, cx(1.0), t1, "me", l1, "ie", U, "mi", false);
+  contract(c, mul(-1.0), U, "mi", y1, "ia", Dov, "ma");
+  Ten P = tmp(c, {v, v});  // t^e_m lambda^m_a -> [e][a]
+  contract(c, cx(1.0), t1, "me", l1, "ma", P, "ea", false);
+  contract(c, mul(-1.0), y1, "ia", P, "ea", Dov, "ie");
+  Ten A = tmp(c, {o, o});  // t^fe_mn lambda^mi_fe -> [n][i]
+  contract(c, cx(1.0), t2, "mnfe", l2, "mife", A, "ni", false);
+  contract(c, mul(-0.5), A, "ni", y1, "ia", Dov, "na");
+  Ten B = tmp(c, {v, v});  // t^fe_nm lambda^nm_fa -> [e][a]
+  contract(c, cx(1.0), t2, "nmfe", l2, "nmfa", B, "ea", false);
+  contract(c, mul(-0.5), B, "ea", y1, "ia", Dov, "ie");
+  // doubles of eta^X
+  contract(c, mul(1.0), y2, "ijab", l1, "ia", Dov, "jb");
+  contract(c, mul(0.5), y2, "ijab", l2, "ijae", Dvv, "eb");
+  Ten Y = tmp(c, {o, o});  // y^ij_ab lambda^im_ab -> [j][m]
+  contract(c, cx(1.0), y2, "ijab", l2, "imab", Y, "jm", false);
+  tcopy(c, Doo, "jm", Y, "jm", mul(-0.5));
+  Ten L3 = tmp(c, {o, o, v, o});  // t^e_m lambda^ij_ae -> [i][j][a][m]
+  contract(c, cx(1.0), t1, "me", l2, "ijae", L3, "ijam", false);
+  contract(c, mul(-0.5), y2, "ijab", L3, "ijam", Dov, "mb");
+  contract(c, mul(-0.5), Y, "jm", t1, "me", Dov, "je");
+  c->arena.reset(mk);
+}

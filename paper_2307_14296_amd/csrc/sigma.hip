@@ -52,7 +52,8 @@ void ring(cclr_ctx* c, const VecSet& in, const Ten& Xai, bool right) {
   else { g.B = c->WL.c(); g.sBk = ov; g.sBn = 1; }
   g.C = Xai.p; g.sCm = ov; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-  run_gemm(c, g);
+  if (c->sigma_prec == CCLR_FP64) run_gemm(c, g);
+  else launch_zgemm_lowp(g, c->sigma_prec, c->stream);
   c->arena.reset(mk);
 }
 
@@ -69,17 +70,21 @@ void ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
   else { g.sBk = V2; g.sBn = 1; }
   g.C = out.d; g.sCb = 0; g.sCm = V2; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
+  auto launch = [&]() {
+    if (c->sigma_prec == CCLR_FP64) launch_zgemm(g, c->stream);
+    else launch_zgemm_lowp(g, c->sigma_prec, c->stream);
+  };
   if (c->prof) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, c->stream));
-    launch_zgemm(g, c->stream);
+    launch();
     HIPCHK(hipEventRecord(e1, c->stream));
     c->prof_events.push_back({e0, e1});
     c->prof_flops.push_back(8.0 * (double)g.M * (double)g.N * (double)g.K);
   } else {
-    launch_zgemm(g, c->stream);
+    launch();
   }
 }
 }  // namespace

@@ -275,7 +275,7 @@ unsigned vgrid(i64 n) {
 
 // --------------------------------------------------------------- driver
 int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
-             cclr_solve_info* info) {
+             cclr_solve_info* info, double tol, int maxit_in) {
   auto t0 = std::chrono::steady_clock::now();
   const i64 ov = c->ns(), nd = c->nd(), n = ov + nd;
   const int ms = std::max(4, std::min(c->opt.max_subspace, 120));
@@ -365,7 +365,7 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
   int iters = 0;
   long nsigma = 0;
   auto sigma = (side == CCLR_RIGHT) ? sigma_right : sigma_left;
-  const int maxit = std::max(1, c->opt.maxiter);
+  const int maxit = std::max(1, maxit_in);
   while (na > 0) {
     // batched transform of the newest trial vectors
     for (int a = 0; a < na; ++a) {
@@ -402,7 +402,7 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
       const int r = act[a];
       res[r] = std::sqrt(std::max(hv[r].x, 0.0)) / xinorm[r];
       msub[r] = m;
-      if (res[r] <= c->opt.tol || !std::isfinite(res[r])) done[r] = 1;
+      if (res[r] <= tol || !std::isfinite(res[r])) done[r] = 1;
       else still.push_back(r);
     }
     if (still.empty() || iters >= maxit) break;
@@ -443,7 +443,7 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
   double mx = 0.0;
   for (int r = 0; r < nr; ++r) {
     mx = std::max(mx, res[r]);
-    if (!(res[r] <= c->opt.tol)) conv = 0;
+    if (!(res[r] <= tol)) conv = 0;
   }
   if (info) {
     info->iters = iters;
@@ -453,4 +453,117 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
     info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return conv ? CCLR_OK : CCLR_ENOTCONV;
+}
+
+// ------------------------------------------------------- precision driver
+namespace {
+__global__ __launch_bounds__(256) void k_axpy_set(cplx* x, const cplx* y, i64 n, double a) {
+  // x = x + a*y
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (i64)gridDim.x * blockDim.x) {
+    x[e].x += a * y[e].x;
+    x[e].y += a * y[e].y;
+  }
+}
+void axpy(cclr_ctx* c, cplx* x, const cplx* y, i64 n, double a) {
+  if (n <= 0) return;
+  i64 g = std::min<i64>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_axpy_set, dim3((unsigned)g), dim3(256), 0, c->stream, x, y, n, a);
+  HIPCHK(hipGetLastError());
+}
+}  // namespace
+
+// Solve with the context's precision.  FP64: one Davidson solve.  FP32 /
+// split-BF16: iterative refinement — the Davidson solve runs with low-
+// precision ladder and ring products (its residuals, orthogonalisation and
+// projected system stay FP64), then the true residual R = (A - z) x + b is
+// formed with FP64 transforms and the correction equation is solved the same
+// way, until ||R|| <= tol ||b||.
+int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
+                 cclr_solve_info* info) {
+  const double tol = c->opt.tol;
+  if (c->opt.prec == CCLR_FP64) {
+    c->sigma_prec = CCLR_FP64;
+    return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter);
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  const i64 ov = c->ns(), nd = c->nd();
+  hipStream_t st = c->stream;
+  Arena::Mark mk = c->arena.mark();
+  auto vbuf = [&](int nvec) {
+    VecSet v;
+    v.s = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * ov));
+    v.d = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * nd));
+    v.n = nvec;
+    return v;
+  };
+  VecSet R = vbuf(nr), D = vbuf(nr);
+  cplx* zd = (cplx*)c->arena.get(sizeof(cplx) * nr);
+  HIPCHK(hipMemcpyAsync(zd, zh, sizeof(cplx) * nr, hipMemcpyHostToDevice, st));
+  launch_fill(xout.s, nr * ov, cx(0.0), st);
+  launch_fill(xout.d, nr * nd, cx(0.0), st);
+  HIPCHK(hipMemcpyAsync(R.s, rhs.s, sizeof(cplx) * nr * ov, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(R.d, rhs.d, sizeof(cplx) * nr * nd, hipMemcpyDeviceToDevice, st));
+  // inner accuracy: what the low-precision products can deliver
+  const double inner = c->opt.prec == CCLR_FP32 ? 1e-6 : 1e-4;
+  auto sigma = (side == CCLR_RIGHT) ? sigma_right : sigma_left;
+  // ||v_r|| per right-hand side (device Gram kernels, FP64)
+  int* act = (int*)c->arena.get(sizeof(int) * nr);
+  cplx* partial = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * kChunks);
+  cplx* nrm = (cplx*)c->arena.get(sizeof(cplx) * nr);
+  {
+    std::vector<int> all(nr);
+    for (int r = 0; r < nr; ++r) all[r] = r;
+    HIPCHK(hipMemcpyAsync(act, all.data(), sizeof(int) * nr, hipMemcpyHostToDevice, st));
+  }
+  auto norms = [&](const VecSet& v) {
+    const VS X{v.s, v.d, 1};
+    hipLaunchKernelGGL(k_gram, dim3(kChunks, 1, nr), dim3(kThreads), 0, st, X, 0, 1, X, 0, act, ov, nd, partial);
+    hipLaunchKernelGGL(k_reduce, dim3(nr), dim3(kThreads), 0, st, partial, 1, act, nrm, 1, 0, 0);
+    std::vector<cplx> h(nr);
+    HIPCHK(hipMemcpyAsync(h.data(), nrm, sizeof(cplx) * nr, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> out(nr);
+    for (int r = 0; r < nr; ++r) out[r] = std::sqrt(std::max(h[r].x, 0.0));
+    return out;
+  };
+  const std::vector<double> b0 = norms(rhs);
+  int iters = 0, outer = 0;
+  long nsig = 0;
+  double worst = 0.0;
+  int rc = CCLR_ENOTCONV;
+  const int max_outer = 8;
+  for (outer = 0; outer < max_outer; ++outer) {
+    cclr_solve_info in{};
+    c->sigma_prec = c->opt.prec;
+    davidson(c, side, nr, zh, R, D, &in, inner, c->opt.maxiter);
+    iters += in.iters;
+    nsig += in.nsigma;
+    axpy(c, xout.s, D.s, nr * ov, 1.0);
+    axpy(c, xout.d, D.d, nr * nd, 1.0);
+    // true residual with FP64 transforms: R = (A - z) x + b
+    c->sigma_prec = CCLR_FP64;
+    sigma(c, xout, R, zd);
+    nsig += nr;
+    axpy(c, R.s, rhs.s, nr * ov, 1.0);
+    axpy(c, R.d, rhs.d, nr * nd, 1.0);
+    const std::vector<double> rn = norms(R);
+    worst = 0.0;
+    for (int r = 0; r < nr; ++r) worst = std::max(worst, b0[r] > 0 ? rn[r] / b0[r] : 0.0);
+    if (worst <= tol) {
+      rc = CCLR_OK;
+      ++outer;
+      break;
+    }
+  }
+  c->sigma_prec = CCLR_FP64;
+  HIPCHK(hipStreamSynchronize(st));
+  c->arena.reset(mk);
+  if (info) {
+    info->iters = iters;
+    info->converged = rc == CCLR_OK;
+    info->resnorm = worst;
+    info->nsigma = nsig;
+    info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return rc;
 }

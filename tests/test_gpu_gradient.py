@@ -1,0 +1,136 @@
+"""Adjoint of the response function with respect to the perturbation
+matrices (cclr_response_backward and the torch.autograd wrapper).
+
+Reference: central finite differences of the CPU oracle's response function
+for L(X) = Re sum conj(G) <<X_p;X_q>>.  L is a quadratic polynomial in the
+entries of X (xi^X and eta^X are linear in X), so the central difference is
+exact up to rounding for any step.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gen import synth as s
+from helpers import config_problem
+from oracle import cclr_ref as O
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(torch.complex128).cuda()
+
+
+def loss(ref, Xs, zs, G):
+    out = np.stack([ref.response(Xs, z) for z in zs])
+    return float(np.real(np.sum(np.conj(G) * out)))
+
+
+def fd_dir(ref, Xs, zs, G, r, d, h=1e-3):
+    """central difference of L along the complex direction d of X_r"""
+    Xp = [x.copy() for x in Xs]
+    Xm = [x.copy() for x in Xs]
+    Xp[r] = Xp[r] + h * d
+    Xm[r] = Xm[r] - h * d
+    return (loss(ref, Xp, zs, G) - loss(ref, Xm, zs, G)) / (2 * h)
+
+
+def an_dir(g, d):
+    """directional derivative from the gradient convention dL/dRe + i dL/dIm"""
+    return float(np.real(np.sum(np.conj(g) * d)))
+
+
+@pytest.fixture(scope="module")
+def small():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_14296_amd as cc
+    pb, inst, H, t1, t2 = config_problem(3, 6, 4)
+    ref = O.CCLR(H, t1, t2)
+    ref.solve_lambda("dense")
+    op = cc.cclr_default_options()
+    op.tol = 1e-12
+    ctx = cc.cclr_create(3, 6, op)
+    keep = [dev(H.f)] + [dev(H.blocks[k]) for k in s.CANONICAL_BLOCKS] + [dev(t1), dev(t2)]
+    cc.cclr_set_hamiltonian(ctx, *keep[:7])
+    cc.cclr_set_amplitudes(ctx, *keep[7:])
+    Xs = [s.dipole(pb, 0).numpy(), s.magnetic_like(pb, 0).numpy()]
+    yield cc, ctx, ref, Xs
+    cc.cclr_destroy(ctx)
+
+
+def test_backward_matches_oracle_finite_differences(small):
+    cc, ctx, ref, Xs = small
+    zs = [0.3 + 0.02j, 0.0]
+    rng = np.random.default_rng(0)
+    G = rng.normal(size=(len(zs), 2, 2)) + 1j * rng.normal(size=(len(zs), 2, 2))
+    dX = [torch.empty_like(dev(x)) for x in Xs]
+    rc, info = cc.cclr_response_backward(ctx, [dev(x) for x in Xs], [z.real for z in zs], [z.imag for z in zs],
+                                         G, dX)
+    assert rc == 0, info.as_dict()
+    for r in range(2):
+        g = dX[r].cpu().numpy()
+        for k in range(4):
+            d = rng.normal(size=g.shape) + 1j * rng.normal(size=g.shape)
+            if k == 0:
+                d = np.zeros_like(g)
+                d[1, 7] = 1.0          # one real entry (ov block)
+            if k == 1:
+                d = np.zeros_like(g)
+                d[5, 2] = 1j           # one imaginary entry (vo block)
+            fd = fd_dir(ref, Xs, zs, G, r, d)
+            an = an_dir(g, d)
+            print(f"gradient X_{r} direction {k}: {an:.12e} vs oracle FD {fd:.12e}", flush=True)
+            assert abs(an - fd) <= 1e-8 * max(abs(fd), 1e-3 * np.abs(g).max())
+
+
+def test_autograd_wrapper(small):
+    cc, ctx, ref, Xs = small
+    z = 0.25 + 0.01j
+    X = [dev(x).requires_grad_(True) for x in Xs]
+    out = cc.response_function(ctx, X, [z.real], [z.imag])
+    ref_out = ref.response(Xs, z)
+    assert np.linalg.norm(out.detach().cpu().numpy()[0] - ref_out) <= 1e-9 * np.linalg.norm(ref_out)
+    G = torch.tensor(np.arange(4).reshape(1, 2, 2) * (0.3 - 0.2j) + 1.0, dtype=torch.complex128, device="cuda")
+    L = (G.conj() * out).real.sum()
+    L.backward()
+    rng = np.random.default_rng(3)
+    for r in range(2):
+        d = rng.normal(size=Xs[r].shape) + 1j * rng.normal(size=Xs[r].shape)
+        fd = fd_dir(ref, Xs, [z], G.cpu().numpy(), r, d)
+        an = an_dir(X[r].grad.cpu().numpy(), d)
+        assert abs(an - fd) <= 1e-8 * abs(fd)
+
+
+def test_backward_config1_directional(small):
+    """o=4, v=16: directional derivatives along random complex directions."""
+    import paper_2307_14296_amd as cc
+    pb, inst, H, t1, t2 = config_problem(4, 16, 0)
+    ref = O.CCLR(H, t1, t2)
+    op = cc.cclr_default_options()
+    op.tol = 1e-12
+    ctx = cc.cclr_create(4, 16, op)
+    try:
+        keep = [dev(H.f)] + [dev(H.blocks[k]) for k in s.CANONICAL_BLOCKS] + [dev(t1), dev(t2)]
+        cc.cclr_set_hamiltonian(ctx, *keep[:7])
+        cc.cclr_set_amplitudes(ctx, *keep[7:])
+        Xs = [s.dipole(pb, k).numpy() for k in range(3)]
+        z = 0.1 + 0.005j
+        G = np.ones((1, 3, 3), dtype=np.complex128) * (0.5 + 0.25j)
+        dX = [torch.empty_like(dev(x)) for x in Xs]
+        rc, info = cc.cclr_response_backward(ctx, [dev(x) for x in Xs], [z.real], [z.imag], G, dX)
+        assert rc == 0
+        rng = np.random.default_rng(1)
+        for r in range(3):
+            d = rng.normal(size=Xs[r].shape) + 1j * rng.normal(size=Xs[r].shape)
+            h = 1e-3
+            Xp = [x.copy() for x in Xs]
+            Xm = [x.copy() for x in Xs]
+            Xp[r] = Xp[r] + h * d
+            Xm[r] = Xm[r] - h * d
+            fd = (loss(ref, Xp, [z], G) - loss(ref, Xm, [z], G)) / (2 * h)
+            an = float(np.real(np.sum(np.conj(dX[r].cpu().numpy()) * d)))
+            print(f"config1 directional derivative X_{r}: {an:.12e} vs FD {fd:.12e}", flush=True)
+            assert abs(an - fd) <= 1e-8 * abs(fd)
+    finally:
+        cc.cclr_destroy(ctx)
