@@ -113,8 +113,12 @@ def main():
     ap.add_argument("--max-subspace", type=int, default=24)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="run a plain device copy of this many GiB first (reference for HBM byte counters)")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
-                    help="skip the mixed-precision (FP32 products + FP64 refinement) run")
+                    help="skip the mixed-precision runs (reduced-precision products + FP64 refinement)")
+    ap.add_argument("--mixed-precs", default="fp32,bf16x3",
+                    help="comma list of reduced precisions to run after the FP64 run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -130,6 +134,7 @@ def main():
     L.cclr_dbg_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.cclr_dbg_set_sigma_prec.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.cclr_dbg_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_longlong]
     o, v = args.o, args.v
     dev = torch.device("cuda:0")
     z = complex(args.omega, args.gamma)
@@ -144,7 +149,7 @@ def main():
         opt = cc.cclr_default_options()
         opt.max_subspace = args.max_subspace
         opt.tol = args.tol
-        opt.prec = {"fp64": cc.CCLR_FP64, "fp32": cc.CCLR_FP32}[prec]
+        opt.prec = {"fp64": cc.CCLR_FP64, "fp32": cc.CCLR_FP32, "bf16x3": cc.CCLR_BF16X3}[prec]
         ctx = cc.cclr_create(o, v, opt)
         cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
         del V
@@ -195,22 +200,35 @@ def main():
         nl, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
         L.cclr_dbg_profile_read(ctx, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
         L.cclr_dbg_profile(ctx, 0)
+        buf = ctypes.create_string_buffer(1 << 16)
+        L.cclr_dbg_tuning(ctx, -1, buf, len(buf))
+        res["gemm_tuning"] = [ln for ln in buf.value.decode().splitlines() if ln][:12]
         cc.cclr_destroy(ctx)
         del f, t1, t2, X
         torch.cuda.empty_cache()
         res.update({"transforms": ntr, "dt": dt, "nl": nl.value, "ms": ms.value, "fl": fl.value})
         return res
 
+    if args.copy_probe_gib > 0:
+        nel = int(args.copy_probe_gib * (1 << 30) / 16)
+        a = torch.ones(nel, dtype=torch.complex128, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nel * 16 / (1 << 30):.3f} GiB read + written")
+        del a, b
+        torch.cuda.empty_cache()
     main_res = run("fp64")
-    mixed = None
+    mixed = {}
     if args.mixed:
-        mixed = run("fp32")
+        for p in [x for x in args.mixed_precs.split(",") if x]:
+            mixed[p] = run(p)
     ntr, dt = main_res["transforms"], main_res["dt"]
     nl = ctypes.c_longlong(main_res["nl"])
     ms = ctypes.c_double(main_res["ms"])
     fl = ctypes.c_double(main_res["fl"])
     t_gen = main_res["input_generation_s"]
-    extra = {k: main_res[k] for k in ("solver", "rc") if k in main_res}
+    extra = {k: main_res[k] for k in ("solver", "rc", "gemm_tuning") if k in main_res}
     achieved = fl.value / (ms.value * 1e-3) / 1e12 if ms.value > 0 else 0.0
     sf = sigma_flops(o, v)
     roofline = {
@@ -248,18 +266,24 @@ def main():
     if "alpha" in main_res:
         a = main_res["alpha"]
         line["config"]["alpha_fp64"] = [[[x.real, x.imag] for x in row] for row in a]
-    if mixed is not None:
-        mx = {"prec": "fp32 ladder/ring products, FP64 refinement", "value": mixed["transforms"] / mixed["dt"],
-              "ms_per_step": 1e3 * mixed["dt"] / args.steps, "transforms": mixed["transforms"],
-              "job_speedup_vs_fp64": main_res["dt"] / mixed["dt"]}
-        if "alpha" in mixed:
+    names = {"fp32": "FP32 MFMA ladder/ring products, FP64 refinement",
+             "bf16x3": "split-BF16 MFMA ladder/ring products (3 bf16 products per real product, FP32 "
+                       "accumulation), FP64 refinement"}
+    if mixed:
+        line["mixed_precision"] = {}
+    for p, mres in mixed.items():
+        mx = {"prec": names[p], "value": mres["transforms"] / mres["dt"],
+              "ms_per_step": 1e3 * mres["dt"] / args.steps, "transforms": mres["transforms"],
+              "job_speedup_vs_fp64": main_res["dt"] / mres["dt"]}
+        if "alpha" in mres:
             import numpy as np
-            mx["alpha_rel_err_vs_fp64"] = float(np.linalg.norm(mixed["alpha"] - main_res["alpha"]) /
+            mx["alpha_rel_err_vs_fp64"] = float(np.linalg.norm(mres["alpha"] - main_res["alpha"]) /
                                                 np.linalg.norm(main_res["alpha"]))
-            mx["solver"] = mixed.get("solver")
-        if mixed["ms"] > 0:
-            mx["ladder_tflops"] = round(mixed["fl"] / (mixed["ms"] * 1e-3) / 1e12, 3)
-        line["mixed_precision"] = mx
+            mx["solver"] = mres.get("solver")
+        if mres["ms"] > 0:
+            mx["ladder_tflops_fp64_equivalent"] = round(mres["fl"] / (mres["ms"] * 1e-3) / 1e12, 3)
+            mx["ladder_avg_launch_ms"] = round(mres["ms"] / max(1, mres["nl"]), 4)
+        line["mixed_precision"][p] = mx
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline()

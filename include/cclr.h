@@ -150,22 +150,36 @@ int cclr_response_function(cclr_ctx* ctx, int nx, const cclr_c64* const* X,
                            int nfreq, const double* omega, const double* gamma,
                            cclr_c64* out, cclr_solve_info* info);
 
-/* Gradient of the response function with respect to the perturbation
- * matrices (adjoint of cclr_response_function).  For the real scalar
+/* Gradient of the response function (adjoint of cclr_response_function).
+ * For the real scalar
  *   L = Re sum_{w,p,q} conj(G[w][p][q]) * out[w][p][q]
  * (G: HOST array nfreq*nx*nx, e.g. the output gradient handed down by an
- * autograd engine) it writes dX[r] = dL/dRe X_r + i dL/dIm X_r into the nx
- * DEVICE n x n matrices dX[r] (overwritten), treating every entry of X_r as
- * independent.  The response function depends on X through xi^X and eta^X,
- * which are linear in X (SI, "Linear response"); the adjoint of the damped
- * solves is the left transform, so the gradient needs one left damped solve
- * x (A - f) = -u per perturbation and frequency f in {z, -z, z*, -z*}
- * (eq. "LR response equation_cpp", transposed) followed by one-particle
- * transition densities of xi^X and eta^X.  Intermediates and solutions are
- * recomputed, not stored by the forward call.  Gradients with respect to f
- * and the integrals are not provided. */
+ * autograd engine) it writes gradients in the convention
+ * dL/dRe x + i dL/dIm x for every complex input entry x:
+ *   dX[r]  (array of nx DEVICE n x n matrices, or NULL): with respect to the
+ *          perturbation matrices, every entry of X_r treated as independent;
+ *   df     (DEVICE n x n, or NULL) and dV (array of 6 DEVICE blocks in the
+ *          layouts of cclr_set_hamiltonian: oooo, ooov, oovv, ovov, ovvv,
+ *          vvvv; or NULL): with respect to the Fock matrix and the
+ *          antisymmetrized integrals, projected onto changes that keep the
+ *          symmetries of the inputs (f Hermitian; <pq||rs> antisymmetric in
+ *          pq and in rs, and equal to conj <rs||pq>), so that for every such
+ *          change dL = Re sum conj(grad) * change.  df and dV are given
+ *          together or both NULL.  The amplitudes t are held fixed.
+ * All outputs are overwritten.
+ * X enters through xi^X and eta^X, linear in X (SI, "Linear response"); the
+ * adjoint of the damped solves is the left transform, so the gradient needs
+ * one left damped solve x (A - f) = -u per perturbation and frequency f in
+ * {z, -z, z*, -z*} (eq. "LR response equation_cpp", transposed) followed by
+ * transition densities of xi^X and eta^X.  The Hamiltonian enters through
+ * the Hbar intermediates, the Jacobian, the Hessian product t^X F and the
+ * Lambda equation (theory section, eq. "Lambda"), all linear in it at fixed
+ * t; its gradient adds one right solve A x = -lambda-bar and the transposed
+ * products of the intermediates, sigma and t^X F.  Intermediates and
+ * solutions are recomputed, not stored by the forward call. */
 int cclr_response_backward(cclr_ctx* ctx, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
-                           const double* gamma, const cclr_c64* G, cclr_c64* const* dX, cclr_solve_info* info);
+                           const double* gamma, const cclr_c64* G, cclr_c64* const* dX, cclr_c64* df,
+                           cclr_c64* const* dV, cclr_solve_info* info);
 
 /* Message describing the last error on ctx (or a creation error if ctx is
  * NULL); valid until the next call on the same context. */

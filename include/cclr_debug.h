@@ -19,6 +19,13 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
                    int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn, int conjB, cclr_c64* C,
                    long long sCb, long long sCm, long long sCn, double alpha_re, double alpha_im, int beta);
 
+/* The same product (batch 1) in reduced arithmetic: prec = CCLR_FP32 (FP32
+ * MFMA) or CCLR_BF16X3 (split-BF16 MFMA, three bf16 products per real
+ * product, FP32 accumulation); operands and C stay complex128. */
+int cclr_dbg_zgemm_lowp(int prec, int M, int N, int K, const cclr_c64* A, long long sAm, long long sAk, int conjA,
+                        const cclr_c64* B, long long sBk, long long sBn, int conjB, cclr_c64* C, long long sCm,
+                        long long sCn, double alpha_re, double alpha_im, int beta);
+
 /* C[lc] += alpha * sum A[la] B[lb] through the contraction engine; A, B, C are
  * contiguous row-major tensors with the given dims (nd = strlen of labels). */
 int cclr_dbg_contract(cclr_ctx* ctx, double alpha_re, double alpha_im, const cclr_c64* A, const char* la,
@@ -43,6 +50,11 @@ int cclr_dbg_profile_read(cclr_ctx* ctx, long long* launches, double* ms, double
  * cclr_jacobian_right/left calls on ctx (CCLR_FP64, CCLR_FP32, CCLR_BF16X3);
  * the solvers set it themselves. */
 int cclr_dbg_set_sigma_prec(cclr_ctx* ctx, int prec);
+
+/* Autotuner record: writes up to cap bytes of text, one line per tuned
+ * GEMM shape class: "MxNxK bB layoutL: ms of each variant -> chosen".
+ * enable >= 0 switches tuning on (1) or off (0) for later products. */
+int cclr_dbg_tuning(cclr_ctx* ctx, int enable, char* buf, long long cap);
 
 #ifdef __cplusplus
 }

@@ -72,8 +72,8 @@ def lib():
     L.cclr_solve_lambda.argtypes = [P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_get_lambda.argtypes = [P, P, P]
     L.cclr_response_function.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(cclr_solve_info)]
-    L.cclr_response_backward.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(P),
-                                         ctypes.POINTER(cclr_solve_info)]
+    L.cclr_response_backward.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(P), P,
+                                         ctypes.POINTER(P), ctypes.POINTER(cclr_solve_info)]
     L.cclr_last_error.argtypes = [P]
     L.cclr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -191,16 +191,20 @@ def cclr_response_function(ctx, X, omega, gamma):
     return rc, out[:nf], info
 
 
-def cclr_response_backward(ctx, X, omega, gamma, G, dX):
-    """G: host array (nfreq, nx, nx) complex; dX: list of GPU complex128 (n, n) tensors (written)."""
+def cclr_response_backward(ctx, X, omega, gamma, G, dX=None, df=None, dV=None):
+    """G: host array (nfreq, nx, nx) complex.  Outputs (GPU complex128, overwritten; None to skip):
+    dX: list of nx (n, n) tensors; df: (n, n); dV: list of the six integral blocks in the order
+    oooo, ooov, oovv, ovov, ovvv, vvvv."""
     import numpy as np
     nx = len(X)
     G = np.ascontiguousarray(np.asarray(G, dtype=np.complex128))
     ptrs = (ctypes.c_void_p * nx)(*[_ptr(x, "X").value for x in X])
-    dptrs = (ctypes.c_void_p * nx)(*[_ptr(d, "dX").value for d in dX])
+    dptrs = (ctypes.c_void_p * nx)(*[_ptr(d, "dX").value for d in dX]) if dX is not None else None
+    vptrs = (ctypes.c_void_p * 6)(*[_ptr(d, "dV").value for d in dV]) if dV is not None else None
+    fptr = _ptr(df, "df") if df is not None else None
     info = cclr_solve_info()
     rc = lib().cclr_response_backward(ctx, nx, ptrs, len(omega), _dbl(omega), _dbl(gamma),
-                                      ctypes.c_void_p(G.ctypes.data), dptrs, ctypes.byref(info))
+                                      ctypes.c_void_p(G.ctypes.data), dptrs, fptr, vptrs, ctypes.byref(info))
     _check(ctx, rc, allow_notconv=True)
     return rc, info
 
@@ -229,7 +233,7 @@ def _autograd():
             Xc = fctx.saved_tensors
             dX = [torch.empty_like(x) for x in Xc]
             cclr_response_backward(fctx.handle, list(Xc), fctx.omega, fctx.gamma,
-                                   gout.detach().cpu().numpy(), dX)
+                                   gout.detach().cpu().numpy(), dX=dX)
             return (None, None, None, *dX)
 
     return ResponseFunction

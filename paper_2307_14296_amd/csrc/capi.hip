@@ -8,18 +8,13 @@
 
 #include "internal.h"
 
-void launch_check_finite(const cplx* p, i64 n, int* flag, hipStream_t s);
-void launch_bdot(int npair, const cplx* const* xs, const cplx* const* xd, const cplx* const* ys,
-                 const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s);
-int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
-                 cclr_solve_info* info);
-void build_xi(cclr_ctx* c, const cplx* X, const VecSet& out);
-void build_eta(cclr_ctx* c, const cplx* X, const VecSet& out);
-void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out);
-void density_xi(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
-void density_eta(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
-void launch_caxpy(i64 n, cplx a, const cplx* x, cplx* y, hipStream_t s);
-void launch_conj_inplace(i64 n, cplx* x, hipStream_t s);
+VecSet packed_buf(cclr_ctx* c, int n) {
+  VecSet v;
+  v.s = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(n * c->ns()));
+  v.d = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(n * c->nd()));
+  v.n = n;
+  return v;
+}
 
 static thread_local std::string g_create_error;
 
@@ -84,14 +79,6 @@ void check_freqs(int n, const double* omega, const double* gamma) {
     REQUIRE(std::isfinite(omega[k]) && std::isfinite(gamma[k]), CCLR_EINVAL, "non-finite frequency");
     REQUIRE(gamma[k] >= 0.0, CCLR_EINVAL, "negative damping gamma");
   }
-}
-
-VecSet packed_buf(cclr_ctx* c, int n) {
-  VecSet v;
-  v.s = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(n * c->ns()));
-  v.d = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(n * c->nd()));
-  v.n = n;
-  return v;
 }
 
 // full (r1[n][o][v], r2[n][o][o][v][v]) -> packed
@@ -422,17 +409,24 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
 }
 
 int cclr_response_backward(cclr_ctx* c, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
-                           const double* gamma, const cclr_c64* Gh, cclr_c64* const* dX, cclr_solve_info* info) {
+                           const double* gamma, const cclr_c64* Gh, cclr_c64* const* dX, cclr_c64* df,
+                           cclr_c64* const* dV, cclr_solve_info* info) {
   if (!c) return CCLR_EINVAL;
   return guarded(c, [&]() -> int {
     auto t0 = std::chrono::steady_clock::now();
     require_t(c);
-    REQUIRE(nx >= 1 && X && dX && Gh, CCLR_EINVAL, "need perturbations, G and gradient outputs");
+    REQUIRE(nx >= 1 && X && Gh, CCLR_EINVAL, "need perturbations and G");
+    REQUIRE((df == nullptr) == (dV == nullptr), CCLR_EINVAL, "df and dV are given together or not at all");
+    REQUIRE(dX || df, CCLR_EINVAL, "no gradient requested (dX, df and dV are NULL)");
     check_freqs(nfreq, omega, gamma);
     const i64 n = c->o + c->v, ov = c->ns(), nd = c->nd();
     for (int p = 0; p < nx; ++p) {
       check_ptr(X[p], "X");
-      check_ptr(dX[p], "dX");
+      if (dX) check_ptr(dX[p], "dX");
+    }
+    if (df) {
+      check_ptr(df, "df");
+      for (int b = 0; b < 6; ++b) check_ptr(dV[b], "dV");
     }
     for (int k = 0; k < nfreq * nx * nx; ++k)
       REQUIRE(std::isfinite(Gh[k].re) && std::isfinite(Gh[k].im), CCLR_EINVAL, "non-finite G");
@@ -476,6 +470,12 @@ int cclr_response_backward(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
     hessian_product(c, sol, tf);
     // adjoint right-hand sides u[f][r] (left solves) and density vectors y[r] (eta densities)
     VecSet U = packed_buf(c, nr), Y = packed_buf(c, nx);
+    // Hessian pairings (F PA_r) . t_r for the Hamiltonian gradient: PA_r = sum cf t^p(-s), r = (s, q)
+    VecSet PA = df ? packed_buf(c, nr) : VecSet{};
+    if (df) {
+      launch_fill(PA.s, nr * ov, cx(0.0), c->stream);
+      launch_fill(PA.d, nr * nd, cx(0.0), c->stream);
+    }
     launch_fill(U.s, nr * ov, cx(0.0), c->stream);
     launch_fill(U.d, nr * nd, cx(0.0), c->stream);
     launch_fill(Y.s, nx * ov, cx(0.0), c->stream);
@@ -508,6 +508,7 @@ int cclr_response_backward(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
             // t^p(-s) with coefficient vector eta^q + F t^q(s): left solve at -s for X_p
             axpy(U, fms * nx + p, eta, q, cf);
             axpy(U, fms * nx + p, tf, fs * nx + q, cf);
+            if (df) axpy(PA, fs * nx + q, sol, fms * nx + p, cf);
           }
       }
     }
@@ -515,24 +516,36 @@ int cclr_response_backward(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
     VecSet xl = packed_buf(c, nr);
     const int ra = solve_system(c, CCLR_LEFT, nr, zr.data(), U, xl, &ainfo);
     nsig += ainfo.nsigma;
-    for (int r = 0; r < nx; ++r) launch_fill((cplx*)dX[r], n * n, cx(0.0), c->stream);
-    for (int f = 0; f < nf; ++f)
+    if (dX) {
+      for (int r = 0; r < nx; ++r) launch_fill((cplx*)dX[r], n * n, cx(0.0), c->stream);
+      for (int f = 0; f < nf; ++f)
+        for (int r = 0; r < nx; ++r)
+          density_xi(c, VecSet{xl.s + (f * nx + r) * ov, xl.d + (f * nx + r) * nd, 1}, (cplx*)dX[r], cx(1.0));
       for (int r = 0; r < nx; ++r)
-        density_xi(c, VecSet{xl.s + (f * nx + r) * ov, xl.d + (f * nx + r) * nd, 1}, (cplx*)dX[r], cx(1.0));
-    for (int r = 0; r < nx; ++r)
-      density_eta(c, VecSet{Y.s + r * ov, Y.d + r * nd, 1}, (cplx*)dX[r], cx(1.0));
-    // dL/dRe X + i dL/dIm X = conj(dh/dX)
-    for (int r = 0; r < nx; ++r) launch_conj_inplace(n * n, (cplx*)dX[r], c->stream);
+        density_eta(c, VecSet{Y.s + r * ov, Y.d + r * nd, 1}, (cplx*)dX[r], cx(1.0));
+      // dL/dRe X + i dL/dIm X = conj(dh/dX)
+      for (int r = 0; r < nx; ++r) launch_conj_inplace(n * n, (cplx*)dX[r], c->stream);
+    }
+    cclr_solve_info hinfo{};
+    if (df) {
+      cplx* Xs = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nx * n * n));
+      for (int p = 0; p < nx; ++p)
+        HIPCHK(hipMemcpyAsync(Xs + p * n * n, X[p], sizeof(cplx) * n * n, hipMemcpyDeviceToDevice, c->stream));
+      hamiltonian_adjoint(c, nx, Xs, sol, xl, Y, PA, sol, (cplx*)df, (cplx* const*)dV, &hinfo);
+      nsig += hinfo.nsigma;
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     c->arena.reset(mk);
     if (info) {
       info->iters = std::max(std::max(sinfo.iters, ainfo.iters), linfo.iters);
-      info->converged = sinfo.converged && ainfo.converged && (linfo.iters == 0 || linfo.converged);
-      info->resnorm = std::max(std::max(sinfo.resnorm, ainfo.resnorm), linfo.resnorm);
+      info->converged = sinfo.converged && ainfo.converged && (linfo.iters == 0 || linfo.converged) &&
+                        (!df || hinfo.converged);
+      info->resnorm = std::max(std::max(std::max(sinfo.resnorm, ainfo.resnorm), linfo.resnorm), hinfo.resnorm);
       info->nsigma = nsig;
       info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
-    if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV || ra == CCLR_ENOTCONV) return CCLR_ENOTCONV;
+    if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV || ra == CCLR_ENOTCONV || (df && !hinfo.converged))
+      return CCLR_ENOTCONV;
     return CCLR_OK;
   });
 }

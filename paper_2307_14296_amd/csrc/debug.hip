@@ -24,6 +24,38 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
   }
 }
 
+int cclr_dbg_zgemm_lowp(int prec, int M, int N, int K, const cclr_c64* A, long long sAm, long long sAk, int conjA,
+                        const cclr_c64* B, long long sBk, long long sBn, int conjB, cclr_c64* C, long long sCm,
+                        long long sCn, double ar, double ai, int beta) {
+  void* wa = nullptr;
+  void* wb = nullptr;
+  int rc = CCLR_OK;
+  try {
+    REQUIRE(M > 0 && N > 0 && K > 0, CCLR_EINVAL, "empty product");
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K; g.batch = 1;
+    g.A = (const cplx*)A; g.sAm = sAm; g.sAk = sAk; g.conjA = conjA;
+    g.B = (const cplx*)B; g.sBk = sBk; g.sBn = sBn; g.conjB = conjB;
+    g.C = (cplx*)C; g.sCm = sCm; g.sCn = sCn;
+    g.ar = ar; g.ai = ai; g.beta = beta;
+    if (prec == CCLR_BF16X3) {
+      HIPCHK(hipMalloc(&wa, split_bytes(M, K)));
+      HIPCHK(hipMalloc(&wb, split_bytes(N, K)));
+      const SplitMat sa = launch_split_bf16(M, K, g.A, sAm, sAk, conjA, wa, nullptr);
+      const SplitMat sb = launch_split_bf16(N, K, g.B, sBn, sBk, conjB, wb, nullptr);
+      launch_cgemm_bf16x3(sa, sb, g.C, sCm, sCn, ar, ai, beta, nullptr);
+    } else {
+      launch_zgemm_lowp(g, prec, nullptr);
+    }
+    HIPCHK(hipDeviceSynchronize());
+  } catch (const CclrError& e) {
+    rc = e.code;
+  }
+  if (wa) (void)hipFree(wa);
+  if (wb) (void)hipFree(wb);
+  return rc;
+}
+
 static Ten dten(const cclr_c64* p, const char* l, const long long* dims) {
   Ten t;
   t.p = (cplx*)p;
@@ -115,6 +147,27 @@ int cclr_dbg_profile_read(cclr_ctx* c, long long* launches, double* ms, double* 
 int cclr_dbg_set_sigma_prec(cclr_ctx* c, int prec) {
   if (!c || (prec != CCLR_FP64 && prec != CCLR_FP32 && prec != CCLR_BF16X3)) return CCLR_EINVAL;
   c->sigma_prec = prec;
+  return CCLR_OK;
+}
+
+int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {
+  if (!c) return CCLR_EINVAL;
+  if (enable >= 0) c->autotune = enable != 0;
+  std::string out;
+  for (const auto& kv : c->gemm_tuning_log) {
+    out += kv.first + ":";
+    int best = 0;
+    for (size_t v = 0; v < kv.second.size(); ++v) {
+      out += " " + std::to_string(kv.second[v]);
+      if (kv.second[v] < kv.second[best]) best = (int)v;
+    }
+    out += " -> " + std::to_string(best) + "\n";
+  }
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>(out.size(), (size_t)cap - 1);
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
   return CCLR_OK;
 }
 }

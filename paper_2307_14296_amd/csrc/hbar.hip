@@ -15,6 +15,10 @@ void launch_diag(int o, int v, const cplx* Foo, const cplx* Fvv, cplx* diag, hip
 
 void build_intermediates(cclr_ctx* c) {
   const i64 o = c->o, v = c->v;
+  for (int w = 0; w < 4; ++w) {  // split copies of the previous operators
+    c->wsplit[w].release();
+    c->wsplit_m[w] = SplitMat{};
+  }
   Arena::Mark mk = c->arena.mark();
   const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
   Ten t1 = ten(c->t1, {o, v});

@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 #include <stdexcept>
 
@@ -102,14 +104,33 @@ struct GemmArgs {
   int kchunk;      // > 0: blockIdx.z is a K split covering [z*kchunk, (z+1)*kchunk) (batch must be 1)
 };
 void launch_zgemm(const GemmArgs& g, hipStream_t s);
+// FP64 kernel variants (tile shape, three or four real products per complex block)
+enum { GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4, GEMM_NVAR = 5 };
+void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);
+int gemm_default_variant(const GemmArgs& g);
 // the same product with FP32 (prec = CCLR_FP32) or split-BF16 (CCLR_BF16X3)
 // MFMA arithmetic and FP32 accumulation; operands and C stay complex128 in memory
 void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s);
+// Split-BF16 operand: a rows x K complex matrix as bf16 planes
+// [K/32][rows_pad][re_hi, re_lo, im_hi, im_lo][32], zero padded.
+struct SplitMat {
+  const void* p = nullptr;
+  int rows = 0, K = 0, rows_pad = 0, nkc = 0;
+};
+SplitMat split_shape(int rows, int K);
+size_t split_bytes(int rows, int K);
+// dst <- split of op(src)[r][k] = src[r*sR + k*sK] (conjugated if conj)
+SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, hipStream_t s);
+// C[m][n] (+)= alpha * sum_k A[m][k] B[n][k], three bf16 products per real product, FP32 accumulation
+void launch_cgemm_bf16x3(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
+                         int beta, hipStream_t s);
 // C[m][n] = (beta ? C : 0) + alpha * sum_s W[s][m][n]
 void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
                           int beta, hipStream_t s);
 // GEMM with automatic K splitting when the output has too few tiles to fill the GPU
 void run_gemm(cclr_ctx* c, const GemmArgs& g);
+// FP64 GEMM through the autotuner (large products: variant timed once per shape class)
+void tuned_gemm(cclr_ctx* c, const GemmArgs& g);
 
 struct CopyArgs {
   int nd;
@@ -158,6 +179,10 @@ struct cclr_ctx {
   DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo, Wvvvv;
   DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
+  // split-BF16 copies of the ladder and ring operators, made on first use in
+  // that precision: right ladder, left ladder, right ring, left ring
+  DevBuf wsplit[4];
+  SplitMat wsplit_m[4];
   DevBuf diag;       // Fock-like diagonal for preconditioning: singles then doubles (packed)
   DevBuf lam_s, lam_d;  // lambda, packed
   Arena arena;
@@ -165,6 +190,11 @@ struct cclr_ctx {
   // (CCLR_FP64 for the FP64 path and every true residual; opt.prec inside the
   // low-precision inner solves)
   int sigma_prec = CCLR_FP64;
+  // GEMM autotuner: best FP64 kernel variant per shape class, and a record of
+  // the timings that decided it (variant -> ms)
+  std::map<std::tuple<int, int, int, int, int>, int> gemm_choice;
+  std::vector<std::pair<std::string, std::vector<double>>> gemm_tuning_log;
+  bool autotune = true;
   // optional timing of the particle-particle ladder GEMM launches
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -197,3 +227,23 @@ void build_intermediates(cclr_ctx* c);
 // sigma for nvec packed vectors in `in` -> `out` (packed); z per vector (may be null)
 void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_dev);
 void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_dev);
+
+// ------------------------------------------------- solver and response pieces
+void launch_check_finite(const cplx* p, i64 n, int* flag, hipStream_t s);
+void launch_bdot(int npair, const cplx* const* xs, const cplx* const* xd, const cplx* const* ys,
+                 const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s);
+void launch_caxpy(i64 n, cplx a, const cplx* x, cplx* y, hipStream_t s);
+void launch_conj_inplace(i64 n, cplx* x, hipStream_t s);
+// (A - z_k) x_k = -rhs_k (right) or x_k (A - z_k) = -rhs_k (left) in the context's precision
+int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
+                 cclr_solve_info* info);
+// nvec packed vectors from the arena
+VecSet packed_buf(cclr_ctx* c, int n);
+void build_xi(cclr_ctx* c, const cplx* X, const VecSet& out);
+void build_eta(cclr_ctx* c, const cplx* X, const VecSet& out);
+void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out);
+void density_xi(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
+void density_eta(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
+// gradient with respect to f and the integral blocks (see adjoint.hip)
+void hamiltonian_adjoint(cclr_ctx* c, int nx, const cplx* Xs, const VecSet& sol, const VecSet& xl, const VecSet& Y,
+                         const VecSet& PA, const VecSet& PB, cplx* df, cplx* const* dV, cclr_solve_info* info);

@@ -4,7 +4,7 @@
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 // output row of v_mfma_f32_16x16x4_f32 for (lane, register)
-#define F32_ROW(lane, r) (4 * (r) + ((lane) >> 4))
+#define F32_ROW(lane, r) (4 * ((lane) >> 4) + (r))
 
 // --------------------------------------------------------------------------
 // Complex GEMM  C[b][m][n] (+)= alpha * sum_k A[b][m][k] * B[b][k][n]
@@ -150,14 +150,15 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int S, int M, int N, cons
 // barrier.  Four waves in a 2x2 arrangement, each owning a (BM/2)x(BN/2)
 // sub-tile.
 // --------------------------------------------------------------------------
-template <int BM, int BN, bool AK, bool BNF>
+template <int BM, int BN, bool AK, bool BNF, bool G3>
 __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-  __shared__ double sA[2][3][BK][BM + 1];  // Ar, Ai, Ar + Ai
-  __shared__ double sB[2][3][BK][BN + 1];  // Br, Bi - Br, Br + Bi
+  constexpr int NP = G3 ? 3 : 2;
+  __shared__ double sA[2][NP][BK][BM + 1];  // Ar, Ai (, Ar + Ai)
+  __shared__ double sB[2][NP][BK][BN + 1];  // Br, Bi - Br (, Br + Bi)  |  Br, Bi
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const i64 bz = blockIdx.z;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
       const double re = ra[r].x, im = sa * ra[r].y;
       sA[buf][0][kk][mm] = re;
       sA[buf][1][kk][mm] = im;
-      sA[buf][2][kk][mm] = re + im;
+      if (G3) sA[buf][2][kk][mm] = re + im;
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
@@ -208,19 +209,19 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
       const int kk = BNF ? e / BN : e % BK;
       const double re = rb[r].x, im = sb * rb[r].y;
       sB[buf][0][kk][nn] = re;
-      sB[buf][1][kk][nn] = im - re;
-      sB[buf][2][kk][nn] = re + im;
+      sB[buf][1][kk][nn] = G3 ? im - re : im;
+      if (G3) sB[buf][2][kk][nn] = re + im;
     }
   };
 
-  d4 k1[FM][FN], k2[FM][FN], k3[FM][FN];
+  d4 k1[FM][FN], k2[FM][FN], k3[G3 ? FM : 1][G3 ? FN : 1];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       k1[i][j] = d4{0, 0, 0, 0};
       k2[i][j] = d4{0, 0, 0, 0};
-      k3[i][j] = d4{0, 0, 0, 0};
+      if (G3) k3[G3 ? i : 0][G3 ? j : 0] = d4{0, 0, 0, 0};
     }
 
   gload(kbeg);
@@ -239,23 +240,42 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
         const int mm = wm + i * 16 + (lane & 15);
         ar[i] = sA[buf][0][kk][mm];
         ai[i] = sA[buf][1][kk][mm];
-        as[i] = sA[buf][2][kk][mm];
+        as[i] = G3 ? sA[buf][NP - 1][kk][mm] : 0.0;
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int nn = wn + j * 16 + (lane & 15);
         br[j] = sB[buf][0][kk][nn];
         bd[j] = sB[buf][1][kk][nn];
-        bs[j] = sB[buf][2][kk][nn];
+        bs[j] = G3 ? sB[buf][NP - 1][kk][nn] : 0.0;
       }
+      if (G3) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], br[j], k1[i][j], 0, 0, 0);
-          k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bd[j], k2[i][j], 0, 0, 0);
-          k3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bs[j], k3[i][j], 0, 0, 0);
-        }
+          for (int j = 0; j < FN; ++j) {
+            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], br[j], k1[i][j], 0, 0, 0);
+            k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bd[j], k2[i][j], 0, 0, 0);
+            k3[G3 ? i : 0][G3 ? j : 0] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bs[j], k3[G3 ? i : 0][G3 ? j : 0], 0, 0, 0);
+          }
+      } else {
+        // four products: k1 = Re, k2 = Im  (bd holds Bi here)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], k1[i][j], 0, 0, 0);
+            k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bd[j], k2[i][j], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bd[j], k1[i][j], 0, 0, 0);
+            k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], k2[i][j], 0, 0, 0);
+          }
+      }
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -271,7 +291,8 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
         const int m = m0 + wm + i * 16 + 4 * r + (lane >> 4);
         const int n = n0 + wn + j * 16 + (lane & 15);
         if (m < g.M && n < g.N) {
-          const double cr = k1[i][j][r] - k3[i][j][r], ci = k1[i][j][r] + k2[i][j][r];
+          const double cr = G3 ? k1[i][j][r] - k3[G3 ? i : 0][G3 ? j : 0][r] : k1[i][j][r];
+          const double ci = G3 ? k1[i][j][r] + k2[i][j][r] : k2[i][j][r];
           cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
           cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
           if (g.beta) {
@@ -605,39 +626,37 @@ inline unsigned grid_for(i64 total) {
 }
 }  // namespace
 
-void launch_zgemm(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-  if (g.K <= 0) {
-    if (!g.beta) {
-      // C = 0 for an empty reduction: handled by callers through tzero
-    }
-    return;
-  }
+// FP64 GEMM variants: tile 128x64 or 64x64, three or four real products
+template <int BM, int BN, bool G3>
+static void launch_p(const GemmArgs& g, hipStream_t s) {
   const bool ak = g.sAk == 1, bn = g.sBn == 1;
-  // large outputs: 128x64 tiles; otherwise 64x64
-  const bool big = (i64)g.M * g.N * g.batch >= (i64)128 * 64 * 1024;
-  if (big) {
-    dim3 grid((g.M + 127) / 128, (g.N + 63) / 64, g.batch);
-    if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<128, 64, true, true>), grid, dim3(256), 0, s, g);
-    else if (ak) hipLaunchKernelGGL((k_zgemm_p<128, 64, true, false>), grid, dim3(256), 0, s, g);
-    else if (bn) hipLaunchKernelGGL((k_zgemm_p<128, 64, false, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_zgemm_p<128, 64, false, false>), grid, dim3(256), 0, s, g);
-  } else {
-    dim3 grid((g.M + 63) / 64, (g.N + 63) / 64, g.batch);
-    if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<64, 64, true, true>), grid, dim3(256), 0, s, g);
-    else if (ak) hipLaunchKernelGGL((k_zgemm_p<64, 64, true, false>), grid, dim3(256), 0, s, g);
-    else if (bn) hipLaunchKernelGGL((k_zgemm_p<64, 64, false, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_zgemm_p<64, 64, false, false>), grid, dim3(256), 0, s, g);
+  dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, true, G3>), grid, dim3(256), 0, s, g);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, false, G3>), grid, dim3(256), 0, s, g);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, true, G3>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, false, G3>), grid, dim3(256), 0, s, g);
+}
+
+void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  switch (variant) {
+    case GEMM_128x64_G3: launch_p<128, 64, true>(g, s); break;
+    case GEMM_64x64_G3: launch_p<64, 64, true>(g, s); break;
+    case GEMM_128x64_G4: launch_p<128, 64, false>(g, s); break;
+    case GEMM_64x64_G4: launch_p<64, 64, false>(g, s); break;
+    default: {
+      dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
+      hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
+    }
   }
   HIPCHK(hipGetLastError());
 }
 
-void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
-                          int beta, hipStream_t s) {
-  hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((i64)M * N)), dim3(256), 0, s, S, M, N, W, C, sCm, sCn, ar, ai,
-                     beta);
-  HIPCHK(hipGetLastError());
+int gemm_default_variant(const GemmArgs& g) {
+  return (i64)g.M * g.N * g.batch >= (i64)128 * 64 * 1024 ? GEMM_128x64_G4 : GEMM_64x64_G4;
 }
+
+void launch_zgemm(const GemmArgs& g, hipStream_t s) { launch_zgemm_variant(g, gemm_default_variant(g), s); }
 
 void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
@@ -656,6 +675,13 @@ void launch_zgemm_simple(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
   hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
+                          int beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((i64)M * N)), dim3(256), 0, s, S, M, N, W, C, sCm, sCn, ar, ai,
+                     beta);
   HIPCHK(hipGetLastError());
 }
 

@@ -34,6 +34,34 @@ Acc prepare(cclr_ctx* c, const VecSet& in) {
   return a;
 }
 
+// Product with one of the Jacobian's large operators (B side of g: 0 right
+// ladder, 1 left ladder, 2 right ring, 3 left ring) in the arithmetic of the
+// transforms being applied.  Split-BF16 keeps a split copy of the operator,
+// made on first use; the trial-vector side is split per product.
+void op_gemm(cclr_ctx* c, const GemmArgs& g, int which) {
+  if (c->sigma_prec == CCLR_FP64) {
+    if (which < 2) tuned_gemm(c, g);
+    else run_gemm(c, g);
+    return;
+  }
+  if (c->sigma_prec == CCLR_FP32) {
+    launch_zgemm_lowp(g, CCLR_FP32, c->stream);
+    return;
+  }
+  REQUIRE(c->sigma_prec == CCLR_BF16X3 && g.batch == 1 && g.kchunk == 0, CCLR_EINVAL, "unsupported product form");
+  SplitMat& W = c->wsplit_m[which];
+  if (!W.p) {
+    c->wsplit[which].alloc(c, split_bytes(g.N, g.K));
+    W = launch_split_bf16(g.N, g.K, g.B, g.sBn, g.sBk, g.conjB, c->wsplit[which].p, c->stream);
+  }
+  REQUIRE(W.rows == g.N && W.K == g.K, CCLR_EINVAL, "split operator has another shape");
+  Arena::Mark mk = c->arena.mark();
+  void* ws = c->arena.get(split_bytes(g.M, g.K));
+  const SplitMat A = launch_split_bf16(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, ws, c->stream);
+  launch_cgemm_bf16x3(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
+  c->arena.reset(mk);
+}
+
 // Ring term  Z[(k,i,a),(j,b)] = sum_(m,e) R[(k,i,a),(m,e)] W[(m,e),(j,b)]  written into the
 // [k][i][a][j][b] accumulator (first writer: overwrites).  Right: W^mb_ej r^ae_im;
 // left: l^im_ae W^je_bm.
@@ -52,8 +80,7 @@ void ring(cclr_ctx* c, const VecSet& in, const Ten& Xai, bool right) {
   else { g.B = c->WL.c(); g.sBk = ov; g.sBn = 1; }
   g.C = Xai.p; g.sCm = ov; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-  if (c->sigma_prec == CCLR_FP64) run_gemm(c, g);
-  else launch_zgemm_lowp(g, c->sigma_prec, c->stream);
+  op_gemm(c, g, right ? 2 : 3);
   c->arena.reset(mk);
 }
 
@@ -70,10 +97,7 @@ void ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
   else { g.sBk = V2; g.sBn = 1; }
   g.C = out.d; g.sCb = 0; g.sCm = V2; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-  auto launch = [&]() {
-    if (c->sigma_prec == CCLR_FP64) launch_zgemm(g, c->stream);
-    else launch_zgemm_lowp(g, c->sigma_prec, c->stream);
-  };
+  auto launch = [&]() { op_gemm(c, g, right ? 0 : 1); };
   if (c->prof) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));

@@ -134,3 +134,114 @@ def test_backward_config1_directional(small):
             assert abs(an - fd) <= 1e-8 * abs(fd)
     finally:
         cc.cclr_destroy(ctx)
+
+
+# ---------------------------------------------------------------- Hamiltonian
+BLOCKS = ("oooo", "ooov", "oovv", "ovov", "ovvv", "vvvv")
+
+
+def sym_direction(o, v, rng):
+    """Random change of (f, <pq||rs>) that keeps the input symmetries: f
+    Hermitian, the integrals antisymmetric in each pair and Hermitian under
+    bra-ket exchange; returned as (df, {block: dV})."""
+    n = o + v
+    cr = lambda *s: rng.normal(size=s) + 1j * rng.normal(size=s)  # noqa: E731
+    D = cr(n, n, n, n)
+    D = D - D.transpose(1, 0, 2, 3)
+    D = D - D.transpose(0, 1, 3, 2)
+    D = 0.5 * (D + D.conj().transpose(2, 3, 0, 1))
+    sl = {"o": slice(0, o), "v": slice(o, None)}
+    dV = {k: D[sl[k[0]], sl[k[1]], sl[k[2]], sl[k[3]]].copy() for k in BLOCKS}
+    F = cr(n, n)
+    return 0.5 * (F + F.conj().T), dV
+
+
+def h_loss(H, t1, t2, Xs, zs, G, df, dV, h):
+    Hp = O.Hamiltonian(H.o, H.v, H.f + h * df, {k: H.blocks[k] + h * dV.get(k, 0.0) for k in BLOCKS})
+    return loss(O.CCLR(Hp, t1, t2), Xs, zs, G)
+
+
+def h_fd(H, t1, t2, Xs, zs, G, df, dV, h=2e-3):
+    """central differences at h and h/2, Richardson-extrapolated (error O(h^4))"""
+    d = [(h_loss(H, t1, t2, Xs, zs, G, df, dV, s) - h_loss(H, t1, t2, Xs, zs, G, df, dV, -s)) / (2 * s)
+         for s in (h, h / 2)]
+    return (4 * d[1] - d[0]) / 3
+
+
+def h_an(gf, gV, df, dV):
+    return float(np.real(np.sum(np.conj(gf) * df))) + sum(float(np.real(np.sum(np.conj(gV[k]) * x)))
+                                                         for k, x in dV.items())
+
+
+def run_backward_h(cc, ctx, H, Xs, zs, G):
+    o, v, n = H.o, H.v, H.o + H.v
+    gf = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    gV = [torch.empty(H.blocks[k].shape, dtype=torch.complex128, device="cuda") for k in BLOCKS]
+    rc, info = cc.cclr_response_backward(ctx, [dev(x) for x in Xs], [z.real for z in zs], [z.imag for z in zs],
+                                         G, df=gf, dV=gV)
+    assert rc == 0, info.as_dict()
+    return gf.cpu().numpy(), {k: g.cpu().numpy() for k, g in zip(BLOCKS, gV)}
+
+
+def test_backward_hamiltonian_matches_oracle_fd(small):
+    """d/d(f, V) of L along symmetry-keeping directions: each block alone, f
+    alone and all together, against Richardson-extrapolated central
+    differences of the oracle."""
+    cc, ctx, ref, Xs = small
+    import helpers
+    pb, inst, H, t1, t2 = helpers.config_problem(3, 6, 4)
+    zs = [0.3 + 0.02j, 0.0]
+    rng = np.random.default_rng(7)
+    G = rng.normal(size=(len(zs), 2, 2)) + 1j * rng.normal(size=(len(zs), 2, 2))
+    gf, gV = run_backward_h(cc, ctx, H, Xs, zs, G)
+    n = H.o + H.v
+    df, dV = sym_direction(H.o, H.v, rng)
+    cases = [("f", df, {})] + [(k, np.zeros((n, n)), {k: dV[k]}) for k in BLOCKS] + [("all", df, dV)]
+    for name, a, b in cases:
+        fd = h_fd(H, t1, t2, Xs, zs, G, a, b)
+        an = h_an(gf, gV, a, b)
+        print(f"Hamiltonian gradient along {name}: {an:.12e} vs oracle FD {fd:.12e}", flush=True)
+        assert abs(an - fd) <= 1e-7 * max(abs(fd), 1e-2)
+
+
+def test_backward_hamiltonian_is_symmetric(small):
+    """The returned gradient lies in the space of symmetric changes: f
+    Hermitian, blocks antisymmetric and Hermitian where the block allows."""
+    cc, ctx, ref, Xs = small
+    import helpers
+    pb, inst, H, t1, t2 = helpers.config_problem(3, 6, 4)
+    G = np.ones((1, 2, 2)) * (0.3 - 0.1j)
+    gf, gV = run_backward_h(cc, ctx, H, Xs, [0.2 + 0.01j], G)
+    sc = max(np.abs(gf).max(), max(np.abs(g).max() for g in gV.values()))
+    assert np.abs(gf - gf.conj().T).max() <= 1e-13 * sc
+    for k in ("oooo", "vvvv"):
+        g = gV[k]
+        assert np.abs(g + g.transpose(1, 0, 2, 3)).max() <= 1e-13 * sc
+        assert np.abs(g - g.conj().transpose(2, 3, 0, 1)).max() <= 1e-13 * sc
+    assert np.abs(gV["oovv"] + gV["oovv"].transpose(0, 1, 3, 2)).max() <= 1e-13 * sc
+    assert np.abs(gV["ovov"] - gV["ovov"].conj().transpose(2, 3, 0, 1)).max() <= 1e-13 * sc
+
+
+def test_backward_hamiltonian_config1(small):
+    """o=4, v=16: one symmetric direction against the oracle (central
+    differences, Richardson-extrapolated)."""
+    import paper_2307_14296_amd as cc
+    pb, inst, H, t1, t2 = config_problem(4, 16, 0)
+    op = cc.cclr_default_options()
+    op.tol = 1e-12
+    ctx = cc.cclr_create(4, 16, op)
+    try:
+        keep = [dev(H.f)] + [dev(H.blocks[k]) for k in s.CANONICAL_BLOCKS] + [dev(t1), dev(t2)]
+        cc.cclr_set_hamiltonian(ctx, *keep[:7])
+        cc.cclr_set_amplitudes(ctx, *keep[7:])
+        Xs = [s.dipole(pb, k).numpy() for k in range(2)]
+        zs = [0.1 + 0.005j]
+        G = np.array([[[1.0, 0.5j], [0.25, -0.5 + 0.1j]]])
+        gf, gV = run_backward_h(cc, ctx, H, Xs, zs, G)
+        df, dV = sym_direction(4, 16, np.random.default_rng(2))
+        fd = h_fd(H, t1, t2, Xs, zs, G, df, dV)
+        an = h_an(gf, gV, df, dV)
+        print(f"config1 Hamiltonian directional derivative: {an:.12e} vs FD {fd:.12e}", flush=True)
+        assert abs(an - fd) <= 1e-7 * abs(fd)
+    finally:
+        cc.cclr_destroy(ctx)
