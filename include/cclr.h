@@ -119,6 +119,18 @@ int cclr_jacobian_right(cclr_ctx* ctx, int nvec, const double* omega, const doub
 int cclr_jacobian_left(cclr_ctx* ctx, int nvec, const double* omega, const double* gamma,
                        const cclr_c64* l1, const cclr_c64* l2, cclr_c64* s1, cclr_c64* s2);
 
+/* Right transforms of several independent problems (contexts of any sizes
+ * o, v) in one call: for context i, s_i = (A_i - z_ik) r_ik for k < nvec[i],
+ * with the arrays of context i at omega[i], gamma[i], r1[i], r2[i], s1[i],
+ * s2[i] (layouts as for cclr_jacobian_right).  The ring and particle-
+ * particle ladder products of all contexts (SI, eq. sigma_double-ee) run
+ * as one persistent launch each, with the tile shape timed once per set of
+ * shapes.  The contexts must be distinct, share one hip_stream and use FP64
+ * transforms; errors are reported on ctx[0]. */
+int cclr_jacobian_right_multi(int nctx, cclr_ctx* const* ctx, const int* nvec, const double* const* omega,
+                              const double* const* gamma, const cclr_c64* const* r1, const cclr_c64* const* r2,
+                              cclr_c64* const* s1, cclr_c64* const* s2);
+
 /* Damped linear systems, one per right-hand side k < nrhs:
  *   side == CCLR_RIGHT:  (A - z_k) x_k = -b_k
  *   side == CCLR_LEFT :  x_k (A - z_k) = -b_k

@@ -25,7 +25,7 @@ CCLR_RIGHT, CCLR_LEFT = 0, 1
 
 EXPORTED = (
     "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_amplitudes",
-    "cclr_jacobian_right", "cclr_jacobian_left", "cclr_solve_damped", "cclr_solve_lambda", "cclr_get_lambda",
+    "cclr_jacobian_right", "cclr_jacobian_left", "cclr_jacobian_right_multi", "cclr_solve_damped", "cclr_solve_lambda", "cclr_get_lambda",
     "cclr_response_function", "cclr_response_backward", "cclr_last_error",
 )
 
@@ -68,6 +68,8 @@ def lib():
     L.cclr_set_amplitudes.argtypes = [P, P, P]
     L.cclr_jacobian_right.argtypes = [P, I, D, D, P, P, P, P]
     L.cclr_jacobian_left.argtypes = [P, I, D, D, P, P, P, P]
+    PP = ctypes.POINTER(P)
+    L.cclr_jacobian_right_multi.argtypes = [I, PP, ctypes.POINTER(I), PP, PP, PP, PP, PP, PP]
     L.cclr_solve_damped.argtypes = [P, I, I, D, D, P, P, P, P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_solve_lambda.argtypes = [P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_get_lambda.argtypes = [P, P, P]
@@ -157,6 +159,22 @@ def cclr_jacobian_left(ctx, omega, gamma, l1, l2, s1, s2):
     n = len(omega)
     return _check(ctx, lib().cclr_jacobian_left(ctx, n, _dbl(omega), _dbl(gamma), _ptr(l1, "l1"), _ptr(l2, "l2"),
                                                 _ptr(s1, "s1"), _ptr(s2, "s2")))
+
+
+def cclr_jacobian_right_multi(ctxs, omegas, gammas, r1s, r2s, s1s, s2s):
+    """Right transforms of several contexts in one call (lists, one entry per
+    context: frequency lists and GPU tensors as for cclr_jacobian_right)."""
+    n = len(ctxs)
+    arr = lambda xs: (ctypes.c_void_p * n)(*xs)  # noqa: E731
+    om = [_dbl(w) for w in omegas]
+    ga = [_dbl(g) for g in gammas]
+    rc = lib().cclr_jacobian_right_multi(
+        n, arr([c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs]),
+        (ctypes.c_int * n)(*[len(w) for w in omegas]),
+        arr([ctypes.cast(x, ctypes.c_void_p).value for x in om]), arr([ctypes.cast(x, ctypes.c_void_p).value for x in ga]),
+        arr([_ptr(x, "r1").value for x in r1s]), arr([_ptr(x, "r2").value for x in r2s]),
+        arr([_ptr(x, "s1").value for x in s1s]), arr([_ptr(x, "s2").value for x in s2s]))
+    return _check(ctxs[0], rc)
 
 
 def cclr_solve_damped(ctx, side, omega, gamma, b1, b2, x1, x2):

@@ -236,6 +236,117 @@ int cclr_jacobian_right(cclr_ctx* c, int nvec, const double* omega, const double
   return jacobian(c, CCLR_RIGHT, nvec, omega, gamma, r1, r2, s1, s2);
 }
 
+namespace {
+// One persistent launch for products of several contexts that share operand
+// layouts; the kernel variant is timed once per set of shapes and kept.
+void grouped_products(cclr_ctx* c0, std::vector<GemmArgs> g) {
+  g.erase(std::remove_if(g.begin(), g.end(), [](const GemmArgs& x) { return x.M <= 0 || x.N <= 0 || x.K <= 0; }),
+          g.end());
+  if (g.empty()) return;
+  const bool ak = g[0].sAk == 1, bn = g[0].sBn == 1;
+  for (const GemmArgs& x : g)
+    REQUIRE((x.sAk == 1) == ak && (x.sBn == 1) == bn && x.kchunk == 0, CCLR_EINVAL, "grouped products: layouts differ");
+  // longest reductions first: the tiles are dealt round-robin to the workgroups
+  std::stable_sort(g.begin(), g.end(), [](const GemmArgs& a, const GemmArgs& b) { return a.K > b.K; });
+  std::string key = ak ? "A1" : "A0";
+  key += bn ? "B1" : "B0";
+  for (const GemmArgs& x : g) key += ":" + std::to_string(x.M) + "x" + std::to_string(x.N) + "x" + std::to_string(x.K);
+  Arena::Mark mk = c0->arena.mark();
+  GemmArgs* pd = (GemmArgs*)c0->arena.get(sizeof(GemmArgs) * g.size());
+  int* td = (int*)c0->arena.get(sizeof(int) * (g.size() + 1));
+  HIPCHK(hipMemcpyAsync(pd, g.data(), sizeof(GemmArgs) * g.size(), hipMemcpyHostToDevice, c0->stream));
+  auto launch = [&](int variant) {
+    std::vector<int> ts(g.size() + 1, 0);
+    const int bm = gemm_tile_rows(variant);
+    for (size_t p = 0; p < g.size(); ++p) {
+      const i64 tiles = (i64)((g[p].M + bm - 1) / bm) * ((g[p].N + 63) / 64) * g[p].batch;
+      REQUIRE(ts[p] + tiles < (1ll << 31), CCLR_EINVAL, "grouped products: too many tiles");
+      ts[p + 1] = ts[p] + (int)tiles;
+    }
+    HIPCHK(hipMemcpyAsync(td, ts.data(), sizeof(int) * ts.size(), hipMemcpyHostToDevice, c0->stream));
+    launch_zgemm_group(pd, td, (int)g.size(), ts.back(), variant, ak, bn, c0->stream);
+  };
+  auto it = c0->group_choice.find(key);
+  if (it == c0->group_choice.end()) {
+    int best = GEMM_128x64_G4;
+    double best_ms = -1;
+    std::vector<double> ms_all;
+    for (int var : {GEMM_128x64_G3, GEMM_64x64_G3, GEMM_128x64_G4, GEMM_64x64_G4}) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventRecord(e0, c0->stream));
+      launch(var);
+      HIPCHK(hipEventRecord(e1, c0->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      ms_all.push_back(ms);
+      if (best_ms < 0 || ms < best_ms) best_ms = ms, best = var;
+    }
+    c0->group_choice[key] = best;
+    c0->gemm_tuning_log.push_back({"group " + key, ms_all});
+    it = c0->group_choice.find(key);
+  }
+  launch(it->second);
+  c0->arena.reset(mk);
+}
+}  // namespace
+
+int cclr_jacobian_right_multi(int nctx, cclr_ctx* const* ctx, const int* nvec, const double* const* omega,
+                              const double* const* gamma, const cclr_c64* const* r1, const cclr_c64* const* r2,
+                              cclr_c64* const* s1, cclr_c64* const* s2) {
+  if (nctx < 1 || !ctx || !ctx[0]) return CCLR_EINVAL;
+  cclr_ctx* c0 = ctx[0];
+  std::vector<Arena::Mark> marks(nctx);
+  std::vector<bool> marked(nctx, false);
+  const int rc = guarded(c0, [&]() -> int {
+    REQUIRE(nvec && omega && gamma && r1 && r2 && s1 && s2, CCLR_EINVAL, "null argument array");
+    for (int i = 0; i < nctx; ++i) {
+      REQUIRE(ctx[i], CCLR_EINVAL, "null context");
+      for (int j = 0; j < i; ++j) REQUIRE(ctx[j] != ctx[i], CCLR_EINVAL, "a context appears twice");
+      require_t(ctx[i]);
+      REQUIRE(ctx[i]->stream == c0->stream, CCLR_EINVAL, "contexts must share one stream");
+      REQUIRE(ctx[i]->sigma_prec == CCLR_FP64, CCLR_EINVAL, "grouped transforms are FP64");
+      check_freqs(nvec[i], omega[i], gamma[i]);
+    }
+    std::vector<VecSet> in(nctx), out(nctx);
+    std::vector<cplx*> zd(nctx, nullptr);
+    std::vector<SigmaWork> w(nctx);
+    std::vector<GemmArgs> rings, ladders;
+    for (int i = 0; i < nctx; ++i) {
+      cclr_ctx* c = ctx[i];
+      if (nvec[i] == 0) continue;
+      marks[i] = c->arena.mark();
+      marked[i] = true;
+      in[i] = packed_buf(c, nvec[i]);
+      out[i] = packed_buf(c, nvec[i]);
+      pack_in(c, nvec[i], r1[i], r2[i], in[i], "r");
+      std::vector<cplx> z(nvec[i]);
+      for (int k = 0; k < nvec[i]; ++k) z[k] = cx(omega[i][k], gamma[i][k]);
+      zd[i] = (cplx*)c->arena.get(sizeof(cplx) * nvec[i]);
+      HIPCHK(hipMemcpyAsync(zd[i], z.data(), sizeof(cplx) * nvec[i], hipMemcpyHostToDevice, c->stream));
+      w[i] = sigma_right_begin(c, in[i], out[i]);
+      rings.push_back(w[i].ring);
+      ladders.push_back(w[i].ladder);
+    }
+    grouped_products(c0, rings);
+    grouped_products(c0, ladders);
+    for (int i = 0; i < nctx; ++i) {
+      if (nvec[i] == 0) continue;
+      sigma_finish(ctx[i], w[i], in[i], out[i], zd[i]);
+      unpack_out(ctx[i], out[i], s1[i], s2[i], "output");
+    }
+    HIPCHK(hipStreamSynchronize(c0->stream));
+    return CCLR_OK;
+  });
+  for (int i = 0; i < nctx; ++i)
+    if (marked[i]) ctx[i]->arena.reset(marks[i]);
+  return rc;
+}
+
 int cclr_jacobian_left(cclr_ctx* c, int nvec, const double* omega, const double* gamma, const cclr_c64* l1,
                        const cclr_c64* l2, cclr_c64* s1, cclr_c64* s2) {
   if (!c) return CCLR_EINVAL;

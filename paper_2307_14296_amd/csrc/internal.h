@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <algorithm>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -108,6 +109,13 @@ void launch_zgemm(const GemmArgs& g, hipStream_t s);
 enum { GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4, GEMM_NVAR = 5 };
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);
 int gemm_default_variant(const GemmArgs& g);
+// Several products (same operand layouts: ak = unit-stride k in A, bn = unit-
+// stride n in B; batch 1 or batched, no K splitting) in one persistent launch.
+// probs / tstart are DEVICE arrays: problem p owns tiles [tstart[p], tstart[p+1])
+// of the variant's tile shape (rows gemm_tile_rows(variant), 64 columns).
+void launch_zgemm_group(const GemmArgs* probs, const int* tstart, int nprob, int total, int variant, bool ak, bool bn,
+                        hipStream_t s);
+int gemm_tile_rows(int variant);
 // the same product with FP32 (prec = CCLR_FP32) or split-BF16 (CCLR_BF16X3)
 // MFMA arithmetic and FP32 accumulation; operands and C stay complex128 in memory
 void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s);
@@ -195,6 +203,8 @@ struct cclr_ctx {
   std::map<std::tuple<int, int, int, int, int>, int> gemm_choice;
   std::vector<std::pair<std::string, std::vector<double>>> gemm_tuning_log;
   bool autotune = true;
+  // kernel variant of grouped multi-context launches, per set of product shapes
+  std::map<std::string, int> group_choice;
   // optional timing of the particle-particle ladder GEMM launches
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -226,6 +236,20 @@ inline cplx cx(double r, double i = 0.0) { return make_double2(r, i); }
 void build_intermediates(cclr_ctx* c);
 // sigma for nvec packed vectors in `in` -> `out` (packed); z per vector (may be null)
 void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_dev);
+// The right sigma in two halves around its two large products, so that the
+// products of several contexts can be launched together: begin runs every
+// other term and returns the ring and ladder products (not yet launched);
+// finish packs the result once both have run.
+struct SigmaAcc {
+  Ten X0, Xa, Xi, Xai, S1, R1, R2;
+};
+struct SigmaWork {
+  Arena::Mark mk;
+  SigmaAcc a;
+  GemmArgs ring, ladder;
+};
+SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out);
+void sigma_finish(cclr_ctx* c, SigmaWork& w, const VecSet& in, const VecSet& out, const cplx* z_dev);
 void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_dev);
 
 // ------------------------------------------------- solver and response pieces

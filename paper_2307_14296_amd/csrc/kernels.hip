@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int S, int M, int N, cons
 // sub-tile.
 // --------------------------------------------------------------------------
 template <int BM, int BN, bool AK, bool BNF, bool G3>
-__global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
+__device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, const int n0, const i64 bz) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -160,8 +160,6 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
   __shared__ double sA[2][NP][BK][BM + 1];  // Ar, Ai (, Ar + Ai)
   __shared__ double sB[2][NP][BK][BN + 1];  // Br, Bi - Br (, Br + Bi)  |  Br, Bi
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const i64 bz = blockIdx.z;
   int kbeg = 0, kend = g.K;
   if (g.kchunk > 0) {
     kbeg = (int)bz * g.kchunk;
@@ -303,6 +301,29 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
           *dst = y;
         }
       }
+}
+
+template <int BM, int BN, bool AK, bool BNF, bool G3>
+__global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
+  zgemm_tile<BM, BN, AK, BNF, G3>(g, blockIdx.x * BM, blockIdx.y * BN, blockIdx.z);
+}
+
+// Grouped persistent form: one launch walks the tiles of several products
+// (problem p owns tiles [tstart[p], tstart[p+1])), each workgroup taking
+// every gridDim.x-th tile.  The LDS of a tile is released by the barrier
+// that ends its last K step, so consecutive tiles reuse it safely.
+template <int BM, int BN, bool AK, bool BNF, bool G3>
+__global__ __launch_bounds__(256) void k_zgemm_group(const GemmArgs* __restrict__ probs, const int* __restrict__ tstart,
+                                                     int nprob, int total) {
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int p = 0;
+    while (p + 1 < nprob && t >= tstart[p + 1]) ++p;
+    const GemmArgs g = probs[p];
+    const int lt = t - tstart[p];
+    const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    const int mi = lt % tm, rest = lt / tm;
+    zgemm_tile<BM, BN, AK, BNF, G3>(g, mi * BM, (rest % tn) * BN, rest / tn);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -648,6 +669,34 @@ void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
       dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
       hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
     }
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <int BM, int BN, bool G3>
+static void launch_group(const GemmArgs* probs, const int* tstart, int nprob, int total, bool ak, bool bn,
+                         hipStream_t s) {
+  // persistent grid: as many workgroups as fit on the 256 CUs at once (LDS bound)
+  constexpr int NP = G3 ? 3 : 2;
+  constexpr int lds = 2 * NP * 16 * (BM + 1 + BN + 1) * 8;
+  const int per_cu = (160 * 1024) / lds;
+  const int grid = std::min(total, 256 * std::max(1, per_cu));
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_group<BM, BN, true, true, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_group<BM, BN, true, false, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_group<BM, BN, false, true, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+  else hipLaunchKernelGGL((k_zgemm_group<BM, BN, false, false, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+}
+
+int gemm_tile_rows(int variant) { return (variant == GEMM_128x64_G3 || variant == GEMM_128x64_G4) ? 128 : 64; }
+
+void launch_zgemm_group(const GemmArgs* probs, const int* tstart, int nprob, int total, int variant, bool ak, bool bn,
+                        hipStream_t s) {
+  if (total <= 0) return;
+  switch (variant) {
+    case GEMM_128x64_G3: launch_group<128, 64, true>(probs, tstart, nprob, total, ak, bn, s); break;
+    case GEMM_64x64_G3: launch_group<64, 64, true>(probs, tstart, nprob, total, ak, bn, s); break;
+    case GEMM_128x64_G4: launch_group<128, 64, false>(probs, tstart, nprob, total, ak, bn, s); break;
+    default: launch_group<64, 64, false>(probs, tstart, nprob, total, ak, bn, s); break;
   }
   HIPCHK(hipGetLastError());
 }

@@ -14,13 +14,10 @@
 #include "internal.h"
 
 namespace {
-struct Acc {
-  Ten X0, Xa, Xi, Xai, S1, R1, R2;
-};
 
-Acc prepare(cclr_ctx* c, const VecSet& in) {
+SigmaAcc prepare(cclr_ctx* c, const VecSet& in) {
   const i64 o = c->o, v = c->v, k = in.n;
-  Acc a;
+  SigmaAcc a;
   a.R1 = ten(in.s, {k, o, v});
   a.R2 = tmp(c, {k, o, o, v, v});
   launch_unpack((int)k, (int)o, (int)v, in.s, in.d, nullptr, a.R2.p, c->stream);
@@ -64,10 +61,10 @@ void op_gemm(cclr_ctx* c, const GemmArgs& g, int which) {
 
 // Ring term  Z[(k,i,a),(j,b)] = sum_(m,e) R[(k,i,a),(m,e)] W[(m,e),(j,b)]  written into the
 // [k][i][a][j][b] accumulator (first writer: overwrites).  Right: W^mb_ej r^ae_im;
-// left: l^im_ae W^je_bm.
-void ring(cclr_ctx* c, const VecSet& in, const Ten& Xai, bool right) {
+// left: l^im_ae W^je_bm.  Unpacks the vectors into the ring layout (arena) and
+// returns the product; the caller launches it.
+GemmArgs ring_args(cclr_ctx* c, const VecSet& in, const Ten& Xai, bool right) {
   const i64 o = c->o, v = c->v, ov = o * v, nv = in.n;
-  Arena::Mark mk = c->arena.mark();
   cplx* rr = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nv * ov * ov));
   launch_unpack_ring((int)nv, (int)o, (int)v, in.d, rr, c->stream);
   GemmArgs g{};
@@ -80,11 +77,11 @@ void ring(cclr_ctx* c, const VecSet& in, const Ten& Xai, bool right) {
   else { g.B = c->WL.c(); g.sBk = ov; g.sBn = 1; }
   g.C = Xai.p; g.sCm = ov; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-  op_gemm(c, g, right ? 2 : 3);
-  c->arena.reset(mk);
+  return g;
 }
 
-void ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
+// Particle-particle ladder on packed pairs (overwrites the packed doubles of out).
+GemmArgs ladder_args(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
   const i64 V2 = c->V2(), O2 = c->O2();
   GemmArgs g{};
   g.M = (int)(O2 * in.n);
@@ -97,27 +94,36 @@ void ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
   else { g.sBk = V2; g.sBn = 1; }
   g.C = out.d; g.sCb = 0; g.sCm = V2; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-  auto launch = [&]() { op_gemm(c, g, right ? 0 : 1); };
-  if (c->prof) {
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, c->stream));
-    launch();
-    HIPCHK(hipEventRecord(e1, c->stream));
-    c->prof_events.push_back({e0, e1});
-    c->prof_flops.push_back(8.0 * (double)g.M * (double)g.N * (double)g.K);
-  } else {
-    launch();
-  }
+  return g;
 }
+
+// launch with optional event timing (the debug profile hook)
+template <class F>
+void timed(cclr_ctx* c, double flops, F&& launch) {
+  if (!c->prof) {
+    launch();
+    return;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, c->stream));
+  launch();
+  HIPCHK(hipEventRecord(e1, c->stream));
+  c->prof_events.push_back({e0, e1});
+  c->prof_flops.push_back(flops);
+}
+
+double gemm_flops(const GemmArgs& g) { return 8.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch; }
 }  // namespace
 
-void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z) {
+SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   const i64 o = c->o, v = c->v, nv = in.n;
-  Arena::Mark mk = c->arena.mark();
+  SigmaWork w;
+  w.mk = c->arena.mark();
   const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
-  Acc a = prepare(c, in);
+  w.a = prepare(c, in);
+  SigmaAcc& a = w.a;
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
@@ -134,38 +140,48 @@ void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z
   contract(c, mone, Wovoo, "mbij", a.R1, "kma", a.Xa, "kijab");
   contract(c, one, Wvvvo, "abej", a.R1, "kie", a.Xi, "kijab");
   {
-    Ten Y = tmp(c, {nv, v, v});  // W^bm_fe r^e_m
+    // P(ab) [W^bm_fe r^e_m t^af_ij - 1/2 V^nm_fe r^ea_mn t^fb_ij] = P(ab) t^af_ij Y_bf with
+    // Y_bf = W^bm_fe r^e_m - 1/2 V^nm_fe r^eb_mn, and likewise
+    // -P(ij) [W^nm_je r^e_m t^ab_in + 1/2 V^nm_fe r^fe_im t^ba_jn] = -P(ij) t^ab_in Z_nj with
+    // Z_nj = W^nm_je r^e_m + 1/2 V^nm_fe r^fe_jm  (antisymmetry of t relabels the second terms)
+    Ten Voovv = Vblk(c, "oovv");
+    Ten Y = tmp(c, {nv, v, v});
     contract(c, one, Wvovv, "bmfe", a.R1, "kme", Y, "kbf", false);
+    contract(c, mhalf, Voovv, "nmfe", a.R2, "kmneb", Y, "kbf");
     contract(c, one, t2, "ijaf", Y, "kbf", a.Xa, "kijab");
-    Ten Z = tmp(c, {nv, o, o});  // W^nm_je r^e_m
+    Ten Z = tmp(c, {nv, o, o});
     contract(c, one, Wooov, "nmje", a.R1, "kme", Z, "knj", false);
+    contract(c, half, Voovv, "nmfe", a.R2, "kjmfe", Z, "knj");
     contract(c, mone, t2, "inab", Z, "knj", a.Xi, "kijab");
   }
   contract(c, one, Fvv, "be", a.R2, "kijae", a.Xa, "kijab");
   contract(c, mone, Foo, "mj", a.R2, "kimab", a.Xi, "kijab");
   contract(c, half, Woooo, "mnij", a.R2, "kmnab", a.X0, "kijab");
-  ring(c, in, a.Xai, true);
-  {
-    Ten Voovv = Vblk(c, "oovv");
-    Ten Q = tmp(c, {nv, v, v});  // V^nm_fe r^ea_mn
-    contract(c, one, Voovv, "nmfe", a.R2, "kmnea", Q, "kfa", false);
-    contract(c, mhalf, t2, "ijfb", Q, "kfa", a.Xa, "kijab");
-    Ten P = tmp(c, {nv, o, o});  // V^nm_fe r^fe_im
-    contract(c, one, Voovv, "nmfe", a.R2, "kimfe", P, "kni", false);
-    contract(c, mhalf, t2, "jnba", P, "kni", a.Xi, "kijab");
-  }
-  ladder(c, in, out, true);
+  w.ring = ring_args(c, in, a.Xai, true);
+  w.ladder = ladder_args(c, in, out, true);
+  return w;
+}
+
+void sigma_finish(cclr_ctx* c, SigmaWork& w, const VecSet& in, const VecSet& out, const cplx* z) {
+  const i64 o = c->o, v = c->v, nv = in.n;
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
-  launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
-                    c->stream, true);
-  c->arena.reset(mk);
+  launch_pack_sigma((int)nv, (int)o, (int)v, w.a.X0.p, w.a.Xa.p, w.a.Xi.p, w.a.Xai.p, w.a.S1.p, out.s, out.d, z, in.s,
+                    in.d, c->stream, true);
+  c->arena.reset(w.mk);
+}
+
+void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z) {
+  SigmaWork w = sigma_right_begin(c, in, out);
+  op_gemm(c, w.ring, 2);
+  timed(c, gemm_flops(w.ladder), [&]() { op_gemm(c, w.ladder, 0); });
+  sigma_finish(c, w, in, out, z);
 }
 
 void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z) {
   const i64 o = c->o, v = c->v, nv = in.n;
   Arena::Mark mk = c->arena.mark();
   const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
-  Acc a = prepare(c, in);
+  SigmaAcc a = prepare(c, in);
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
@@ -188,13 +204,16 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   contract(c, one, a.R2, "kijae", Fvv, "eb", a.Xa, "kijab");
   contract(c, mone, a.R2, "kimab", Foo, "jm", a.Xi, "kijab");
   contract(c, half, a.R2, "kmnab", Woooo, "ijmn", a.X0, "kijab");
-  ring(c, in, a.Xai, false);
+  op_gemm(c, ring_args(c, in, a.Xai, false), 3);
   contract(c, one, Voovv, "ijae", Gvv, "keb", a.Xa, "kijab");
   contract(c, mone, a.R1, "kma", Wooov, "ijmb", a.Xa, "kijab");
   contract(c, mone, Voovv, "imab", Goo, "kjm", a.Xi, "kijab");
   contract(c, one, a.R1, "kie", Wvovv, "ejab", a.Xi, "kijab");
   contract(c, one, a.R1, "kia", Fov, "jb", a.Xai, "kijab");
-  ladder(c, in, out, false);
+  {
+    const GemmArgs g = ladder_args(c, in, out, false);
+    timed(c, gemm_flops(g), [&]() { op_gemm(c, g, 1); });
+  }
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
                     c->stream, true);
