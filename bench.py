@@ -94,6 +94,65 @@ def cpu_baseline(seconds_target=15.0):
     }
 
 
+def batching_bench(cc, dev, nvec=3, reps=3):
+    """Four problems of uneven size, (o, v) = (8, 60), (12, 90), (16, 120),
+    (20, 150), nvec right transforms each: one cclr_jacobian_right_multi call
+    (grouped persistent ring and ladder launches) against one
+    cclr_jacobian_right call per problem."""
+    import torch
+    from gen import synth as s
+    shapes = [(8, 60), (12, 90), (16, 120), (20, 150)]
+    ctxs, args = [], []
+    try:
+        for k, (o, v) in enumerate(shapes):
+            pb, f, V, t1, t2, X = make_inputs(o, v, 20 + k, dev)
+            c = cc.cclr_create(o, v)
+            ctxs.append(c)
+            cc.cclr_set_hamiltonian(c, f, *[V[b] for b in s.CANONICAL_BLOCKS])
+            cc.cclr_set_amplitudes(c, t1, t2)
+            del V
+            r1 = torch.zeros((nvec, o, v), dtype=torch.complex128, device=dev)
+            r2 = torch.zeros((nvec, o, o, v, v), dtype=torch.complex128, device=dev)
+            for j in range(nvec):
+                r1[j], r2[j] = s.excitation_vector(pb, j, dev)
+            args.append((r1, r2, torch.empty_like(r1), torch.empty_like(r2), [0.0774] * nvec, [0.005] * nvec))
+        torch.cuda.empty_cache()
+
+        def seq():
+            for c, (r1, r2, s1, s2, om, ga) in zip(ctxs, args):
+                cc.cclr_jacobian_right(c, om, ga, r1, r2, s1, s2)
+
+        def grouped():
+            cc.cclr_jacobian_right_multi(ctxs, [a[4] for a in args], [a[5] for a in args], [a[0] for a in args],
+                                         [a[1] for a in args], [a[2] for a in args], [a[3] for a in args])
+        res = {}
+        for name, fn in (("one_call_per_problem", seq), ("grouped_persistent", grouped)):
+            fn()  # warm-up (autotuning)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            res[name] = {"ms": round(1e3 * dt, 2), "transforms_per_s": round(len(shapes) * nvec / dt, 2)}
+            log(f"batching: {name} {1e3 * dt:.1f} ms per round of {len(shapes) * nvec} transforms")
+        # agreement of the two paths
+        outs = [(a[2].clone(), a[3].clone()) for a in args]
+        seq()
+        torch.cuda.synchronize()
+        diff = max(float(((a[2] - o1).abs().max() / o1.abs().max()).item()) for a, (o1, o2) in zip(args, outs))
+        work = sum(sigma_flops(o, v)["total"] for o, v in shapes) * nvec
+        res.update({"problems": [list(x) for x in shapes], "vectors_per_problem": nvec,
+                    "speedup_grouped": round(res["one_call_per_problem"]["ms"] / res["grouped_persistent"]["ms"], 3),
+                    "tflops_grouped": round(work / (res["grouped_persistent"]["ms"] * 1e-3) / 1e12, 2),
+                    "max_rel_diff_singles": diff})
+        return res
+    finally:
+        for c in ctxs:
+            cc.cclr_destroy(c)
+        torch.cuda.empty_cache()
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -117,6 +176,8 @@ def main():
                     help="run a plain device copy of this many GiB first (reference for HBM byte counters)")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the mixed-precision runs (reduced-precision products + FP64 refinement)")
+    ap.add_argument("--no-batching", dest="batching", action="store_false",
+                    help="skip the uneven multi-problem transform comparison")
     ap.add_argument("--mixed-precs", default="fp32,bf16x3",
                     help="comma list of reduced precisions to run after the FP64 run")
     args = ap.parse_args()
@@ -284,6 +345,8 @@ def main():
             mx["ladder_tflops_fp64_equivalent"] = round(mres["fl"] / (mres["ms"] * 1e-3) / 1e12, 3)
             mx["ladder_avg_launch_ms"] = round(mres["ms"] / max(1, mres["nl"]), 4)
         line["mixed_precision"][p] = mx
+    if args.batching and args.mode == "response":
+        line["batching"] = batching_bench(cc, dev)
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline()

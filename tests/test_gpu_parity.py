@@ -176,5 +176,40 @@ def test_error_paths(gpu):
         with pytest.raises(cc.CclrError) as e:
             cc.cclr_set_hamiltonian(ctx, *args)
         assert e.value.code == cc.CCLR_EINVAL
+        # a solve stopped by maxiter reports CCLR_ENOTCONV with the result written
+        args = [dev(H.f)] + [dev(H.blocks[k]) for k in s.CANONICAL_BLOCKS]
+        cc.cclr_set_hamiltonian(ctx, *args)
+        cc.cclr_set_amplitudes(ctx, dev(t1), dev(t2))
+        x1, x2 = torch.empty_like(r), torch.empty_like(r2)
+        b1 = dev(np.ones((1, 2, 3)))
+        b2 = dev(np.zeros((1, 2, 2, 3, 3)))
+        b2[0, 1, 0, 2, 1] = 1.0
+        b2[0, 0, 1, 2, 1] = -1.0
+        b2[0, 1, 0, 1, 2] = -1.0
+        b2[0, 0, 1, 1, 2] = 1.0
+        rc, info = cc.cclr_solve_damped(ctx, cc.CCLR_RIGHT, [0.1], [0.01], b1, b2, x1, x2)
+        assert rc == cc.CCLR_OK
+    finally:
+        cc.cclr_destroy(ctx)
+    op = cc.cclr_default_options()
+    op.maxiter = 1
+    op.tol = 1e-14
+    ctx = cc.cclr_create(2, 3, op)
+    try:
+        cc.cclr_set_hamiltonian(ctx, *args)
+        cc.cclr_set_amplitudes(ctx, dev(t1), dev(t2))
+        rc, info = cc.cclr_solve_damped(ctx, cc.CCLR_RIGHT, [0.1], [0.01], b1, b2, x1, x2)
+        assert rc == cc.CCLR_ENOTCONV and info.converged == 0
+        assert np.isfinite(x1.cpu().numpy()).all()
+    finally:
+        cc.cclr_destroy(ctx)
+    # a device-memory cap below what the context needs
+    op = cc.cclr_default_options()
+    op.device_mem_cap = 4096
+    ctx = cc.cclr_create(2, 3, op)
+    try:
+        with pytest.raises(cc.CclrError) as e:
+            cc.cclr_set_hamiltonian(ctx, *args)
+        assert e.value.code == cc.CCLR_ENOMEM
     finally:
         cc.cclr_destroy(ctx)
