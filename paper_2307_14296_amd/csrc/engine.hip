@@ -272,6 +272,96 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
   };
   chk(Lb), chk(Lm), chk(Ln), chk(Lk);
 
+  // Without shared batch labels, output labels of one operand that break the
+  // nesting of the M (or N) group can become a batch index of their own (the
+  // other operand gets stride 0), which avoids copying large operands.  A
+  // small operand may be copied into the order the plan wants.
+  if (Lb.empty()) {
+    const i64 small = (i64)1 << 22;
+    struct Plan {
+      std::string sm, rm, sn, rn;
+      bool ca = false, cb = false;
+      double score = -1;
+    } best;
+    const int nm = (int)Lm.size(), nn = (int)Ln.size();
+    for (int ca = 0; ca < 2; ++ca)
+      for (int cbq = 0; cbq < 2; ++cbq) {
+        if ((ca && A.size() > small) || (cbq && B.size() > small)) continue;
+        if (best.score > 0 && (ca + cbq) > (int)best.ca + (int)best.cb) continue;  // fewer copies first
+        for (int mm = 0; mm < (1 << nm); ++mm)
+          for (int mn = 0; mn < (1 << nn); ++mn) {
+            std::string sm, rm, sn, rn;
+            for (int q = 0; q < nm; ++q) ((mm >> q) & 1 ? sm : rm) += Lm[q];
+            for (int q = 0; q < nn; ++q) ((mn >> q) & 1 ? sn : rn) += Ln[q];
+            const bool okA = ca || (merge(A, la, Lk).ok && merge(A, la, rm).ok && merge(A, la, sm).ok);
+            const bool okB = cbq || (merge(B, lb, Lk).ok && merge(B, lb, rn).ok && merge(B, lb, sn).ok);
+            if (!okA || !okB) continue;
+            if (!(merge(C, lc, rm).ok && merge(C, lc, rn).ok && merge(C, lc, sm).ok && merge(C, lc, sn).ok)) continue;
+            if (mm == 0 && mn == 0 && !ca && !cbq) continue;  // the plain plan below handles it
+            const i64 nbat = merge(C, lc, sm).size * merge(C, lc, sn).size;
+            if (nbat >= 65536) continue;
+            const double score = (double)merge(C, lc, rm).size * (double)merge(C, lc, rn).size;
+            const bool fewer = (ca + cbq) < (int)best.ca + (int)best.cb;
+            if (best.score < 0 || fewer || score > best.score) best = Plan{sm, rm, sn, rn, ca != 0, cbq != 0, score};
+          }
+      }
+    const bool okA0 = merge(A, la, Lk).ok && merge(A, la, Lm).ok, okB0 = merge(B, lb, Lk).ok && merge(B, lb, Ln).ok,
+               okC0 = merge(C, lc, Lm).ok && merge(C, lc, Ln).ok;
+    // bytes the plain path would copy
+    const i64 copied = (okA0 ? 0 : A.size()) + (okB0 ? 0 : B.size()) + (okC0 ? 0 : 2 * C.size());
+    if (!(okA0 && okB0 && okC0) && copied > small && best.score > 0) {
+      Arena::Mark mk = c->arena.mark();
+      Ten Aw = A, Bw = B;
+      std::string law = la, lbw = lb;
+      auto relayout = [&](const Ten& X, const char* lx, const std::string& order, Ten& out, std::string& lout) {
+        i64 n = 1;
+        for (char ch : order) n *= labsize(X, lx, ch);
+        Ten T;
+        T.p = (cplx*)c->arena.get(sizeof(cplx) * (size_t)std::max<i64>(n, 1));
+        T.nd = (int)order.size();
+        i64 st = 1;
+        for (int d = T.nd - 1; d >= 0; --d) {
+          T.dim[d] = labsize(X, lx, order[d]);
+          T.st[d] = st;
+          st *= T.dim[d];
+        }
+        tcopy(c, T, order.c_str(), X, lx, cx(1.0), false);
+        out = T;
+        lout = order;
+      };
+      if (best.ca) relayout(A, la, best.sm + best.rm + Lk, Aw, law);
+      if (best.cb) relayout(B, lb, best.sn + Lk + best.rn, Bw, lbw);
+      const Group Am2 = merge(Aw, law.c_str(), best.rm), Ak2 = merge(Aw, law.c_str(), Lk),
+                  As = merge(Aw, law.c_str(), best.sm);
+      const Group Bn2 = merge(Bw, lbw.c_str(), best.rn), Bk2 = merge(Bw, lbw.c_str(), Lk),
+                  Bs = merge(Bw, lbw.c_str(), best.sn);
+      const Group Cm2 = merge(C, lc, best.rm), Cn2 = merge(C, lc, best.rn), Cs1 = merge(C, lc, best.sn),
+                  Cs2 = merge(C, lc, best.sm);
+      // a copied operand already carries its scale and conjugation
+      const double sr = Aw.sr * Bw.sr - Aw.si * Bw.si, si = Aw.sr * Bw.si + Aw.si * Bw.sr;
+      GemmArgs g{};
+      g.M = (int)Am2.size;
+      g.N = (int)Bn2.size;
+      g.K = (int)Ak2.size;
+      g.nb2 = (int)Cs2.size;
+      g.batch = (int)(Cs1.size * Cs2.size);
+      g.A = Aw.p; g.sAb = 0; g.sAb2 = As.stride; g.sAm = Am2.stride; g.sAk = Ak2.stride; g.conjA = Aw.conj;
+      g.B = Bw.p; g.sBb = Bs.stride; g.sBb2 = 0; g.sBk = Bk2.stride; g.sBn = Bn2.stride; g.conjB = Bw.conj;
+      g.C = C.p; g.sCb = Cs1.stride; g.sCb2 = Cs2.stride; g.sCm = Cm2.stride; g.sCn = Cn2.stride;
+      g.ar = alpha.x * sr - alpha.y * si;
+      g.ai = alpha.x * si + alpha.y * sr;
+      g.beta = accumulate ? 1 : 0;
+      REQUIRE(Am2.size < (1ll << 31) && Bn2.size < (1ll << 31) && Ak2.size < (1ll << 31), CCLR_EINVAL,
+              "contract: dimension too large for one GEMM");
+      if (g.K == 0) {
+        if (!accumulate) tzero(c, C);
+      } else {
+        run_gemm(c, g);
+      }
+      c->arena.reset(mk);
+      return;
+    }
+  }
   Arena::Mark mk = c->arena.mark();
   // ---- A as [b][m][k]
   Group Ab = merge(A, la, Lb), Am = merge(A, la, Lm), Ak = merge(A, la, Lk);
@@ -372,28 +462,31 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
 void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   const i64 tiles = (i64)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
-  if (g.batch == 1 && tiles < 512 && g.K >= 512) {
+  if (g.nb2 <= 1 && tiles < 512 && g.K >= 512) {
     i64 S = std::min<i64>((1024 + tiles - 1) / tiles, g.K / 256);
     S = std::max<i64>(S, 2);
     i64 kc = (g.K + S - 1) / S;
     kc = (kc + 15) / 16 * 16;
     S = (g.K + kc - 1) / kc;
-    Arena::Mark mk = c->arena.mark();
-    cplx* W = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(S * g.M * (i64)g.N));
-    GemmArgs h = g;
-    h.kchunk = (int)kc;
-    h.batch = (int)S;
-    h.C = W;
-    h.sCb = (i64)g.M * g.N;
-    h.sCm = g.N;
-    h.sCn = 1;
-    h.ar = 1.0;
-    h.ai = 0.0;
-    h.beta = 0;
-    launch_zgemm(h, c->stream);
-    launch_splitk_reduce((int)S, g.M, g.N, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
-    c->arena.reset(mk);
-    return;
+    if ((i64)g.batch * S < 65536) {
+      Arena::Mark mk = c->arena.mark();
+      cplx* W = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(g.batch * S * g.M * (i64)g.N));
+      GemmArgs h = g;
+      h.kchunk = (int)kc;
+      h.batch = (int)(g.batch * S);
+      h.nb2 = 0;
+      h.C = W;
+      h.sCb = (i64)g.M * g.N;
+      h.sCm = g.N;
+      h.sCn = 1;
+      h.ar = 1.0;
+      h.ai = 0.0;
+      h.beta = 0;
+      launch_zgemm(h, c->stream);
+      launch_splitk_reduce(g.batch, (int)S, g.M, g.N, W, g.C, g.sCb, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
+      c->arena.reset(mk);
+      return;
+    }
   }
   tuned_gemm(c, g);
 }
@@ -409,14 +502,16 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
     launch_zgemm(g, c->stream);
     return;
   }
-  const auto key = std::make_tuple(g.M, g.N, g.K, g.batch, (g.sAk == 1 ? 1 : 0) + (g.sBn == 1 ? 2 : 0));
+  const auto key = std::make_tuple(g.M, g.N, g.K, g.batch,
+                                   (g.sAk == 1 ? 1 : 0) + (g.sBn == 1 ? 2 : 0) + (g.nb2 > 1 ? 4 : 0));
   auto it = c->gemm_choice.find(key);
   if (it != c->gemm_choice.end()) {
     launch_zgemm_variant(g, it->second, c->stream);
     return;
   }
   // scratch output covering the same index range
-  const i64 extent = (i64)(g.M - 1) * g.sCm + (i64)(g.N - 1) * g.sCn + (i64)(g.batch - 1) * g.sCb + 1;
+  const i64 nb2 = g.nb2 > 1 ? g.nb2 : 1, nb1 = g.batch / nb2;
+  const i64 extent = (i64)(g.M - 1) * g.sCm + (i64)(g.N - 1) * g.sCn + (nb1 - 1) * g.sCb + (nb2 - 1) * g.sCb2 + 1;
   Arena::Mark mk = c->arena.mark();
   GemmArgs h = g;
   h.C = (cplx*)c->arena.get(sizeof(cplx) * (size_t)extent);

@@ -102,7 +102,12 @@ struct GemmArgs {
   cplx* C; i64 sCb, sCm, sCn;
   double ar, ai;   // alpha
   int beta;        // 0: C = alpha*AB, 1: C += alpha*AB
-  int kchunk;      // > 0: blockIdx.z is a K split covering [z*kchunk, (z+1)*kchunk) (batch must be 1)
+  int kchunk;      // > 0: K split in chunks of kchunk; batch then counts (batch index, chunk) pairs,
+                   // chunk fastest, and C is the [batch][chunk][M][N] workspace (single batch index)
+  // optional second batch index: with nb2 > 1, batch b = b1 * nb2 + b2 and the
+  // operands are offset by b1 * s?b + b2 * s?b2
+  int nb2;
+  i64 sAb2, sBb2, sCb2;
 };
 void launch_zgemm(const GemmArgs& g, hipStream_t s);
 // FP64 kernel variants (tile shape, three or four real products per complex block)
@@ -132,9 +137,9 @@ SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int
 // C[m][n] (+)= alpha * sum_k A[m][k] B[n][k], three bf16 products per real product, FP32 accumulation
 void launch_cgemm_bf16x3(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
                          int beta, hipStream_t s);
-// C[m][n] = (beta ? C : 0) + alpha * sum_s W[s][m][n]
-void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
-                          int beta, hipStream_t s);
+// C[b][m][n] = (beta ? C : 0) + alpha * sum_s W[b][s][m][n]
+void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i64 sCb, i64 sCm, i64 sCn, double ar,
+                          double ai, int beta, hipStream_t s);
 // GEMM with automatic K splitting when the output has too few tiles to fill the GPU
 void run_gemm(cclr_ctx* c, const GemmArgs& g);
 // FP64 GEMM through the autotuner (large products: variant timed once per shape class)

@@ -18,6 +18,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 namespace {
 constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 1;
 
+// element offset of batch bz (one or two batch indices)
+__device__ __forceinline__ i64 boff(const GemmArgs& g, i64 bz, i64 s1, i64 s2) {
+  if (g.nb2 <= 1) return bz * s1;
+  return (bz / g.nb2) * s1 + (bz % g.nb2) * s2;
+}
+
 __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
   __shared__ double sAr[GBK][GBM + GPAD], sAi[GBK][GBM + GPAD];
   __shared__ double sBr[GBK][GBN + GPAD], sBi[GBK][GBN + GPAD];
@@ -25,12 +31,15 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   const i64 bz = blockIdx.z;
   int kbeg = 0, kend = g.K;
+  i64 bb = bz;  // batch index of the operands (the K chunk is folded into bz when splitting)
   if (g.kchunk > 0) {
-    kbeg = (int)bz * g.kchunk;
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
     kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
   }
-  const cplx* __restrict__ A = g.A + (g.kchunk > 0 ? 0 : bz * g.sAb);
-  const cplx* __restrict__ B = g.B + (g.kchunk > 0 ? 0 : bz * g.sBb);
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const bool a_kfast = (g.sAk == 1);
   const bool b_nfast = (g.sBn == 1);
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
     }
     __syncthreads();
   }
-  cplx* __restrict__ C = g.C + bz * g.sCb;
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -116,20 +125,22 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
       }
 }
 
-__global__ __launch_bounds__(256) void k_splitk_reduce(int S, int M, int N, const cplx* __restrict__ W,
-                                                       cplx* __restrict__ C, i64 sCm, i64 sCn, double ar, double ai,
-                                                       int beta) {
-  const i64 total = (i64)M * N, stride = (i64)gridDim.x * blockDim.x;
+// W[b][s][m][n] summed over s in a fixed order into C[b][m][n]
+__global__ __launch_bounds__(256) void k_splitk_reduce(int nb, int S, int M, int N, const cplx* __restrict__ W,
+                                                       cplx* __restrict__ C, i64 sCb, i64 sCm, i64 sCn, double ar,
+                                                       double ai, int beta) {
+  const i64 mn = (i64)M * N, total = mn * nb, stride = (i64)gridDim.x * blockDim.x;
   for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const i64 b = e / mn, r = e % mn;
     double sr = 0.0, si = 0.0;
     for (int q = 0; q < S; ++q) {
-      const cplx w = W[(i64)q * total + e];
+      const cplx w = W[(b * S + q) * mn + r];
       sr += w.x;
       si += w.y;
     }
-    const i64 m = e / N, n = e % N;
+    const i64 m = r / N, n = r % N;
     cplx y = make_double2(ar * sr - ai * si, ar * si + ai * sr);
-    cplx* dst = C + m * sCm + n * sCn;
+    cplx* dst = C + b * sCb + m * sCm + n * sCn;
     if (beta) {
       const cplx o = *dst;
       y.x += o.x;
@@ -161,12 +172,15 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
   __shared__ double sB[2][NP][BK][BN + 1];  // Br, Bi - Br (, Br + Bi)  |  Br, Bi
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int kbeg = 0, kend = g.K;
+  i64 bb = bz;  // batch index of the operands (the K chunk is folded into bz when splitting)
   if (g.kchunk > 0) {
-    kbeg = (int)bz * g.kchunk;
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
     kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
   }
-  const cplx* __restrict__ A = g.A + (g.kchunk > 0 ? 0 : bz * g.sAb);
-  const cplx* __restrict__ B = g.B + (g.kchunk > 0 ? 0 : bz * g.sBb);
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
   const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
   const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
 
@@ -279,7 +293,7 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
     __syncthreads();
     buf ^= 1;
   }
-  cplx* __restrict__ C = g.C + bz * g.sCb;
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -350,8 +364,8 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const i64 bz = blockIdx.z;
   const int kbeg = 0, kend = g.K;
-  const cplx* __restrict__ A = g.A + bz * g.sAb;
-  const cplx* __restrict__ B = g.B + bz * g.sBb;
+  const cplx* __restrict__ A = g.A + boff(g, bz, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bz, g.sBb, g.sBb2);
   const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
   const float sa = g.conjA ? -1.f : 1.f, sb = g.conjB ? -1.f : 1.f;
   cplx ra[LA], rb[LB];
@@ -442,7 +456,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
     __syncthreads();
     buf ^= 1;
   }
-  cplx* __restrict__ C = g.C + bz * g.sCb;
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -727,10 +741,10 @@ void launch_zgemm_simple(const GemmArgs& g, hipStream_t s) {
   HIPCHK(hipGetLastError());
 }
 
-void launch_splitk_reduce(int S, int M, int N, const cplx* W, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
-                          int beta, hipStream_t s) {
-  hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((i64)M * N)), dim3(256), 0, s, S, M, N, W, C, sCm, sCn, ar, ai,
-                     beta);
+void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i64 sCb, i64 sCm, i64 sCn, double ar,
+                          double ai, int beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((i64)M * N * nb)), dim3(256), 0, s, nb, S, M, N, W, C, sCb, sCm,
+                     sCn, ar, ai, beta);
   HIPCHK(hipGetLastError());
 }
 

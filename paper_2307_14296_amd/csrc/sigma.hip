@@ -129,11 +129,14 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
   Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
+  Ten WR = ten(c->WR, {o, v, o, v});
   // singles
   contract(c, one, Fvv, "ae", a.R1, "kie", a.S1, "kia");
   contract(c, mone, Foo, "mi", a.R1, "kma", a.S1, "kia");
-  contract(c, one, Fov, "me", a.R2, "kmiea", a.S1, "kia");
-  contract(c, one, Wovvo, "maei", a.R1, "kme", a.S1, "kia");
+  // r^ea_mi = -r^ea_im: unit-stride (m,e) reduction over the stored r[k][i][m][e][a]
+  contract(c, mone, Fov, "me", a.R2, "kimea", a.S1, "kia");
+  // W^ma_ei read from the ring operator WR[i][a][m][e]
+  contract(c, one, WR, "iame", a.R1, "kme", a.S1, "kia");
   contract(c, half, Wvovv, "amef", a.R2, "kimef", a.S1, "kia");
   contract(c, half, Wooov, "mnie", a.R2, "kmnea", a.S1, "kia");
   // doubles
@@ -146,8 +149,9 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
     // Z_nj = W^nm_je r^e_m + 1/2 V^nm_fe r^fe_jm  (antisymmetry of t relabels the second terms)
     Ten Voovv = Vblk(c, "oovv");
     Ten Y = tmp(c, {nv, v, v});
-    contract(c, one, Wvovv, "bmfe", a.R1, "kme", Y, "kbf", false);
-    contract(c, mhalf, Voovv, "nmfe", a.R2, "kmneb", Y, "kbf");
+    // antisymmetry relabellings W^bm_fe = -W^bm_ef, V^nm_fe = V^mn_ef keep the reductions unit-stride
+    contract(c, mone, Wvovv, "bmef", a.R1, "kme", Y, "kbf", false);
+    contract(c, mhalf, Voovv, "mnef", a.R2, "kmneb", Y, "kbf");
     contract(c, one, t2, "ijaf", Y, "kbf", a.Xa, "kijab");
     Ten Z = tmp(c, {nv, o, o});
     contract(c, one, Wooov, "nmje", a.R1, "kme", Z, "knj", false);
@@ -188,18 +192,19 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
   Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
   Ten Voovv = Vblk(c, "oovv");
+  Ten WL = ten(c->WL, {o, v, o, v});
   // G^e_a = -1/2 l^mn_af t^ef_mn ; G^i_m = 1/2 l^in_ef t^ef_mn  (SI, eqs. G_ea, G_mi)
   Ten Gvv = tmp(c, {nv, v, v}), Goo = tmp(c, {nv, o, o});
-  contract(c, mhalf, a.R2, "kmnaf", t2, "mnef", Gvv, "kea", false);
+  contract(c, mhalf, a.R2, "kmnfa", t2, "mnfe", Gvv, "kea", false);  // l^mn_af t^ef_mn = l^mn_fa t^fe_mn
   contract(c, half, a.R2, "kinef", t2, "mnef", Goo, "kim", false);
   // singles
   contract(c, one, a.R1, "kie", Fvv, "ea", a.S1, "kia");
   contract(c, mone, a.R1, "kma", Foo, "im", a.S1, "kia");
   contract(c, half, a.R2, "kimef", Wvvvo, "efam", a.S1, "kia");
-  contract(c, mhalf, a.R2, "kmnae", Wovoo, "iemn", a.S1, "kia");
+  contract(c, half, a.R2, "kmnea", Wovoo, "iemn", a.S1, "kia");  // l^mn_ae = -l^mn_ea
   contract(c, mone, Gvv, "kfe", Wvovv, "eifa", a.S1, "kia");
   contract(c, mone, Goo, "knm", Wooov, "mina", a.S1, "kia");
-  contract(c, one, a.R1, "kme", Wovvo, "ieam", a.S1, "kia");
+  contract(c, one, a.R1, "kme", WL, "meia", a.S1, "kia");  // W^ie_am = WL[m][e][i][a]
   // doubles
   contract(c, one, a.R2, "kijae", Fvv, "eb", a.Xa, "kijab");
   contract(c, mone, a.R2, "kimab", Foo, "jm", a.Xi, "kijab");

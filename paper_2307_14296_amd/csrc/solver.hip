@@ -274,9 +274,22 @@ unsigned vgrid(i64 n) {
 }  // namespace
 
 // --------------------------------------------------------------- driver
+// Davidson solve of (A - z_r) x_r = -rhs_r (right) or x_r (A - z_r) = -rhs_r
+// (left) for nr right-hand sides in lockstep.
+//
+// lowp != CCLR_FP64 selects iterative refinement with subspace recycling:
+// the trial vectors are transformed with reduced-precision ladder and ring
+// products; when a right-hand side's projected residual falls below
+// inner_tol relative to its current right-hand side, its solution is
+// accumulated, the true residual R = (A - z) x + rhs is formed with FP64
+// transforms, and if ||R|| > tol ||rhs|| the same subspace continues on the
+// correction equation with right-hand side R (only the projected right-hand
+// side C' is recomputed).  Residual norms, orthogonalisation and the
+// projected system are FP64 throughout.
 int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
-             cclr_solve_info* info, double tol, int maxit_in) {
+             cclr_solve_info* info, double tol, int maxit_in, int lowp, double inner_tol) {
   auto t0 = std::chrono::steady_clock::now();
+  const bool refine = lowp != CCLR_FP64;
   const i64 ov = c->ns(), nd = c->nd(), n = ov + nd;
   const int ms = std::max(4, std::min(c->opt.max_subspace, 120));
   hipStream_t st = c->stream;
@@ -289,8 +302,15 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
     return v;
   };
   VecSet Bv = vbuf(nr * ms), Sv = vbuf(nr * ms), Rv = vbuf(nr), Ev = vbuf(nr), Xin = vbuf(nr), Xout = vbuf(nr);
+  VecSet Yv = vbuf(nr);                      // restart scratch
+  VecSet RCv = refine ? vbuf(nr) : rhs;      // current right-hand side (the true residual after refinement)
   const VS B{Bv.s, Bv.d, ms}, S{Sv.s, Sv.d, ms}, R{Rv.s, Rv.d, 1}, E{Ev.s, Ev.d, 1};
-  const VS XI{rhs.s, rhs.d, 1}, XO{xout.s, xout.d, 1}, T{Xout.s, Xout.d, 1};
+  const VS XI{RCv.s, RCv.d, 1}, X0{rhs.s, rhs.d, 1}, XO{xout.s, xout.d, 1}, T{Xout.s, Xout.d, 1};
+  const VS YT{Yv.s, Yv.d, 1};
+  if (refine) {
+    HIPCHK(hipMemcpyAsync(RCv.s, rhs.s, sizeof(cplx) * (size_t)nr * ov, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(RCv.d, rhs.d, sizeof(cplx) * (size_t)nr * nd, hipMemcpyDeviceToDevice, st));
+  }
   cplx* G = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms * ms);
   cplx* Cp = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms);
   cplx* beta = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * ms);
@@ -345,12 +365,13 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
   std::vector<cplx> hv;
   gram(XI, 0, 1, XI, 0, tmpv, 1, 0, 0);
   fetch(tmpv, hv, 1);
-  std::vector<double> xinorm(nr), res(nr, 0.0);
-  std::vector<int> msub(nr, 0), done(nr, 0);
+  std::vector<double> xinorm(nr), rcnorm(nr), res(nr, 0.0);
+  std::vector<int> msub(nr, 0), done(nr, 0), outer(nr, 0), accumulated(nr, 0);
   for (int r = 0; r < nr; ++r) {
-    xinorm[r] = std::sqrt(hv[r].x);
-    if (xinorm[r] == 0.0) done[r] = 1;  // x = 0
+    xinorm[r] = rcnorm[r] = std::sqrt(hv[r].x);
+    if (xinorm[r] == 0.0) done[r] = 1, accumulated[r] = 1;  // x = 0
   }
+  const int max_outer = 8;
   launch_fill(xout.s, (i64)nr * ov, cx(0.0), st);
   launch_fill(xout.d, (i64)nr * nd, cx(0.0), st);
   {
@@ -366,6 +387,39 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
   long nsigma = 0;
   auto sigma = (side == CCLR_RIGHT) ? sigma_right : sigma_left;
   const int maxit = std::max(1, maxit_in);
+  c->sigma_prec = lowp;
+  // projected solve and residual R = sum_i beta_i s_i + rhs_cur for the active set; returns the
+  // relative residual of each active right-hand side (by rhs index)
+  auto project = [&](int m) {
+    hipLaunchKernelGGL(k_small_solve, dim3(na), dim3(kThreads), 0, st, G, Cp, m, ms, W, beta, sing_d, act_d);
+    lincomb(R, 0, S, 0, m, beta, ms, 1.0, XI, 0, 1, 0);
+    gram(R, 0, 1, R, 0, tmpv, 1, 0, 0);
+    fetch(tmpv, hv, 1);
+  };
+  // x += sum beta b, then the FP64 true residual into the current right-hand side
+  auto refine_step = [&](const std::vector<int>& cand, int m) {
+    set_active(cand);
+    lincomb(XO, 0, B, 0, m, beta, ms, 1.0, XO, 0, 0, 1);
+    for (int a = 0; a < na; ++a) {
+      const int r = act[a];
+      HIPCHK(hipMemcpyAsync(Xin.s + a * ov, xout.s + (i64)r * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(Xin.d + a * nd, xout.d + (i64)r * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, st));
+    }
+    VecSet vin = Xin, vout = Xout;
+    vin.n = vout.n = na;
+    c->sigma_prec = CCLR_FP64;
+    sigma(c, vin, vout, za_d);
+    c->sigma_prec = lowp;
+    nsigma += na;
+    for (int a = 0; a < na; ++a) {
+      const int r = act[a];
+      HIPCHK(hipMemcpyAsync(RCv.s + (i64)r * ov, Xout.s + a * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(RCv.d + (i64)r * nd, Xout.d + a * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, st));
+    }
+    lincomb(XI, 0, B, 0, 0, beta, ms, 1.0, X0, 0, 1, 1);  // rhs_cur = (A - z) x + rhs
+    gram(XI, 0, 1, XI, 0, tmpv, 1, 0, 0);
+    fetch(tmpv, hv, 1);
+  };
   while (na > 0) {
     // batched transform of the newest trial vectors
     for (int a = 0; a < na; ++a) {
@@ -390,32 +444,59 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
       gram(S, 0, j, B, j, tmpv, ms, 0, 1);    // conj <s_i, b_j> = <b_j, s_i>
       hipLaunchKernelGGL(k_put, dim3(na), dim3(128), 0, st, tmpv, j, G, ms, j, 1, act_d);
     }
-    gram(B, j, 1, XI, 0, Cp, ms, j, 0);       // C'_j = <b_j, xi>
+    gram(B, j, 1, XI, 0, Cp, ms, j, 0);       // C'_j = <b_j, rhs_cur>
     const int m = j + 1;
-    hipLaunchKernelGGL(k_small_solve, dim3(na), dim3(kThreads), 0, st, G, Cp, m, ms, W, beta, sing_d, act_d);
-    // residual R = sum_i beta_i s_i + xi and its norm
-    lincomb(R, 0, S, 0, m, beta, ms, 1.0, XI, 0, 1, 0);
-    gram(R, 0, 1, R, 0, tmpv, 1, 0, 0);
-    fetch(tmpv, hv, 1);
-    std::vector<int> still;
+    project(m);
+    std::vector<int> still, cand;
     for (int a = 0; a < na; ++a) {
       const int r = act[a];
-      res[r] = std::sqrt(std::max(hv[r].x, 0.0)) / xinorm[r];
+      const double rin = std::sqrt(std::max(hv[r].x, 0.0)) / rcnorm[r];
+      res[r] = rin * rcnorm[r] / xinorm[r];
       msub[r] = m;
-      if (res[r] <= tol || !std::isfinite(res[r])) done[r] = 1;
+      if (!std::isfinite(res[r])) done[r] = 1;
+      else if (!refine && res[r] <= tol) done[r] = 1;
+      else if (refine && (rin <= inner_tol || res[r] <= tol)) cand.push_back(r);
       else still.push_back(r);
     }
+    // refinement: accumulate, FP64 residual, continue on the correction equation in the same subspace
+    while (!cand.empty()) {
+      refine_step(cand, m);
+      std::vector<int> again;
+      for (int r : cand) {
+        const double tn = std::sqrt(std::max(hv[r].x, 0.0));
+        res[r] = tn / xinorm[r];
+        ++outer[r];
+        if (res[r] <= tol || !std::isfinite(res[r]) || outer[r] >= max_outer) {
+          done[r] = 1;
+          accumulated[r] = 1;
+        } else {
+          rcnorm[r] = tn;
+          again.push_back(r);
+        }
+      }
+      if (again.empty()) break;
+      set_active(again);
+      gram(B, 0, m, XI, 0, Cp, ms, 0, 0);     // C' for the new right-hand side
+      project(m);
+      cand.clear();
+      for (int r : again) {
+        const double rin = std::sqrt(std::max(hv[r].x, 0.0)) / rcnorm[r];
+        if (rin <= inner_tol) cand.push_back(r);
+        else still.push_back(r);
+      }
+    }
     if (still.empty() || iters >= maxit) break;
+    std::sort(still.begin(), still.end());
     set_active(still);
     // correction (z - D)^-1 R
     scale(E, 0, R, 0, nullptr, 0);
     int nj = m;
     if (m == ms) {
       // restart from the current solution: b0 = x/|x|, s0 = (sum beta s)/|x|
-      lincomb(XO, 0, B, 0, m, beta, ms, 1.0, XO, 0, 0, 0);
+      lincomb(YT, 0, B, 0, m, beta, ms, 1.0, YT, 0, 0, 0);
       lincomb(T, 0, S, 0, m, beta, ms, 1.0, T, 0, 0, 0);
-      gram(XO, 0, 1, XO, 0, tmpv, 1, 0, 0);
-      scale(B, 0, XO, 0, tmpv, 1);
+      gram(YT, 0, 1, YT, 0, tmpv, 1, 0, 0);
+      scale(B, 0, YT, 0, tmpv, 1);
       scale(S, 0, T, 0, tmpv, 1);
       gram(B, 0, 1, S, 0, tmpv, ms, 0, 0);
       hipLaunchKernelGGL(k_put, dim3(na), dim3(128), 0, st, tmpv, 1, G, ms, 0, 0, act_d);
@@ -431,12 +512,14 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
     scale(B, j, E, 0, tmpv, 1);
   }
   // solutions x_r = sum_i beta_i b_i over each right-hand side's final subspace
+  // (added to the accumulated solution when refining)
   for (int r = 0; r < nr; ++r) {
-    if (msub[r] == 0) continue;
+    if (msub[r] == 0 || accumulated[r]) continue;
     std::vector<int> one{r};
     set_active(one);
-    lincomb(XO, 0, B, 0, msub[r], beta, ms, 1.0, XO, 0, 0, 0);
+    lincomb(XO, 0, B, 0, msub[r], beta, ms, 1.0, XO, 0, 0, refine ? 1 : 0);
   }
+  c->sigma_prec = CCLR_FP64;
   HIPCHK(hipStreamSynchronize(st));
   c->arena.reset(mk);
   int conv = 1;
@@ -473,97 +556,17 @@ void axpy(cclr_ctx* c, cplx* x, const cplx* y, i64 n, double a) {
 }  // namespace
 
 // Solve with the context's precision.  FP64: one Davidson solve.  FP32 /
-// split-BF16: iterative refinement — the Davidson solve runs with low-
-// precision ladder and ring products (its residuals, orthogonalisation and
-// projected system stay FP64), then the true residual R = (A - z) x + b is
-// formed with FP64 transforms and the correction equation is solved the same
-// way, until ||R|| <= tol ||b||.
+// split-BF16: the Davidson solve with iterative refinement and subspace
+// recycling (see davidson): reduced-precision ladder and ring products for
+// the trial vectors, FP64 true residuals, until ||R|| <= tol ||b||.
 int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
                  cclr_solve_info* info) {
   const double tol = c->opt.tol;
   if (c->opt.prec == CCLR_FP64) {
     c->sigma_prec = CCLR_FP64;
-    return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter);
+    return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter, CCLR_FP64, 0.0);
   }
-  auto t0 = std::chrono::steady_clock::now();
-  const i64 ov = c->ns(), nd = c->nd();
-  hipStream_t st = c->stream;
-  Arena::Mark mk = c->arena.mark();
-  auto vbuf = [&](int nvec) {
-    VecSet v;
-    v.s = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * ov));
-    v.d = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * nd));
-    v.n = nvec;
-    return v;
-  };
-  VecSet R = vbuf(nr), D = vbuf(nr);
-  cplx* zd = (cplx*)c->arena.get(sizeof(cplx) * nr);
-  HIPCHK(hipMemcpyAsync(zd, zh, sizeof(cplx) * nr, hipMemcpyHostToDevice, st));
-  launch_fill(xout.s, nr * ov, cx(0.0), st);
-  launch_fill(xout.d, nr * nd, cx(0.0), st);
-  HIPCHK(hipMemcpyAsync(R.s, rhs.s, sizeof(cplx) * nr * ov, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(R.d, rhs.d, sizeof(cplx) * nr * nd, hipMemcpyDeviceToDevice, st));
-  // inner accuracy: what the low-precision products can deliver
+  // inner accuracy: what the reduced-precision products can deliver
   const double inner = c->opt.prec == CCLR_FP32 ? 1e-6 : 1e-4;
-  auto sigma = (side == CCLR_RIGHT) ? sigma_right : sigma_left;
-  // ||v_r|| per right-hand side (device Gram kernels, FP64)
-  int* act = (int*)c->arena.get(sizeof(int) * nr);
-  cplx* partial = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nr * kChunks);
-  cplx* nrm = (cplx*)c->arena.get(sizeof(cplx) * nr);
-  {
-    std::vector<int> all(nr);
-    for (int r = 0; r < nr; ++r) all[r] = r;
-    HIPCHK(hipMemcpyAsync(act, all.data(), sizeof(int) * nr, hipMemcpyHostToDevice, st));
-  }
-  auto norms = [&](const VecSet& v) {
-    const VS X{v.s, v.d, 1};
-    hipLaunchKernelGGL(k_gram, dim3(kChunks, 1, nr), dim3(kThreads), 0, st, X, 0, 1, X, 0, act, ov, nd, partial);
-    hipLaunchKernelGGL(k_reduce, dim3(nr), dim3(kThreads), 0, st, partial, 1, act, nrm, 1, 0, 0);
-    std::vector<cplx> h(nr);
-    HIPCHK(hipMemcpyAsync(h.data(), nrm, sizeof(cplx) * nr, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    std::vector<double> out(nr);
-    for (int r = 0; r < nr; ++r) out[r] = std::sqrt(std::max(h[r].x, 0.0));
-    return out;
-  };
-  const std::vector<double> b0 = norms(rhs);
-  int iters = 0, outer = 0;
-  long nsig = 0;
-  double worst = 0.0;
-  int rc = CCLR_ENOTCONV;
-  const int max_outer = 8;
-  for (outer = 0; outer < max_outer; ++outer) {
-    cclr_solve_info in{};
-    c->sigma_prec = c->opt.prec;
-    davidson(c, side, nr, zh, R, D, &in, inner, c->opt.maxiter);
-    iters += in.iters;
-    nsig += in.nsigma;
-    axpy(c, xout.s, D.s, nr * ov, 1.0);
-    axpy(c, xout.d, D.d, nr * nd, 1.0);
-    // true residual with FP64 transforms: R = (A - z) x + b
-    c->sigma_prec = CCLR_FP64;
-    sigma(c, xout, R, zd);
-    nsig += nr;
-    axpy(c, R.s, rhs.s, nr * ov, 1.0);
-    axpy(c, R.d, rhs.d, nr * nd, 1.0);
-    const std::vector<double> rn = norms(R);
-    worst = 0.0;
-    for (int r = 0; r < nr; ++r) worst = std::max(worst, b0[r] > 0 ? rn[r] / b0[r] : 0.0);
-    if (worst <= tol) {
-      rc = CCLR_OK;
-      ++outer;
-      break;
-    }
-  }
-  c->sigma_prec = CCLR_FP64;
-  HIPCHK(hipStreamSynchronize(st));
-  c->arena.reset(mk);
-  if (info) {
-    info->iters = iters;
-    info->converged = rc == CCLR_OK;
-    info->resnorm = worst;
-    info->nsigma = nsig;
-    info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
-  return rc;
+  return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter, c->opt.prec, inner);
 }

@@ -100,6 +100,13 @@ CONTRACT_CASES = [
     # tiny output, long reduction: exercises the split-K path
     ("inef", "mnef", "im", dict(i=3, n=40, e=30, f=31, m=5)),
     ("kimfe", "nmfe", "kni", dict(k=2, i=4, m=9, f=60, e=61, n=7)),
+    # output groups broken by the other operand's labels: one or two free batch indices
+    ("mj", "kimab", "kijab", dict(m=3, j=3, k=2, i=3, a=5, b=5)),
+    ("me", "kimea", "kia", dict(m=3, e=5, k=2, i=3, a=5)),
+    ("mnie", "kmnea", "kia", dict(m=3, n=3, i=3, e=5, a=5, k=3)),
+    ("mbij", "kma", "kijab", dict(m=3, b=5, i=3, j=3, k=2, a=5)),
+    ("abej", "kie", "kijab", dict(a=5, b=5, e=7, j=3, k=2, i=3)),
+    ("inab", "knj", "kijab", dict(i=3, n=4, a=5, b=5, k=2, j=3)),
 ]
 
 

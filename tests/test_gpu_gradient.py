@@ -143,17 +143,19 @@ BLOCKS = ("oooo", "ooov", "oovv", "ovov", "ovvv", "vvvv")
 def sym_direction(o, v, rng):
     """Random change of (f, <pq||rs>) that keeps the input symmetries: f
     Hermitian, the integrals antisymmetric in each pair and Hermitian under
-    bra-ket exchange; returned as (df, {block: dV})."""
+    bra-ket exchange; unit Frobenius norm each; returned as (df, {block: dV})."""
     n = o + v
     cr = lambda *s: rng.normal(size=s) + 1j * rng.normal(size=s)  # noqa: E731
     D = cr(n, n, n, n)
     D = D - D.transpose(1, 0, 2, 3)
     D = D - D.transpose(0, 1, 3, 2)
     D = 0.5 * (D + D.conj().transpose(2, 3, 0, 1))
+    D /= np.linalg.norm(D)
     sl = {"o": slice(0, o), "v": slice(o, None)}
     dV = {k: D[sl[k[0]], sl[k[1]], sl[k[2]], sl[k[3]]].copy() for k in BLOCKS}
     F = cr(n, n)
-    return 0.5 * (F + F.conj().T), dV
+    F = F + F.conj().T
+    return F / np.linalg.norm(F), dV
 
 
 def h_loss(H, t1, t2, Xs, zs, G, df, dV, h):
