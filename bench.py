@@ -20,6 +20,7 @@ import ctypes
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -153,6 +154,27 @@ def batching_bench(cc, dev, nvec=3, reps=3):
         torch.cuda.empty_cache()
 
 
+LADDER_TRAFFIC = os.path.join(ROOT, "profiles", "ladder_gemm_o20v200_traffic.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2307_14296_amd", "csrc", "kernels.hip")
+
+
+def ladder_traffic(variant):
+    """HBM bytes per launch of the batched FP64 ladder GEMM (12 vectors at
+    o=20, v=200) from the committed rocprofv3 --pmc summary; None when the
+    GEMM source or the kernel variant differs from the one the counters
+    were taken on."""
+    import hashlib
+    try:
+        text = open(LADDER_TRAFFIC).read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^- (\w+): (\S+)$", text, flags=re.M))
+    src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != src or vals.get("variant") != str(variant):
+        return None
+    return float(vals["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in vals else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -192,7 +214,7 @@ def main():
 
     L = cc.lib()
     L.cclr_dbg_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    L.cclr_dbg_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
+    L.cclr_dbg_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.cclr_dbg_set_sigma_prec.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.cclr_dbg_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_longlong]
@@ -259,11 +281,11 @@ def main():
             log(f"[{prec}] timed step {k} done ({time.perf_counter() - t0:.2f} s so far)")
         dt = time.perf_counter() - t0
         nl, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
-        L.cclr_dbg_profile_read(ctx, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
+        L.cclr_dbg_profile_read(ctx, 1, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
         L.cclr_dbg_profile(ctx, 0)
         buf = ctypes.create_string_buffer(1 << 16)
         L.cclr_dbg_tuning(ctx, -1, buf, len(buf))
-        res["gemm_tuning"] = [ln for ln in buf.value.decode().splitlines() if ln][:12]
+        res["gemm_tuning"] = [ln for ln in buf.value.decode().splitlines() if ln]
         cc.cclr_destroy(ctx)
         del f, t1, t2, X
         torch.cuda.empty_cache()
@@ -289,17 +311,23 @@ def main():
     ms = ctypes.c_double(main_res["ms"])
     fl = ctypes.c_double(main_res["fl"])
     t_gen = main_res["input_generation_s"]
-    extra = {k: main_res[k] for k in ("solver", "rc", "gemm_tuning") if k in main_res}
+    extra = {k: main_res[k] for k in ("solver", "rc") if k in main_res}
+    extra["gemm_tuning"] = main_res.get("gemm_tuning", [])[:16]
     achieved = fl.value / (ms.value * 1e-3) / 1e12 if ms.value > 0 else 0.0
     sf = sigma_flops(o, v)
+    ladder_shape = f"{(o * (o - 1) // 2) * args.nvec}x{v * (v - 1) // 2}x{v * (v - 1) // 2}"
+    variant = [ln for ln in main_res.get("gemm_tuning", []) if ln.startswith(ladder_shape)]
+    chosen = int(variant[0].rsplit("->", 1)[1]) if variant else None
     roofline = {
         "bound": "mfma",
-        "kernel": "k_zgemm (packed particle-particle ladder)",
+        "kernel": "k_zgemm_p (packed particle-particle ladder, FP64 MFMA), largest launches" +
+                  (f"; autotuner: {variant[0]}" if variant else ""),
         "achieved": round(achieved, 3),
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-        "traffic": None,
+        "traffic": ladder_traffic(chosen),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain-copy reference)",
         "launches": nl.value,
         "avg_launch_ms": round(ms.value / max(1, nl.value), 4),
         "flop_per_launch": fl.value / max(1, nl.value),

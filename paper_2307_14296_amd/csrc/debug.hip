@@ -1,4 +1,5 @@
 // Internal test hooks (include/cclr_debug.h).
+#include <algorithm>
 #include <cstring>
 
 #include "../../include/cclr_debug.h"
@@ -128,17 +129,21 @@ int cclr_dbg_profile(cclr_ctx* c, int enable) {
   return CCLR_OK;
 }
 
-int cclr_dbg_profile_read(cclr_ctx* c, long long* launches, double* ms, double* flops) {
+int cclr_dbg_profile_read(cclr_ctx* c, int largest_only, long long* launches, double* ms, double* flops) {
   if (!c) return CCLR_EINVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return CCLR_EHIP;
-  double t = 0.0, f = 0.0;
+  double t = 0.0, f = 0.0, fmax = 0.0;
+  long long n = 0;
+  for (double x : c->prof_flops) fmax = std::max(fmax, x);
   for (size_t k = 0; k < c->prof_events.size(); ++k) {
+    if (largest_only && c->prof_flops[k] < fmax) continue;
     float x = 0.f;
     if (hipEventElapsedTime(&x, c->prof_events[k].first, c->prof_events[k].second) != hipSuccess) return CCLR_EHIP;
     t += x;
     f += c->prof_flops[k];
+    ++n;
   }
-  if (launches) *launches = (long long)c->prof_events.size();
+  if (launches) *launches = n;
   if (ms) *ms = t;
   if (flops) *flops = f;
   return CCLR_OK;
