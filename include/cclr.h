@@ -142,6 +142,21 @@ int cclr_solve_damped(cclr_ctx* ctx, int side, int nrhs, const double* omega, co
                       const cclr_c64* b1, const cclr_c64* b2, cclr_c64* x1, cclr_c64* x2,
                       cclr_solve_info* info);
 
+/* The nroots lowest EOM-EE excitation energies (smallest real part) and
+ * their eigenvectors: side == CCLR_RIGHT: A x_k = w_k x_k; CCLR_LEFT:
+ * x_k A = w_k x_k.  These are the poles of the response function (theory
+ * section, poles of the linear response function at the EOM-EE excitation
+ * energies; SI, "EOM-EE sigma-vectors").  Davidson's method for a few
+ * eigenpairs of a non-Hermitian matrix: one subspace shared by the roots,
+ * start vectors on the smallest Fock-like diagonal entries, corrections
+ * (w_k - D)^-1 r_k, restart from the Ritz vectors when the subspace is full.
+ * Stops when every residual ||A x_k - w_k x_k|| <= tol (x_k of unit norm).
+ * omega: HOST array of nroots complex values (written); x1[k][o][v] and
+ * x2[k][o][o][v][v]: DEVICE outputs (both may be NULL to skip them).
+ * 1 <= nroots <= 30; options.maxiter bounds the iterations. */
+int cclr_eom_ee(cclr_ctx* ctx, int side, int nroots, double tol, cclr_c64* omega, cclr_c64* x1, cclr_c64* x2,
+                cclr_solve_info* info);
+
 /* Solve lambda A = -eta0 (eta0 singles F^i_a, doubles <ij||ab>) and keep
  * lambda in the context.  Needs cclr_set_amplitudes. */
 int cclr_solve_lambda(cclr_ctx* ctx, cclr_solve_info* info);

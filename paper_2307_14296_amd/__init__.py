@@ -25,7 +25,7 @@ CCLR_RIGHT, CCLR_LEFT = 0, 1
 
 EXPORTED = (
     "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_amplitudes",
-    "cclr_jacobian_right", "cclr_jacobian_left", "cclr_jacobian_right_multi", "cclr_solve_damped", "cclr_solve_lambda", "cclr_get_lambda",
+    "cclr_jacobian_right", "cclr_jacobian_left", "cclr_jacobian_right_multi", "cclr_solve_damped", "cclr_eom_ee", "cclr_solve_lambda", "cclr_get_lambda",
     "cclr_response_function", "cclr_response_backward", "cclr_last_error",
 )
 
@@ -72,6 +72,7 @@ def lib():
     L.cclr_jacobian_right_multi.argtypes = [I, PP, ctypes.POINTER(I), PP, PP, PP, PP, PP, PP]
     L.cclr_solve_damped.argtypes = [P, I, I, D, D, P, P, P, P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_solve_lambda.argtypes = [P, ctypes.POINTER(cclr_solve_info)]
+    L.cclr_eom_ee.argtypes = [P, I, I, ctypes.c_double, P, P, P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_get_lambda.argtypes = [P, P, P]
     L.cclr_response_function.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_response_backward.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(P), P,
@@ -183,6 +184,18 @@ def cclr_solve_damped(ctx, side, omega, gamma, b1, b2, x1, x2):
                                  _ptr(b2, "b2"), _ptr(x1, "x1"), _ptr(x2, "x2"), ctypes.byref(info))
     _check(ctx, rc, allow_notconv=True)
     return rc, info
+
+
+def cclr_eom_ee(ctx, side, nroots, tol, x1=None, x2=None):
+    """Returns (rc, omega as a host numpy complex128 array, info); x1/x2: optional GPU outputs."""
+    import numpy as np
+    om = np.zeros(max(int(nroots), 1), dtype=np.complex128)
+    info = cclr_solve_info()
+    rc = lib().cclr_eom_ee(ctx, int(side), int(nroots), float(tol), ctypes.c_void_p(om.ctypes.data),
+                           _ptr(x1, "x1") if x1 is not None else None, _ptr(x2, "x2") if x2 is not None else None,
+                           ctypes.byref(info))
+    _check(ctx, rc, allow_notconv=True)
+    return rc, om[:nroots], info
 
 
 def cclr_solve_lambda(ctx):

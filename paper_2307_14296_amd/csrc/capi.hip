@@ -374,6 +374,26 @@ int cclr_solve_damped(cclr_ctx* c, int side, int nrhs, const double* omega, cons
   });
 }
 
+int cclr_eom_ee(cclr_ctx* c, int side, int nroots, double tol, cclr_c64* omega, cclr_c64* x1, cclr_c64* x2,
+                cclr_solve_info* info) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    require_t(c);
+    REQUIRE(side == CCLR_RIGHT || side == CCLR_LEFT, CCLR_EINVAL, "side must be CCLR_RIGHT or CCLR_LEFT");
+    REQUIRE(omega, CCLR_EINVAL, "null omega");
+    REQUIRE(std::isfinite(tol) && tol > 0.0, CCLR_EINVAL, "tol must be positive");
+    Arena::Mark mk = c->arena.mark();
+    VecSet x = packed_buf(c, std::max(nroots, 1));
+    std::vector<cplx> w;
+    const int rc = eom_davidson(c, side, nroots, tol, c->opt.maxiter, w, x, info);
+    for (int k = 0; k < nroots; ++k) omega[k] = cclr_c64{w[k].x, w[k].y};
+    if (x1 || x2) unpack_out(c, x, x1, x2, "eigenvectors");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->arena.reset(mk);
+    return rc;
+  });
+}
+
 int cclr_solve_lambda(cclr_ctx* c, cclr_solve_info* info) {
   if (!c) return CCLR_EINVAL;
   return guarded(c, [&]() -> int { return solve_lambda_impl(c, info); });

@@ -461,6 +461,7 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
 // products to a workspace, summed in a fixed order afterwards.
 void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  if (g.K <= 32 && launch_zgemm_smallk(g, c->stream)) return;
   const i64 tiles = (i64)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
   if (g.nb2 <= 1 && tiles < 512 && g.K >= 512) {
     i64 S = std::min<i64>((1024 + tiles - 1) / tiles, g.K / 256);

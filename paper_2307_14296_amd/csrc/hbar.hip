@@ -133,6 +133,14 @@ void build_intermediates(cclr_ctx* c) {
   c->WL.alloc(c, sizeof(cplx) * (size_t)(o * v * o * v));
   tcopy(c, ten(c->WR, {o, v, o, v}), "jbme", Wovvo, "mbej", one, false);
   tcopy(c, ten(c->WL, {o, v, o, v}), "mejb", Wovvo, "jebm", one, false);
+  // W^ab_ej as [j][e][a][b] for the right doubles term P(ij) W^ab_ej r^e_i (unit-stride ab)
+  c->WvvvoT.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
+  tcopy(c, ten(c->WvvvoT, {o, v, v, v}), "jeab", Wvvvo, "abej", one, false);
+  // left-transform layouts with unit-stride reductions: W^ef_am as [a][m][e][f], W^ei_fa as [i][a][f][e]
+  c->WvvvoL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
+  tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
+  c->WvovvL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
+  tcopy(c, ten(c->WvovvL, {o, v, v, v}), "iafe", Wvovv, "eifa", one, false);
   // packed ladder operator and preconditioner diagonal
   c->Wp.alloc(c, sizeof(cplx) * (size_t)(c->V2() * c->V2()));
   launch_pack_vvvv((int)v, c->Wvvvv.c(), c->Wp.c(), c->stream);

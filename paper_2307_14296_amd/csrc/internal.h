@@ -137,6 +137,8 @@ SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int
 // C[m][n] (+)= alpha * sum_k A[m][k] B[n][k], three bf16 products per real product, FP32 accumulation
 void launch_cgemm_bf16x3(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
                          int beta, hipStream_t s);
+// products with K <= 32 on the vector ALU (returns false if the form does not apply)
+bool launch_zgemm_smallk(const GemmArgs& g, hipStream_t s);
 // C[b][m][n] = (beta ? C : 0) + alpha * sum_s W[b][s][m][n]
 void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i64 sCb, i64 sCm, i64 sCn, double ar,
                           double ai, int beta, hipStream_t s);
@@ -192,6 +194,8 @@ struct cclr_ctx {
   DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo, Wvvvv;
   DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
+  DevBuf WvvvoT;     // WvvvoT[j][e][a][b] = W^ab_ej
+  DevBuf WvvvoL, WvovvL;  // WvvvoL[a][m][e][f] = W^ef_am, WvovvL[i][a][f][e] = W^ei_fa (left transform)
   // split-BF16 copies of the ladder and ring operators, made on first use in
   // that precision: right ladder, left ladder, right ring, left ring
   DevBuf wsplit[4];
@@ -276,3 +280,6 @@ void density_eta(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
 // gradient with respect to f and the integral blocks (see adjoint.hip)
 void hamiltonian_adjoint(cclr_ctx* c, int nx, const cplx* Xs, const VecSet& sol, const VecSet& xl, const VecSet& Y,
                          const VecSet& PA, const VecSet& PB, cplx* df, cplx* const* dV, cclr_solve_info* info);
+// lowest EOM-EE eigenpairs (right: A x = w x, left: x A = w x); omega by increasing real part
+int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit, std::vector<cplx>& omega,
+                 const VecSet& xout, cclr_solve_info* info);

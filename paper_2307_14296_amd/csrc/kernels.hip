@@ -151,6 +151,64 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int nb, int S, int M, int
 }
 
 // --------------------------------------------------------------------------
+// Short reductions (K <= 32): memory-bound products such as the o-index
+// terms of the doubles.  FP64 on the vector ALU: the threads of a workgroup
+// run along n (coalesced B and C), each keeps its column of B in registers
+// and sweeps a block of 32 rows of A held in LDS, so every element of B and
+// C moves once.
+// --------------------------------------------------------------------------
+constexpr int SK_MAX = 32, SK_MB = 32;
+
+__global__ __launch_bounds__(256) void k_zgemm_smallk(GemmArgs g) {
+  __shared__ cplx sA[SK_MB][SK_MAX];
+  const i64 bz = blockIdx.z;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int m0 = blockIdx.y * SK_MB;
+  const cplx* __restrict__ A = g.A + boff(g, bz, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bz, g.sBb, g.sBb2);
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+  const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+  for (int e = threadIdx.x; e < SK_MB * SK_MAX; e += 256) {
+    const int mm = e / SK_MAX, kk = e % SK_MAX;
+    cplx x = make_double2(0.0, 0.0);
+    if (m0 + mm < g.M && kk < g.K) {
+      x = A[(i64)(m0 + mm) * g.sAm + (i64)kk * g.sAk];
+      x.y *= sa;
+    }
+    sA[mm][kk] = x;
+  }
+  __syncthreads();
+  if (n >= g.N) return;
+  cplx b[SK_MAX];
+#pragma unroll
+  for (int k = 0; k < SK_MAX; ++k) {
+    b[k] = make_double2(0.0, 0.0);
+    if (k < g.K) {
+      b[k] = B[(i64)k * g.sBk + (i64)n * g.sBn];
+      b[k].y *= sb;
+    }
+  }
+  const int mend = min(SK_MB, g.M - m0);
+  for (int mm = 0; mm < mend; ++mm) {
+    double xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int k = 0; k < SK_MAX; ++k) {
+      const cplx a = sA[mm][k];
+      xr += a.x * b[k].x - a.y * b[k].y;
+      xi += a.x * b[k].y + a.y * b[k].x;
+    }
+    cplx y = make_double2(g.ar * xr - g.ai * xi, g.ar * xi + g.ai * xr);
+    cplx* dst = C + (i64)(m0 + mm) * g.sCm + (i64)n * g.sCn;
+    if (g.beta) {
+      const cplx o = *dst;
+      y.x += o.x;
+      y.y += o.y;
+    }
+    *dst = y;
+  }
+}
+
+// --------------------------------------------------------------------------
 // Pipelined complex GEMM with three real products per complex block (Gauss):
 //   k1 = (Ar + Ai) Br,  k2 = Ar (Bi - Br),  k3 = Ai (Br + Bi),
 //   Re C = k1 - k3,     Im C = k1 + k2.
@@ -732,6 +790,23 @@ void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
   else if (bn) hipLaunchKernelGGL((k_cgemm_f32<128, 64, false, true>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((k_cgemm_f32<128, 64, false, false>), grid, dim3(256), 0, s, g);
   HIPCHK(hipGetLastError());
+}
+
+bool launch_zgemm_smallk(const GemmArgs& g0, hipStream_t s) {
+  if (g0.K > SK_MAX || g0.kchunk > 0 || g0.M <= 0 || g0.N <= 0 || g0.batch <= 0 || g0.K <= 0) return false;
+  GemmArgs g = g0;
+  // run the threads along the unit-stride index of C (transpose the product if that is m)
+  if (g0.sCn != 1 && g0.sCm == 1) {
+    g.M = g0.N; g.N = g0.M;
+    g.A = g0.B; g.sAb = g0.sBb; g.sAb2 = g0.sBb2; g.sAm = g0.sBn; g.sAk = g0.sBk; g.conjA = g0.conjB;
+    g.B = g0.A; g.sBb = g0.sAb; g.sBb2 = g0.sAb2; g.sBk = g0.sAk; g.sBn = g0.sAm; g.conjB = g0.conjA;
+    g.sCm = g0.sCn; g.sCn = g0.sCm;
+  }
+  if (g.batch >= 65536 || (g.M + SK_MB - 1) / SK_MB >= 65536) return false;
+  dim3 grid((g.N + 255) / 256, (g.M + SK_MB - 1) / SK_MB, g.batch);
+  hipLaunchKernelGGL(k_zgemm_smallk, grid, dim3(256), 0, s, g);
+  HIPCHK(hipGetLastError());
+  return true;
 }
 
 void launch_zgemm_simple(const GemmArgs& g, hipStream_t s) {

@@ -141,7 +141,7 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   contract(c, half, Wooov, "mnie", a.R2, "kmnea", a.S1, "kia");
   // doubles
   contract(c, mone, Wovoo, "mbij", a.R1, "kma", a.Xa, "kijab");
-  contract(c, one, Wvvvo, "abej", a.R1, "kie", a.Xi, "kijab");
+  contract(c, one, ten(c->WvvvoT, {o, v, v, v}), "jeab", a.R1, "kie", a.Xi, "kijab");
   {
     // P(ab) [W^bm_fe r^e_m t^af_ij - 1/2 V^nm_fe r^ea_mn t^fb_ij] = P(ab) t^af_ij Y_bf with
     // Y_bf = W^bm_fe r^e_m - 1/2 V^nm_fe r^eb_mn, and likewise
@@ -200,9 +200,9 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   // singles
   contract(c, one, a.R1, "kie", Fvv, "ea", a.S1, "kia");
   contract(c, mone, a.R1, "kma", Foo, "im", a.S1, "kia");
-  contract(c, half, a.R2, "kimef", Wvvvo, "efam", a.S1, "kia");
+  contract(c, half, a.R2, "kimef", ten(c->WvvvoL, {v, o, v, v}), "amef", a.S1, "kia");  // W^ef_am as [a][m][e][f]
   contract(c, half, a.R2, "kmnea", Wovoo, "iemn", a.S1, "kia");  // l^mn_ae = -l^mn_ea
-  contract(c, mone, Gvv, "kfe", Wvovv, "eifa", a.S1, "kia");
+  contract(c, mone, Gvv, "kfe", ten(c->WvovvL, {o, v, v, v}), "iafe", a.S1, "kia");  // W^ei_fa as [i][a][f][e]
   contract(c, mone, Goo, "knm", Wooov, "mina", a.S1, "kia");
   contract(c, one, a.R1, "kme", WL, "meia", a.S1, "kia");  // W^ie_am = WL[m][e][i][a]
   // doubles

@@ -570,3 +570,209 @@ int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rh
   const double inner = c->opt.prec == CCLR_FP32 ? 1e-6 : 1e-4;
   return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter, c->opt.prec, inner);
 }
+
+// ------------------------------------------------------------ EOM-EE roots
+// Lowest eigenpairs of the Jacobian (right: A x = w x; left: x A = w x), the
+// EOM-EE excitation energies that are the poles of the response function
+// (SI, "EOM-EE sigma-vectors"; Davidson's method for a few eigenpairs of a
+// non-Hermitian matrix).  One subspace shared by all roots: orthonormal b_i,
+// s_i = A b_i, projected matrix H = B^H S (dense eigenproblem on the host),
+// Ritz pairs (theta_k, x_k = B y_k), residuals r_k = S y_k - theta_k x_k,
+// corrections (theta_k - D)^-1 r_k orthogonalized twice against the
+// subspace.  When the subspace is full it restarts from the Ritz vectors.
+#include "eigen_small.h"
+
+int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, std::vector<cplx>& omega,
+                 const VecSet& xout, cclr_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  const i64 ov = c->ns(), nd = c->nd(), n = ov + nd;
+  const int ms = std::max(std::min(120, std::max(c->opt.max_subspace, 4 * nroots)), 2 * nroots + 2);
+  REQUIRE(nroots >= 1 && nroots <= 30 && nroots <= n, CCLR_EINVAL, "nroots must be in [1, 30] and not above the dimension");
+  hipStream_t st = c->stream;
+  Arena::Mark mk = c->arena.mark();
+  auto vbuf = [&](int nvec) {
+    VecSet v;
+    v.s = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * ov));
+    v.d = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(nvec * nd));
+    v.n = nvec;
+    return v;
+  };
+  VecSet Bv = vbuf(ms), Sv = vbuf(ms), Rv = vbuf(nroots), Ev = vbuf(nroots);
+  const VS B{Bv.s, Bv.d, 0}, S{Sv.s, Sv.d, 0};  // shared by every root (slot stride 0)
+  const VS R{Rv.s, Rv.d, 1}, E{Ev.s, Ev.d, 1}, X{xout.s, xout.d, 1};
+  cplx* tmpv = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nroots * ms);
+  cplx* coef = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nroots * ms);
+  cplx* partial = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nroots * ms * kChunks);
+  int* act_d = (int*)c->arena.get(sizeof(int) * nroots);
+  cplx* z_d = (cplx*)c->arena.get(sizeof(cplx) * nroots);
+  int na = 0;
+  auto set_active = [&](const std::vector<int>& a) {
+    na = (int)a.size();
+    if (na) HIPCHK(hipMemcpyAsync(act_d, a.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
+  };
+  auto gram = [&](VS Xs, int xj0, int nj, VS Ys, int yj, cplx* out, int ld, int col0, int cj) {
+    if (nj <= 0 || na <= 0) return;
+    hipLaunchKernelGGL(k_gram, dim3(kChunks, nj, na), dim3(kThreads), 0, st, Xs, xj0, nj, Ys, yj, act_d, ov, nd, partial);
+    hipLaunchKernelGGL(k_reduce, dim3(na * nj), dim3(kThreads), 0, st, partial, nj, act_d, out, ld, col0, cj);
+  };
+  auto lincomb = [&](VS out, int oj, VS Xs, int xj0, int nj, const cplx* cf, int ldc, int acc) {
+    hipLaunchKernelGGL(k_lincomb, dim3(vgrid(n), na), dim3(kThreads), 0, st, out, oj, Xs, xj0, nj, cf, ldc, 1.0, Xs, 0,
+                       0, acc, act_d, ov, nd);
+  };
+  auto fetch = [&](const cplx* src, std::vector<cplx>& h, size_t count) {
+    h.resize(count);
+    HIPCHK(hipMemcpyAsync(h.data(), src, sizeof(cplx) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  };
+  auto sigma = (side == CCLR_RIGHT) ? sigma_right : sigma_left;
+  // transforms s_j = A b_j for j in [j0, j1)
+  long nsigma = 0;
+  auto transform = [&](int j0, int j1) {
+    VecSet in{Bv.s + (i64)j0 * ov, Bv.d + (i64)j0 * nd, j1 - j0}, out{Sv.s + (i64)j0 * ov, Sv.d + (i64)j0 * nd, j1 - j0};
+    sigma(c, in, out, nullptr);
+    nsigma += j1 - j0;
+  };
+  // orthonormalize E[k] against b_0..b_{m-1} (classical Gram-Schmidt twice) and store it as b_m;
+  // returns false if nothing new is left
+  auto append = [&](int k, int m) {
+    std::vector<int> one{k};
+    set_active(one);
+    std::vector<cplx> hv;
+    gram(E, 0, 1, E, 0, tmpv, 1, 0, 0);  // |e_k|^2 at tmpv[k]
+    fetch(tmpv + k, hv, 1);
+    const double n0 = std::sqrt(std::max(hv[0].x, 0.0));
+    for (int pass = 0; pass < 2 && m > 0; ++pass) {
+      gram(B, 0, m, E, 0, coef, ms, 0, 0);
+      hipLaunchKernelGGL(k_lincomb, dim3(vgrid(n), 1), dim3(kThreads), 0, st, E, 0, B, 0, m, coef, ms, -1.0, E, 0, 0, 1,
+                         act_d, ov, nd);
+    }
+    gram(E, 0, 1, E, 0, tmpv, 1, 0, 0);
+    fetch(tmpv + k, hv, 1);
+    const double n1 = std::sqrt(std::max(hv[0].x, 0.0));
+    if (!(n1 > 1e-3 * n0) || !(n1 > 0.0)) return false;
+    hipLaunchKernelGGL(k_scale, dim3(vgrid(n), 1), dim3(kThreads), 0, st, B, m, E, 0, z_d, c->diag.c(), tmpv, 1, act_d,
+                       ov, nd);
+    return true;
+  };
+  // ---- start: unit vectors on the smallest Re D
+  std::vector<cplx> dh;
+  fetch(c->diag.c(), dh, (size_t)n);
+  std::vector<i64> idx(n);
+  for (i64 e = 0; e < n; ++e) idx[e] = e;
+  const int nstart = std::min<i64>(n, std::min(ms / 2, 2 * nroots));
+  std::partial_sort(idx.begin(), idx.begin() + nstart, idx.end(),
+                    [&](i64 a, i64 b) { return dh[a].x < dh[b].x || (dh[a].x == dh[b].x && a < b); });
+  launch_fill(Bv.s, (i64)ms * ov, cx(0.0), st);
+  launch_fill(Bv.d, (i64)ms * nd, cx(0.0), st);
+  const cplx one_c = cx(1.0);
+  for (int j = 0; j < nstart; ++j) {
+    const i64 e = idx[j];
+    cplx* p = e < ov ? Bv.s + (i64)j * ov + e : Bv.d + (i64)j * nd + (e - ov);
+    HIPCHK(hipMemcpyAsync(p, &one_c, sizeof(cplx), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  int m = nstart;
+  transform(0, m);
+  std::vector<eigsmall::zc> H((size_t)ms * ms, 0.0);
+  auto update_H = [&](int j0, int j1) {  // rows and columns of H for the new vectors j0..j1-1
+    std::vector<int> zero{0};
+    set_active(zero);
+    std::vector<cplx> hv;
+    for (int j = j0; j < j1; ++j) {
+      gram(B, 0, j + 1, S, j, tmpv, ms, 0, 0);  // H[i][j] = <b_i, s_j>, i <= j
+      fetch(tmpv, hv, (size_t)(j + 1));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * ms + j] = eigsmall::zc(hv[i].x, hv[i].y);
+      if (j > 0) {
+        gram(S, 0, j, B, j, tmpv, ms, 0, 1);  // H[j][i] = <b_j, s_i>, i < j
+        fetch(tmpv, hv, (size_t)j);
+        for (int i = 0; i < j; ++i) H[(size_t)j * ms + i] = eigsmall::zc(hv[i].x, hv[i].y);
+      }
+    }
+  };
+  update_H(0, m);
+  const int maxit = std::max(1, maxit_in);
+  int iters = 0;
+  std::vector<double> res(nroots, 1e300);
+  omega.assign(nroots, cx(0.0));
+  bool conv = false;
+  std::vector<int> roots(nroots);
+  for (int k = 0; k < nroots; ++k) roots[k] = k;
+  while (true) {
+    ++iters;
+    // Ritz pairs of the projected matrix
+    std::vector<eigsmall::zc> Hm((size_t)m * m), w, V;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Hm[(size_t)i * m + j] = H[(size_t)i * ms + j];
+    REQUIRE(eigsmall::eig(m, Hm, w, V), CCLR_ENOTCONV, "projected eigenproblem did not converge");
+    std::vector<int> ord(m);
+    for (int i = 0; i < m; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
+    std::vector<cplx> cf((size_t)nroots * ms, cx(0.0)), cf2((size_t)nroots * ms, cx(0.0));
+    for (int k = 0; k < nroots; ++k) {
+      const eigsmall::zc th = w[ord[k]];
+      omega[k] = cx(th.real(), th.imag());
+      for (int i = 0; i < m; ++i) {
+        const eigsmall::zc y = V[(size_t)i * m + ord[k]];
+        cf[(size_t)k * ms + i] = cx(y.real(), y.imag());
+        const eigsmall::zc t = -th * y;
+        cf2[(size_t)k * ms + i] = cx(t.real(), t.imag());
+      }
+    }
+    set_active(roots);
+    HIPCHK(hipMemcpyAsync(coef, cf.data(), sizeof(cplx) * cf.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(z_d, omega.data(), sizeof(cplx) * nroots, hipMemcpyHostToDevice, st));
+    lincomb(X, 0, B, 0, m, coef, ms, 0);   // x_k = B y_k
+    lincomb(R, 0, S, 0, m, coef, ms, 0);   // r_k = S y_k ...
+    HIPCHK(hipMemcpyAsync(coef, cf2.data(), sizeof(cplx) * cf2.size(), hipMemcpyHostToDevice, st));
+    lincomb(R, 0, B, 0, m, coef, ms, 1);   // ... - theta_k B y_k
+    gram(R, 0, 1, R, 0, tmpv, 1, 0, 0);
+    std::vector<cplx> hv;
+    fetch(tmpv, hv, (size_t)nroots);
+    std::vector<int> open;
+    for (int k = 0; k < nroots; ++k) {
+      res[k] = std::sqrt(std::max(hv[k].x, 0.0));
+      if (!(res[k] <= tol)) open.push_back(k);
+    }
+    if (open.empty()) {
+      conv = true;
+      break;
+    }
+    if (iters >= maxit) break;
+    // corrections (theta_k - D)^-1 r_k
+    set_active(open);
+    hipLaunchKernelGGL(k_scale, dim3(vgrid(n), na), dim3(kThreads), 0, st, E, 0, R, 0, z_d, c->diag.c(), nullptr, 0,
+                       act_d, ov, nd);
+    if (m + (int)open.size() > ms) {
+      // restart from the Ritz vectors: b = orthonormalized x_k, s = A b
+      int m2 = 0;
+      for (int k = 0; k < nroots; ++k) {
+        HIPCHK(hipMemcpyAsync(Ev.s + (i64)k * ov, xout.s + (i64)k * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(Ev.d + (i64)k * nd, xout.d + (i64)k * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, st));
+        if (append(k, m2)) ++m2;
+      }
+      m = m2;
+      transform(0, m);
+      std::fill(H.begin(), H.end(), eigsmall::zc(0.0));
+      update_H(0, m);
+      continue;
+    }
+    const int m0 = m;
+    for (int k : open)
+      if (append(k, m)) ++m;
+    if (m == m0) break;  // no new directions
+    transform(m0, m);
+    update_H(m0, m);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  c->arena.reset(mk);
+  double mx = 0.0;
+  for (double r : res) mx = std::max(mx, r);
+  if (info) {
+    info->iters = iters;
+    info->converged = conv ? 1 : 0;
+    info->resnorm = mx;
+    info->nsigma = nsigma;
+    info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return conv ? CCLR_OK : CCLR_ENOTCONV;
+}
