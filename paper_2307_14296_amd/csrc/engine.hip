@@ -462,6 +462,8 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
 void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   if (g.K <= 32 && launch_zgemm_smallk(g, c->stream)) return;
+  // inside reduced-precision transforms the remaining products run on FP32 MFMA as well
+  const bool lowp = c->sigma_prec != CCLR_FP64;
   const i64 tiles = (i64)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
   if (g.nb2 <= 1 && tiles < 512 && g.K >= 512) {
     i64 S = std::min<i64>((1024 + tiles - 1) / tiles, g.K / 256);
@@ -483,13 +485,15 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
       h.ar = 1.0;
       h.ai = 0.0;
       h.beta = 0;
-      launch_zgemm(h, c->stream);
+      if (lowp) launch_zgemm_lowp(h, CCLR_FP32, c->stream);
+      else launch_zgemm(h, c->stream);
       launch_splitk_reduce(g.batch, (int)S, g.M, g.N, W, g.C, g.sCb, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
       c->arena.reset(mk);
       return;
     }
   }
-  tuned_gemm(c, g);
+  if (lowp) launch_zgemm_lowp(g, CCLR_FP32, c->stream);
+  else tuned_gemm(c, g);
 }
 
 // Autotuner.  The first time a large product of a given shape class (M, N,

@@ -85,14 +85,20 @@ __device__ __forceinline__ bf8 neg_bf8(u4v x) { return __builtin_bit_cast(bf8, x
 #define MF(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0)
 
 // C[m][n] (+)= alpha * sum_k A[m][k] B[n][k] on split operands.  128x128
-// tile per workgroup, four waves of 64x64 (4x4 MFMA blocks of 16x16),
-// double-buffered LDS fed from registers.  Workgroups are numbered so that
-// each XCD (workgroups are dealt to the 8 XCDs round-robin) walks a
-// contiguous range of tiles, m fastest: the B tile of a step is shared by
-// the workgroups of one XCD and its L2.
-__global__ __launch_bounds__(256) void k_cgemm_bf16x3(const u4v* __restrict__ As, const u4v* __restrict__ Bs, int Mpad,
-                                                      int Npad, int nkc, int M, int N, cplx* __restrict__ C, i64 sCm,
-                                                      i64 sCn, double ar, double ai, int beta, int Mt, int T) {
+// tile per workgroup, NWM x NWN waves each owning a (128/NWM) x (128/NWN)
+// sub-tile of 16x16 MFMA blocks, double-buffered LDS fed from registers.
+// Workgroups are numbered so that each XCD (workgroups are dealt to the 8
+// XCDs round-robin) walks a contiguous range of tiles, m fastest: the B tile
+// of a step is shared by the workgroups of one XCD and its L2.
+template <int NWM, int NWN>
+__global__ __launch_bounds__(64 * NWM * NWN) void k_cgemm_bf16x3(const u4v* __restrict__ As, const u4v* __restrict__ Bs,
+                                                                 int Mpad, int Npad, int nkc, int M, int N,
+                                                                 cplx* __restrict__ C, i64 sCm, i64 sCn, double ar,
+                                                                 double ai, int beta, int Mt, int T) {
+  constexpr int NT = 64 * NWM * NWN;       // threads
+  constexpr int WM = TB / NWM, WN = TB / NWN;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LQ = TB * 16 / NT;          // 16-byte chunks per thread per operand and k step
   __shared__ u4v sA[2][TB * RS];
   __shared__ u4v sB[2][TB * RS];
   const int per = gridDim.x >> 3;
@@ -100,31 +106,31 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(const u4v* __restrict__ As
   if (t >= T) return;
   const int m0 = (t % Mt) * TB, n0 = (t / Mt) * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  const int wm = (wave % NWM) * WM, wn = (wave / NWM) * WN;
   const int rr = lane & 15, g = lane >> 4;
-  u4v pa[8], pb[8];
+  u4v pa[LQ], pb[LQ];
   auto gload = [&](int kc) {
     const u4v* a = As + ((i64)kc * Mpad + m0) * 16;
     const u4v* b = Bs + ((i64)kc * Npad + n0) * 16;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      pa[q] = a[tid + q * 256];
-      pb[q] = b[tid + q * 256];
+    for (int q = 0; q < LQ; ++q) {
+      pa[q] = a[tid + q * NT];
+      pb[q] = b[tid + q * NT];
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + q * 256;
+    for (int q = 0; q < LQ; ++q) {
+      const int e = tid + q * NT;
       sA[buf][(e >> 4) * RS + (e & 15)] = pa[q];
       sB[buf][(e >> 4) * RS + (e & 15)] = pb[q];
     }
   };
-  f4 cr[4][4], ci[4][4];
+  f4 cr[FM][FN], ci[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < FN; ++j) {
       cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -135,13 +141,13 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(const u4v* __restrict__ As
   for (int kc = 0; kc < nkc; ++kc) {
     const bool more = kc + 1 < nkc;
     if (more) gload(kc + 1);
-    bf8 b[4][4];  // [j][plane]
+    bf8 b[FN][4];  // [j][plane]
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int p = 0; p < 4; ++p) b[j][p] = as_bf8(sB[buf][(wn + 16 * j + rr) * RS + p * 4 + g]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < FM; ++i) {
       u4v a[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) a[p] = sA[buf][(wm + 16 * i + rr) * RS + p * 4 + g];
@@ -149,32 +155,32 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(const u4v* __restrict__ As
       const bf8 naih = neg_bf8(a[2]), nail = neg_bf8(a[3]);
       // small terms first
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FN; ++j) {
         cr[i][j] = MF(arl, b[j][0], cr[i][j]);
         ci[i][j] = MF(arl, b[j][2], ci[i][j]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FN; ++j) {
         cr[i][j] = MF(arh, b[j][1], cr[i][j]);
         ci[i][j] = MF(arh, b[j][3], ci[i][j]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FN; ++j) {
         cr[i][j] = MF(nail, b[j][2], cr[i][j]);
         ci[i][j] = MF(ail, b[j][0], ci[i][j]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FN; ++j) {
         cr[i][j] = MF(naih, b[j][3], cr[i][j]);
         ci[i][j] = MF(aih, b[j][1], ci[i][j]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FN; ++j) {
         cr[i][j] = MF(arh, b[j][0], cr[i][j]);
         ci[i][j] = MF(arh, b[j][2], ci[i][j]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FN; ++j) {
         cr[i][j] = MF(naih, b[j][2], cr[i][j]);
         ci[i][j] = MF(aih, b[j][0], ci[i][j]);
       }
@@ -185,9 +191,9 @@ __global__ __launch_bounds__(256) void k_cgemm_bf16x3(const u4v* __restrict__ As
   }
   // output block (i, j): row 16i + 4*(lane/16) + r, column 16j + lane%16
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + 4 * g + r;
@@ -236,14 +242,20 @@ SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int
 }
 
 void launch_cgemm_bf16x3(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
-                         int beta, hipStream_t st) {
+                         int beta, hipStream_t st, int variant) {
   REQUIRE(A.K == B.K && A.nkc == B.nkc, CCLR_EINVAL, "split GEMM: operands differ in K");
   REQUIRE(A.p && B.p, CCLR_EINVAL, "split GEMM: operand not split");
   const int Mt = A.rows_pad / TB, Nt = B.rows_pad / TB;
   const i64 T = (i64)Mt * Nt;
   REQUIRE(T < (i64)1 << 30, CCLR_EINVAL, "split GEMM: too many tiles");
   const i64 grid = (T + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_cgemm_bf16x3, dim3((unsigned)grid), dim3(256), 0, st, (const u4v*)A.p, (const u4v*)B.p,
-                     A.rows_pad, B.rows_pad, A.nkc, A.rows, B.rows, C, sCm, sCn, ar, ai, beta, Mt, (int)T);
+  if (variant == 1)
+    hipLaunchKernelGGL((k_cgemm_bf16x3<2, 4>), dim3((unsigned)grid), dim3(512), 0, st, (const u4v*)A.p,
+                       (const u4v*)B.p, A.rows_pad, B.rows_pad, A.nkc, A.rows, B.rows, C, sCm, sCn, ar, ai, beta, Mt,
+                       (int)T);
+  else
+    hipLaunchKernelGGL((k_cgemm_bf16x3<2, 2>), dim3((unsigned)grid), dim3(256), 0, st, (const u4v*)A.p,
+                       (const u4v*)B.p, A.rows_pad, B.rows_pad, A.nkc, A.rows, B.rows, C, sCm, sCn, ar, ai, beta, Mt,
+                       (int)T);
   HIPCHK(hipGetLastError());
 }

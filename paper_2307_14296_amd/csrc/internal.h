@@ -135,8 +135,9 @@ size_t split_bytes(int rows, int K);
 // dst <- split of op(src)[r][k] = src[r*sR + k*sK] (conjugated if conj)
 SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, hipStream_t s);
 // C[m][n] (+)= alpha * sum_k A[m][k] B[n][k], three bf16 products per real product, FP32 accumulation
+// variant 0: four waves of 64x64, variant 1: eight waves of 64x32 (more latency hiding)
 void launch_cgemm_bf16x3(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
-                         int beta, hipStream_t s);
+                         int beta, hipStream_t s, int variant = 0);
 // products with K <= 32 on the vector ALU (returns false if the form does not apply)
 bool launch_zgemm_smallk(const GemmArgs& g, hipStream_t s);
 // C[b][m][n] = (beta ? C : 0) + alpha * sum_s W[b][s][m][n]

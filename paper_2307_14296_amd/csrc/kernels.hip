@@ -421,9 +421,16 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const i64 bz = blockIdx.z;
-  const int kbeg = 0, kend = g.K;
-  const cplx* __restrict__ A = g.A + boff(g, bz, g.sAb, g.sAb2);
-  const cplx* __restrict__ B = g.B + boff(g, bz, g.sBb, g.sBb2);
+  int kbeg = 0, kend = g.K;
+  i64 bb = bz;  // batch index of the operands (the K chunk is folded into bz when splitting)
+  if (g.kchunk > 0) {
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
+  }
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
   const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
   const float sa = g.conjA ? -1.f : 1.f, sb = g.conjB ? -1.f : 1.f;
   cplx ra[LA], rb[LB];
@@ -781,7 +788,6 @@ void launch_zgemm(const GemmArgs& g, hipStream_t s) { launch_zgemm_variant(g, ge
 
 void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
-  REQUIRE(g.kchunk == 0, CCLR_EINVAL, "low-precision GEMM: no K splitting");
   REQUIRE(prec == CCLR_FP32, CCLR_EINVAL, "low-precision GEMM: only CCLR_FP32 is available");
   const bool ak = g.sAk == 1, bn = g.sBn == 1;
   dim3 grid((g.M + 127) / 128, (g.N + 63) / 64, g.batch);

@@ -55,7 +55,36 @@ void op_gemm(cclr_ctx* c, const GemmArgs& g, int which) {
   Arena::Mark mk = c->arena.mark();
   void* ws = c->arena.get(split_bytes(g.M, g.K));
   const SplitMat A = launch_split_bf16(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, ws, c->stream);
-  launch_cgemm_bf16x3(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
+  // kernel variant (wave layout) timed once per shape
+  const auto key = std::make_tuple(g.M, g.N, g.K, 1, 200 + which);
+  auto it = c->gemm_choice.find(key);
+  int var = 0;
+  if (it != c->gemm_choice.end()) {
+    var = it->second;
+  } else if (c->autotune && !g.beta) {  // timing runs overwrite C
+    std::vector<double> ms;
+    double best = 1e300;
+    for (int v = 0; v < 2; ++v) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventRecord(e0, c->stream));
+      launch_cgemm_bf16x3(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream, v);
+      HIPCHK(hipEventRecord(e1, c->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      ms.push_back(t);
+      if (t < best) best = t, var = v;
+    }
+    c->gemm_choice[key] = var;
+    c->gemm_tuning_log.push_back({"bf16x3 " + std::to_string(g.M) + "x" + std::to_string(g.N) + "x" +
+                                      std::to_string(g.K) + " op" + std::to_string(which),
+                                  ms});
+  }
+  launch_cgemm_bf16x3(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream, var);
   c->arena.reset(mk);
 }
 
