@@ -177,6 +177,30 @@ int cclr_response_function(cclr_ctx* ctx, int nx, const cclr_c64* const* X,
                            int nfreq, const double* omega, const double* gamma,
                            cclr_c64* out, cclr_solve_info* info);
 
+/* The CC-CI (EOM-CC) response function (eq. CC-CI response function) with
+ * the same conventions as cclr_response_function:
+ *   out[w][p][q] = 1/2 [ h_pq(z) + conj h_pq(-conj z) ],
+ *   h_pq(z) = Eeta^p t^q(z) + Eeta^q t^p(-z)
+ *             - (lambda . t^p(-z)) (lambda . xi^q) - (lambda . t^q(z)) (lambda . xi^p),
+ * with the EOM eta vector Eeta^X (SI: the singles of eta^X plus
+ * lambda^ij_ab xi^X_jb, the doubles of eta^X) and "." the sum over unique
+ * excitations.  The response solves are those of the CC-CC form; no Hessian
+ * product is needed. */
+int cclr_response_function_ci(cclr_ctx* ctx, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
+                              const double* gamma, cclr_c64* out, cclr_solve_info* info);
+
+/* The CC-CC response function in the asymmetric form (the eq. following the
+ * CC-CI response function): for nx operators X and ny operators Y,
+ *   out[w][p][q] = <<X_p; Y_q>>_z = 1/2 [ a_pq(z) + conj a_pq(-conj z) ],
+ *   a_pq(f) = eta^{X_p} . t^{Y_q}(f) + tbar^{Y_q}(f) . xi^{X_p},
+ * with the multiplier responses tbar^Y(f) (A + f) = -(eta^Y + F t^Y(f)).
+ * Response equations are solved for the Y operators only (right and left,
+ * at z and -conj z), which pays off when ny << nx.  Equal to
+ * cclr_response_function for X = Y.  out: HOST array nfreq*nx*ny. */
+int cclr_response_function_asym(cclr_ctx* ctx, int nx, const cclr_c64* const* X, int ny, const cclr_c64* const* Y,
+                                int nfreq, const double* omega, const double* gamma, cclr_c64* out,
+                                cclr_solve_info* info);
+
 /* Gradient of the response function (adjoint of cclr_response_function).
  * For the real scalar
  *   L = Re sum_{w,p,q} conj(G[w][p][q]) * out[w][p][q]

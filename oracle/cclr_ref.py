@@ -16,7 +16,10 @@ Cluster Theory for GPU-accelerated Computer Architectures"):
 * damped response solutions (A - (w + i g)) t^Y = -xi^Y (eq. LR response
   equation_cpp) by dense LU or by GMRES,
 * the symmetric CC-CC response function (eq. CC-CC response function, with
-  the permutation P and the conjugation symmetrizer C^{+-w}).
+  the permutation P and the conjugation symmetrizer C^{+-w}), and the CC-CI
+  (EOM-CC) response function (eq. CC-CI response function, EOM eta vector),
+  and the asymmetric CC-CC form with multiplier responses (eq. asymmetric
+  form of the response function).
 
 Conventions.  Indices i,j,k,l,m,n,o are occupied, a..g virtual; sums are
 unrestricted (Einstein).  Arrays: t1[i,a] = t^a_i, t2[i,j,a,b] = t^ab_ij,
@@ -228,6 +231,14 @@ def eta(H: Hamiltonian, X, t1, t2, lam1, lam2):
     return e1, e2
 
 
+def eom_eta(H: Hamiltonian, X, t1, t2, lam1, lam2):
+    """^EOM eta^X (SI, EOM eta vector): the singles of eta^X plus
+    lambda^ij_ab xi^X_jb; the doubles are those of eta^X."""
+    e1, e2 = eta(H, X, t1, t2, lam1, lam2)
+    x1, _ = xi(H, X, t1, t2)
+    return e1 + einsum("ijab,jb->ia", lam2, x1), e2
+
+
 def eta0(H: Hamiltonian, hb):
     """eta^0_mu = <R|[H, tau_mu]|CC>, the right-hand side of the Lambda
     equation (theory section, eq. Lambda; Table 1 with X -> H0 and
@@ -402,6 +413,63 @@ class CCLR:
 
     def tF(self, x):
         return tF(self.H, self.hb, self.t1, self.t2, *self.lam, *x)
+
+    def response_asym(self, Xs, Ys, z, method="dense"):
+        """Asymmetric CC-CC form (eq. asymmetric response function):
+          <<X;Y>>_z = 1/2 [ a(z) + conj a(-z*) ],  a_XY(z) = eta^X t^Y(z) + tbar^Y(z) xi^X,
+        with the multiplier response tbar^Y(z) (A + z) = -(eta^Y + F t^Y(z)).
+        Only the Y operators need response solves (right and left)."""
+        if self.lam is None:
+            self.solve_lambda(method)
+        z = complex(z)
+        xX = [self.xi(X) for X in Xs]
+        eX = [self.eta(X) for X in Xs]
+        out = np.empty((len(Xs), len(Ys)), dtype=np.complex128)
+
+        def a_of(w):
+            res = np.empty((len(Xs), len(Ys)), dtype=np.complex128)
+            for q, Y in enumerate(Ys):
+                tY = self.solve("right", self.xi(Y), w, method)
+                eY, fY = self.eta(Y), self.tF(tY)
+                tb = self.solve("left", (eY[0] + fY[0], eY[1] + fY[1]), -w, method)
+                for p in range(len(Xs)):
+                    res[p, q] = dot(eX[p], tY) + dot(tb, xX[p])
+            return res
+
+        out[:] = 0.5 * (a_of(z) + np.conj(a_of(-z.conjugate())))
+        return out
+
+    def eom_eta(self, X):
+        return eom_eta(self.H, X, self.t1, self.t2, *self.lam)
+
+    def response_ci(self, Xs, z, method="dense"):
+        """CC-CI (EOM-CC) response function (eq. CC-CI response function) with
+        the same P(X,Y) and C^{+-w} readings as response():
+          <<X;Y>>_z = 1/2 [ h(z) + conj h(-z*) ],
+          h_XY(z) = Eeta^X t^Y(z) + Eeta^Y t^X(-z)
+                    - (lambda t^X(-z)) (lambda xi^Y) - (lambda t^Y(z)) (lambda xi^X),
+        Eeta the EOM eta vector, lambda . v over unique excitations."""
+        if self.lam is None:
+            self.solve_lambda(method)
+        z = complex(z)
+        freqs = {}
+        for w in (z, -z, z.conjugate(), -z.conjugate()):
+            freqs.setdefault(w, None)
+        xis = [self.xi(X) for X in Xs]
+        eetas = [self.eom_eta(X) for X in Xs]
+        tX = {w: [self.solve("right", x, w, method) for x in xis] for w in freqs}
+        lxi = [dot(self.lam, x) for x in xis]
+        nx = len(Xs)
+
+        def h(p, q, w):
+            return (dot(eetas[p], tX[w][q]) + dot(eetas[q], tX[-w][p])
+                    - dot(self.lam, tX[-w][p]) * lxi[q] - dot(self.lam, tX[w][q]) * lxi[p])
+
+        out = np.empty((nx, nx), dtype=np.complex128)
+        for p in range(nx):
+            for q in range(nx):
+                out[p, q] = 0.5 * (h(p, q, z) + np.conj(h(p, q, -z.conjugate())))
+        return out
 
     def response(self, Xs, z, method="dense"):
         """<<X_p; X_q>>_z for all pairs, z = w + i*gamma (complex).

@@ -26,7 +26,8 @@ CCLR_RIGHT, CCLR_LEFT = 0, 1
 EXPORTED = (
     "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_amplitudes",
     "cclr_jacobian_right", "cclr_jacobian_left", "cclr_jacobian_right_multi", "cclr_solve_damped", "cclr_eom_ee", "cclr_solve_lambda", "cclr_get_lambda",
-    "cclr_response_function", "cclr_response_backward", "cclr_last_error",
+    "cclr_response_function", "cclr_response_function_ci", "cclr_response_function_asym", "cclr_response_backward",
+    "cclr_last_error",
 )
 
 
@@ -75,6 +76,9 @@ def lib():
     L.cclr_eom_ee.argtypes = [P, I, I, ctypes.c_double, P, P, P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_get_lambda.argtypes = [P, P, P]
     L.cclr_response_function.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(cclr_solve_info)]
+    L.cclr_response_function_ci.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(cclr_solve_info)]
+    L.cclr_response_function_asym.argtypes = [P, I, ctypes.POINTER(P), I, ctypes.POINTER(P), I, D, D, P,
+                                              ctypes.POINTER(cclr_solve_info)]
     L.cclr_response_backward.argtypes = [P, I, ctypes.POINTER(P), I, D, D, P, ctypes.POINTER(P), P,
                                          ctypes.POINTER(P), ctypes.POINTER(cclr_solve_info)]
     L.cclr_last_error.argtypes = [P]
@@ -209,15 +213,31 @@ def cclr_get_lambda(ctx, l1, l2):
     return _check(ctx, lib().cclr_get_lambda(ctx, _ptr(l1, "l1"), _ptr(l2, "l2")))
 
 
-def cclr_response_function(ctx, X, omega, gamma):
-    """Returns (rc, out[nfreq][nx][nx] as a host numpy complex128 array, info)."""
+def cclr_response_function(ctx, X, omega, gamma, model="cc"):
+    """Returns (rc, out[nfreq][nx][nx] as a host numpy complex128 array, info).
+    model: "cc" (CC-CC, cclr_response_function) or "ci" (CC-CI, cclr_response_function_ci)."""
     import numpy as np
     nx, nf = len(X), len(omega)
     ptrs = (ctypes.c_void_p * nx)(*[_ptr(x, "X").value for x in X])
     out = np.zeros((max(nf, 1), nx, nx), dtype=np.complex128)
     info = cclr_solve_info()
-    rc = lib().cclr_response_function(ctx, nx, ptrs, nf, _dbl(omega), _dbl(gamma),
+    fn = {"cc": lib().cclr_response_function, "ci": lib().cclr_response_function_ci}[model]
+    rc = fn(ctx, nx, ptrs, nf, _dbl(omega), _dbl(gamma),
                                       ctypes.c_void_p(out.ctypes.data), ctypes.byref(info))
+    _check(ctx, rc, allow_notconv=True)
+    return rc, out[:nf], info
+
+
+def cclr_response_function_asym(ctx, X, Y, omega, gamma):
+    """<<X_p; Y_q>> from responses of the Y operators only; returns (rc, out[nfreq][nx][ny], info)."""
+    import numpy as np
+    nx, ny, nf = len(X), len(Y), len(omega)
+    px = (ctypes.c_void_p * nx)(*[_ptr(x, "X").value for x in X])
+    py = (ctypes.c_void_p * ny)(*[_ptr(y, "Y").value for y in Y])
+    out = np.zeros((max(nf, 1), nx, ny), dtype=np.complex128)
+    info = cclr_solve_info()
+    rc = lib().cclr_response_function_asym(ctx, nx, px, ny, py, nf, _dbl(omega), _dbl(gamma),
+                                           ctypes.c_void_p(out.ctypes.data), ctypes.byref(info))
     _check(ctx, rc, allow_notconv=True)
     return rc, out[:nf], info
 

@@ -411,8 +411,10 @@ int cclr_get_lambda(const cclr_ctx* cc, cclr_c64* l1, cclr_c64* l2) {
   });
 }
 
-int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
-                           const double* gamma, cclr_c64* out, cclr_solve_info* info) {
+// model 0: CC-CC (eq. CC-CC response function); model 1: CC-CI (eq. CC-CI
+// response function, EOM eta vector)
+static int response_impl(cclr_ctx* c, int model, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
+                         const double* gamma, cclr_c64* out, cclr_solve_info* info) {
   if (!c) return CCLR_EINVAL;
   return guarded(c, [&]() -> int {
     auto t0 = std::chrono::steady_clock::now();
@@ -441,6 +443,12 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
       VecSet a{xi.s + p * ov, xi.d + p * nd, 1}, b{eta.s + p * ov, eta.d + p * nd, 1};
       build_xi(c, (const cplx*)X[p], a);
       build_eta(c, (const cplx*)X[p], b);
+    }
+    if (model == 1) {  // EOM eta: singles + lambda^ij_ab xi^X_jb
+      const i64 o = c->o, v = c->v;
+      Ten l2 = tmp(c, {o, o, v, v});
+      launch_unpack(1, (int)o, (int)v, c->lam_s.c(), c->lam_d.c(), nullptr, l2.p, c->stream);
+      contract(c, cx(1.0), l2, "ijab", ten(xi.s, {(i64)nx, o, v}), "Zjb", ten(eta.s, {(i64)nx, o, v}), "Zia");
     }
     // distinct solve frequencies: z, -z, conj z, -conj z for every requested z
     std::vector<std::complex<double>> fr;
@@ -477,6 +485,7 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
     for (int w = 0; w < nfreq; ++w)
       for (int f : {idmz[w], idcz[w]})
         if (std::find(xside_f.begin(), xside_f.end(), f) == xside_f.end()) xside_f.push_back(f);
+    if (model == 1) xside_f.clear();  // no Hessian term in the CC-CI form
     const int ntf = (int)xside_f.size() * nx;
     VecSet tfin = packed_buf(c, ntf), tfo = packed_buf(c, ntf);
     std::map<int, int> tf_slot;  // solution index r -> Hessian-product slot
@@ -487,7 +496,7 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
         HIPCHK(hipMemcpyAsync(tfin.s + k * ov, sol.s + r * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(tfin.d + k * nd, sol.d + r * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, c->stream));
       }
-    hessian_product(c, tfin, tfo);
+    if (ntf > 0) hessian_product(c, tfin, tfo);
     // bilinear products
     auto vs = [&](const VecSet& s, int k) { return std::make_pair(s.s + k * ov, s.d + k * nd); };
     std::vector<const cplx*> hx_s, hx_d, hy_s, hy_d;
@@ -500,6 +509,12 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
       for (int r = 0; r < nr; ++r) eta_t[{p, r}] = add(vs(eta, p), vs(sol, r));
     for (const auto& kv : tf_slot)
       for (int r2 = 0; r2 < nr; ++r2) tf_t[{kv.first, r2}] = add(vs(tfo, kv.second), vs(sol, r2));
+    std::vector<int> lam_t(nr), lam_xi(nx);  // lambda . t_r and lambda . xi_p
+    if (model == 1) {
+      const auto lam = std::make_pair(c->lam_s.c(), c->lam_d.c());
+      for (int r = 0; r < nr; ++r) lam_t[r] = add(lam, vs(sol, r));
+      for (int p = 0; p < nx; ++p) lam_xi[p] = add(lam, vs(xi, p));
+    }
     const int np = (int)hx_s.size();
     const cplx** pd = (const cplx**)c->arena.get(sizeof(cplx*) * 4 * np);
     std::vector<const cplx*> all;
@@ -516,8 +531,11 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
     HIPCHK(hipStreamSynchronize(c->stream));
     auto C = [&](int k) { return std::complex<double>(hd[k].x, hd[k].y); };
     // g_pq(z) = eta^p t^q(z) + eta^q t^p(-z) + F t^p(-z) t^q(z)
+    // CC-CI: h_pq(z) = Eeta^p t^q(z) + Eeta^q t^p(-z) - (lambda t^p(-z))(lambda xi^q) - (lambda t^q(z))(lambda xi^p)
     auto g = [&](int p, int q, int fz, int fmz) {
       const int rq = fz * nx + q, rpm = fmz * nx + p;
+      if (model == 1)
+        return C(eta_t[{p, rq}]) + C(eta_t[{q, rpm}]) - C(lam_t[rpm]) * C(lam_xi[q]) - C(lam_t[rq]) * C(lam_xi[p]);
       return C(eta_t[{p, rq}]) + C(eta_t[{q, rpm}]) + C(tf_t[{rpm, rq}]);
     };
     for (int w = 0; w < nfreq; ++w)
@@ -535,6 +553,134 @@ int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
       info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV) return CCLR_ENOTCONV;
+    return CCLR_OK;
+  });
+}
+
+int cclr_response_function(cclr_ctx* c, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
+                           const double* gamma, cclr_c64* out, cclr_solve_info* info) {
+  return response_impl(c, 0, nx, X, nfreq, omega, gamma, out, info);
+}
+
+int cclr_response_function_ci(cclr_ctx* c, int nx, const cclr_c64* const* X, int nfreq, const double* omega,
+                              const double* gamma, cclr_c64* out, cclr_solve_info* info) {
+  return response_impl(c, 1, nx, X, nfreq, omega, gamma, out, info);
+}
+
+int cclr_response_function_asym(cclr_ctx* c, int nx, const cclr_c64* const* X, int ny, const cclr_c64* const* Y,
+                                int nfreq, const double* omega, const double* gamma, cclr_c64* out,
+                                cclr_solve_info* info) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    auto t0 = std::chrono::steady_clock::now();
+    require_t(c);
+    REQUIRE(nx >= 1 && ny >= 1 && X && Y && out, CCLR_EINVAL, "need nx, ny >= 1 perturbations and an output array");
+    check_freqs(nfreq, omega, gamma);
+    const i64 n = c->o + c->v, ov = c->ns(), nd = c->nd();
+    for (int p = 0; p < nx; ++p) check_ptr(X[p], "X");
+    for (int q = 0; q < ny; ++q) check_ptr(Y[q], "Y");
+    for (int p = 0; p < nx + ny; ++p) {
+      Arena::Mark mk = c->arena.mark();
+      check_finite(c, (const cplx*)(p < nx ? X[p] : Y[p - nx]), n * n, "X/Y");
+      c->arena.reset(mk);
+    }
+    cclr_solve_info linfo{}, rinfo{}, minfo{};
+    long nsig = 0;
+    int rc = CCLR_OK;
+    if (!c->have_lam) {
+      rc = solve_lambda_impl(c, &linfo);
+      nsig += linfo.nsigma;
+      if (rc < 0) return rc;
+    }
+    Arena::Mark mk = c->arena.mark();
+    VecSet xiX = packed_buf(c, nx), etX = packed_buf(c, nx), xiY = packed_buf(c, ny), etY = packed_buf(c, ny);
+    for (int p = 0; p < nx; ++p) {
+      build_xi(c, (const cplx*)X[p], VecSet{xiX.s + p * ov, xiX.d + p * nd, 1});
+      build_eta(c, (const cplx*)X[p], VecSet{etX.s + p * ov, etX.d + p * nd, 1});
+    }
+    for (int q = 0; q < ny; ++q) {
+      build_xi(c, (const cplx*)Y[q], VecSet{xiY.s + q * ov, xiY.d + q * nd, 1});
+      build_eta(c, (const cplx*)Y[q], VecSet{etY.s + q * ov, etY.d + q * nd, 1});
+    }
+    // frequencies z and -conj z of every request
+    std::vector<std::complex<double>> fr;
+    auto fid = [&](std::complex<double> w) {
+      for (size_t k = 0; k < fr.size(); ++k)
+        if (fr[k] == w) return (int)k;
+      fr.push_back(w);
+      return (int)fr.size() - 1;
+    };
+    std::vector<int> idz(nfreq), idmcz(nfreq);
+    for (int w = 0; w < nfreq; ++w) {
+      const std::complex<double> z(omega[w], gamma[w]);
+      idz[w] = fid(z);
+      idmcz[w] = fid(-std::conj(z));
+    }
+    const int nf = (int)fr.size(), nr = nf * ny;  // (f, q) at f*ny + q
+    VecSet rhs = packed_buf(c, nr), sol = packed_buf(c, nr), tf = packed_buf(c, nr), tb = packed_buf(c, nr);
+    std::vector<cplx> zr(nr), zl(nr);
+    for (int f = 0; f < nf; ++f)
+      for (int q = 0; q < ny; ++q) {
+        const int r = f * ny + q;
+        zr[r] = cx(fr[f].real(), fr[f].imag());
+        zl[r] = cx(-fr[f].real(), -fr[f].imag());
+        HIPCHK(hipMemcpyAsync(rhs.s + r * ov, xiY.s + q * ov, sizeof(cplx) * ov, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(rhs.d + r * nd, xiY.d + q * nd, sizeof(cplx) * nd, hipMemcpyDeviceToDevice, c->stream));
+      }
+    const int rs = solve_system(c, CCLR_RIGHT, nr, zr.data(), rhs, sol, &rinfo);
+    nsig += rinfo.nsigma;
+    // multiplier responses: tbar (A + f) = -(eta^Y + F t^Y(f))
+    hessian_product(c, sol, tf);
+    for (int f = 0; f < nf; ++f)
+      for (int q = 0; q < ny; ++q) {
+        const int r = f * ny + q;
+        launch_caxpy(ov, cx(1.0), etY.s + q * ov, tf.s + r * ov, c->stream);
+        launch_caxpy(nd, cx(1.0), etY.d + q * nd, tf.d + r * nd, c->stream);
+      }
+    const int ls = solve_system(c, CCLR_LEFT, nr, zl.data(), tf, tb, &minfo);
+    nsig += minfo.nsigma;
+    // a_pq(f) = eta^p . t^q(f) + tbar^q(f) . xi^p
+    std::vector<const cplx*> hx_s, hx_d, hy_s, hy_d;
+    for (int r = 0; r < nr; ++r)
+      for (int p = 0; p < nx; ++p) {
+        hx_s.push_back(etX.s + p * ov), hx_d.push_back(etX.d + p * nd);
+        hy_s.push_back(sol.s + r * ov), hy_d.push_back(sol.d + r * nd);
+        hx_s.push_back(tb.s + r * ov), hx_d.push_back(tb.d + r * nd);
+        hy_s.push_back(xiX.s + p * ov), hy_d.push_back(xiX.d + p * nd);
+      }
+    const int np = (int)hx_s.size();
+    const cplx** pd = (const cplx**)c->arena.get(sizeof(cplx*) * 4 * np);
+    std::vector<const cplx*> all;
+    all.insert(all.end(), hx_s.begin(), hx_s.end());
+    all.insert(all.end(), hx_d.begin(), hx_d.end());
+    all.insert(all.end(), hy_s.begin(), hy_s.end());
+    all.insert(all.end(), hy_d.begin(), hy_d.end());
+    HIPCHK(hipMemcpyAsync(pd, all.data(), sizeof(cplx*) * 4 * np, hipMemcpyHostToDevice, c->stream));
+    cplx* partial = (cplx*)c->arena.get(sizeof(cplx) * (size_t)np * 256);
+    cplx* dots = (cplx*)c->arena.get(sizeof(cplx) * np);
+    launch_bdot(np, pd, pd + np, pd + 2 * np, pd + 3 * np, ov, nd, partial, dots, c->stream);
+    std::vector<cplx> hd(np);
+    HIPCHK(hipMemcpyAsync(hd.data(), dots, sizeof(cplx) * np, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    auto a = [&](int f, int p, int q) {
+      const int k = 2 * ((f * ny + q) * nx + p);
+      return std::complex<double>(hd[k].x, hd[k].y) + std::complex<double>(hd[k + 1].x, hd[k + 1].y);
+    };
+    for (int w = 0; w < nfreq; ++w)
+      for (int p = 0; p < nx; ++p)
+        for (int q = 0; q < ny; ++q) {
+          const std::complex<double> val = 0.5 * (a(idz[w], p, q) + std::conj(a(idmcz[w], p, q)));
+          out[((i64)w * nx + p) * ny + q] = cclr_c64{val.real(), val.imag()};
+        }
+    c->arena.reset(mk);
+    if (info) {
+      info->iters = std::max(std::max(rinfo.iters, minfo.iters), linfo.iters);
+      info->converged = rinfo.converged && minfo.converged && (linfo.iters == 0 || linfo.converged);
+      info->resnorm = std::max(std::max(rinfo.resnorm, minfo.resnorm), linfo.resnorm);
+      info->nsigma = nsig;
+      info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV || ls == CCLR_ENOTCONV) return CCLR_ENOTCONV;
     return CCLR_OK;
   });
 }

@@ -158,6 +158,37 @@ def test_response_config1(cfg1):
     assert np.linalg.norm(out[0] - ref) / np.linalg.norm(ref) < TOL
 
 
+@pytest.mark.parametrize("zs", [[0.1 + 0.005j], [0.0, 0.3 + 0.01j]])
+def test_response_cc_ci_config1(cfg1, zs):
+    """CC-CI (EOM-CC) response function against the oracle's CC-CI form."""
+    pb, H, cc, g = cfg1
+    Xs = [s.dipole(pb, k).numpy() for k in range(3)]
+    rc, out, info = g.cc.cclr_response_function(g.ctx, [dev(X) for X in Xs], [z.real for z in zs],
+                                                [z.imag for z in zs], model="ci")
+    assert rc == 0, info.as_dict()
+    for w, z in enumerate(zs):
+        ref = cc.response_ci(Xs, z)
+        e = np.linalg.norm(out[w] - ref) / np.linalg.norm(ref)
+        print(f"CC-CI response z={z}: rel err {e:.2e}", flush=True)
+        assert e < TOL
+
+
+def test_response_asymmetric_config1(cfg1):
+    """Asymmetric form (responses of Y only) against the oracle's symmetric
+    function: the two forms are equal."""
+    pb, H, cc, g = cfg1
+    Xs = [s.dipole(pb, k).numpy() for k in range(3)]
+    Ys = [Xs[1]]
+    z = 0.1 + 0.005j
+    rc, out, info = g.cc.cclr_response_function_asym(g.ctx, [dev(X) for X in Xs], [dev(Y) for Y in Ys], [z.real],
+                                                     [z.imag])
+    assert rc == 0, info.as_dict()
+    ref = cc.response(Xs, z)[:, 1:2]
+    e = np.linalg.norm(out[0] - ref) / np.linalg.norm(ref)
+    print(f"asymmetric response: rel err {e:.2e}", flush=True)
+    assert e < TOL
+
+
 def test_error_paths(gpu):
     cc = _lib()
     with pytest.raises(cc.CclrError):

@@ -179,6 +179,49 @@ def test_response_equals_fci_sum_over_states(two_electron, z):
     assert np.abs(a - ex).max() <= 1e-12 * np.abs(ex).max()
 
 
+@pytest.mark.parametrize("z", [0.3 + 0.02j, 0.0, 0.45 + 0.01j])
+def test_cc_ci_response_equals_fci_sum_over_states(two_electron, z):
+    """Two electrons: EOM-CCSD is full CI, so the CC-CI response function
+    reproduces the exact sum over states as well."""
+    d = two_electron
+    cc = O.CCLR(d["H"], d["t1"], d["t2"])
+    a = cc.response_ci(d["Xs"], z)
+    ex = np.array([[B.fci_response(d["sp"], d["bf"].H, X, Y, z, d["state"]) for Y in d["Xs"]] for X in d["Xs"]])
+    assert np.abs(a - ex).max() <= 1e-11 * np.abs(ex).max()
+
+
+def test_cc_ci_differs_from_cc_cc_away_from_fci():
+    """At o=3 (CCSD no longer exact) the two models differ slightly, as the
+    paper reports for its molecules; a mistake that dropped the model
+    difference (e.g. Eeta = eta and no lambda-xi product) would not."""
+    pb, inst, H, t1, t2 = config_problem(3, 6, 4)
+    cc = O.CCLR(H, t1, t2)
+    Xs = [s.dipole(pb, 0).numpy(), s.dipole(pb, 1).numpy()]
+    a = cc.response(Xs, 0.2 + 0.01j)
+    b = cc.response_ci(Xs, 0.2 + 0.01j)
+    d = np.abs(a - b).max() / np.abs(a).max()
+    assert 1e-6 < d < 0.2
+
+
+def test_asymmetric_form_equals_symmetric_form(cfg1):
+    """The asymmetric form (multiplier responses for Y only) is the symmetric
+    form regrouped: the t^X(-z) terms equal tbar^Y(z) xi^X exactly."""
+    pb, cc, Xs = cfg1
+    for z in (0.1 + 0.005j, 0.0):
+        a = cc.response(Xs, z)
+        b = cc.response_asym(Xs, Xs, z)
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
+
+
+def test_asymmetric_form_equals_fci(two_electron):
+    d = two_electron
+    cc = O.CCLR(d["H"], d["t1"], d["t2"])
+    z = 0.3 + 0.02j
+    a = cc.response_asym(d["Xs"], d["Xs"][:1], z)
+    ex = np.array([[B.fci_response(d["sp"], d["bf"].H, X, Y, z, d["state"]) for Y in d["Xs"][:1]] for X in d["Xs"]])
+    assert np.abs(a - ex).max() <= 1e-11 * np.abs(ex).max()
+
+
 def test_response_pole_is_eigenvalue_of_jacobian(two_electron):
     """Near an eigenvalue w_n of A, Im alpha ~ |residue|/gamma: the damped
     response peaks at the poles, and the poles are eig(A) (= FCI gaps)."""
