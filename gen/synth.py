@@ -44,6 +44,7 @@ STREAM_V = 1
 STREAM_T1 = 2
 STREAM_VEC = 50          # + k : trial vectors
 STREAM_PERT = 100        # + k : perturbation matrices
+STREAM_CHOL = 3          # Cholesky vectors
 
 
 def _s64(x: int) -> int:
@@ -263,6 +264,19 @@ def excitation_vector(pb: Problem, k: int, device="cpu", std1: float = 1.0, std2
     r2 = cgauss(key, ctr, std2) * sgn
     r2 = torch.where(zero, torch.zeros_like(r2), r2)
     return r1.contiguous(), r2.contiguous()
+
+
+def cholesky_vectors(pb: Problem, nchol: int, device="cpu", std: float | None = None) -> torch.Tensor:
+    """nchol Hermitian n x n matrices L[P] = (G + G^H)/2 (complex Gaussian G),
+    the form of MO-basis Cholesky vectors of the Coulomb integrals.  The
+    default std puts sums of nchol products of entries at about the scale of
+    the directly drawn integrals."""
+    n = pb.n
+    if std is None:
+        std = math.sqrt(pb.vstd * math.sqrt(8.0) / math.sqrt(2.0 * nchol))
+    c = torch.arange(nchol * n * n, dtype=torch.int64, device=device)
+    g = cgauss(stream_key(pb.seed, STREAM_CHOL), c, std).view(nchol, n, n)
+    return (0.5 * (g + g.conj().transpose(1, 2))).contiguous()
 
 
 def instance(pb: Problem, device="cpu", with_blocks=True) -> dict:

@@ -19,7 +19,11 @@ Cluster Theory for GPU-accelerated Computer Architectures"):
   the permutation P and the conjugation symmetrizer C^{+-w}), and the CC-CI
   (EOM-CC) response function (eq. CC-CI response function, EOM eta vector),
   and the asymmetric CC-CC form with multiplier responses (eq. asymmetric
-  form of the response function).
+  form of the response function),
+* the CCSD ground state that feeds all of the above (implementation section,
+  first step): the residual Omega(t), the correlation energy, the CROP
+  solver that section names, and the integral blocks formed from Cholesky
+  vectors (computational details).
 
 Conventions.  Indices i,j,k,l,m,n,o are occupied, a..g virtual; sums are
 unrestricted (Einstein).  Arrays: t1[i,a] = t^a_i, t2[i,j,a,b] = t^ab_ij,
@@ -303,6 +307,110 @@ def tF(H: Hamiltonian, hb, t1, t2, lam1, lam2, x1, x2):
     d = d - 0.5 * Pij(einsum("ikab,jlcd,ijab->klcd", l2, Vv, x2))
     d = d - 0.5 * Pab(einsum("ijac,klbd,ijab->klcd", l2, Vv, x2))
     return s, d
+
+
+# ------------------------------------------------------ CCSD ground state
+def ccsd_residual(H: Hamiltonian, t1, t2):
+    """Omega_mu = <mu|e^-T H_N e^T|R>, the CCSD amplitude equations that the
+    first step of the implementation section solves for t.  The paper does not
+    print them; written here in the spin-orbital intermediate form of Stanton
+    and Gauss (J. Chem. Phys. 94, 4334 (1991)), with the diagonal Fock terms
+    kept in F so that the result is the residual itself (not a Jacobi update),
+    and every f_ov term kept (non-canonical references)."""
+    V, f = H.V, H.fb
+    tt = tau(t1, t2)
+    ts = t2 + 0.25 * Pij(Pab(einsum("ia,jb->ijab", t1, t1)))  # tau-tilde: half the singles products
+    Voovv = V("oovv")
+    Fae = (f("vv") - 0.5 * einsum("me,ma->ae", f("ov"), t1) + einsum("mf,mafe->ae", t1, V("ovvv"))
+           - 0.5 * einsum("mnaf,mnef->ae", ts, Voovv))
+    Fmi = (f("oo") + 0.5 * einsum("ie,me->mi", t1, f("ov")) + einsum("ne,mnie->mi", t1, V("ooov"))
+           + 0.5 * einsum("inef,mnef->mi", ts, Voovv))
+    Fme = f("ov") + einsum("nf,mnef->me", t1, Voovv)
+    # the two 1/4 tau <mn||ef> pieces (hole ladder and particle ladder) are
+    # combined into the hole-ladder intermediate, giving 1/2 tau there
+    w = einsum("je,mnie->mnij", t1, V("ooov"))
+    Wmnij = V("oooo") + (w - w.swapaxes(2, 3)) + 0.5 * einsum("ijef,mnef->mnij", tt, Voovv)
+    w = einsum("mb,amef->abef", t1, V("vovv"))
+    Wabef = V("vvvv") - (w - w.swapaxes(0, 1))
+    Wmbej = (V("ovvo") + einsum("jf,mbef->mbej", t1, V("ovvv")) - einsum("nb,mnej->mbej", t1, V("oovo"))
+             - einsum("jnfb,mnef->mbej", 0.5 * t2 + einsum("jf,nb->jnfb", t1, t1), Voovv))
+    o1 = (f("vo").T + einsum("ie,ae->ia", t1, Fae) - einsum("ma,mi->ia", t1, Fmi)
+          + einsum("imae,me->ia", t2, Fme) - einsum("nf,naif->ia", t1, V("ovov"))
+          - 0.5 * einsum("imef,maef->ia", t2, V("ovvv")) - 0.5 * einsum("mnae,nmei->ia", t2, V("oovo")))
+    Fbe = Fae - 0.5 * einsum("mb,me->be", t1, Fme)
+    Fmj = Fmi + 0.5 * einsum("je,me->mj", t1, Fme)
+    o2 = V("vvoo").transpose(2, 3, 0, 1).copy()
+    o2 = o2 + Pab(einsum("ijae,be->ijab", t2, Fbe)) - Pij(einsum("imab,mj->ijab", t2, Fmj))
+    o2 = o2 + 0.5 * einsum("mnab,mnij->ijab", tt, Wmnij) + 0.5 * einsum("ijef,abef->ijab", tt, Wabef)
+    o2 = o2 + Pij(Pab(einsum("imae,mbej->ijab", t2, Wmbej) - einsum("ie,ma,mbej->ijab", t1, t1, V("ovvo"))))
+    o2 = o2 + Pij(einsum("ie,abej->ijab", t1, V("vvvo"))) - Pab(einsum("ma,mbij->ijab", t1, V("ovoo")))
+    return o1, o2
+
+
+def ccsd_energy(H: Hamiltonian, t1, t2):
+    """Correlation energy <R|e^-T H_N e^T|R> = f_ia t^a_i + 1/4 <ij||ab> tau^ab_ij."""
+    return np.sum(H.fb("ov") * t1) + 0.25 * np.sum(H.V("oovv") * tau(t1, t2))
+
+
+def solve_ccsd(H: Hamiltonian, t1, t2, tol=1e-10, maxiter=200, nsub=3):
+    """CCSD amplitudes from the start (t1, t2) by CROP, the solver the
+    implementation section names for the ground state (conjugate residual
+    with optimal trial vectors; Ziolkowski et al., J. Chem. Phys. 128, 204105
+    (2008); Ettenhuber and Jorgensen, J. Chem. Theory Comput. 11, 1518 (2015)).
+
+    Each iteration takes a Jacobi step from the current optimal vector with
+    the Fock diagonal (x~ = x - Omega/D), evaluates the true residual there,
+    and forms the next optimal vector as the affine combination (coefficients
+    summing to one) of the kept optimal vectors and x~ that minimizes the
+    norm of the same combination of their residuals.  At most nsub vectors
+    take part (nsub - 1 optimal ones and the new one).  Stops when the true
+    residual's 2-norm over unique amplitudes is <= tol; returns (t1, t2,
+    energy, iterations)."""
+    o, v = H.o, H.v
+    fo, fv = np.diag(H.fb("oo")), np.diag(H.fb("vv"))
+    D = pack(fv[None, :] - fo[:, None],
+             fv[None, None, :, None] + fv[None, None, None, :] - fo[:, None, None, None] - fo[None, :, None, None])
+    x = pack(t1, t2)
+    r = pack(*ccsd_residual(H, t1, t2))
+    if np.linalg.norm(r) <= tol:
+        return t1, t2, ccsd_energy(H, t1, t2), 0
+    X, R = [x], [r]
+    for it in range(1, maxiter + 1):
+        xt = X[-1] - R[-1] / D
+        rt = pack(*ccsd_residual(H, *unpack(xt, o, v)))
+        if np.linalg.norm(rt) <= tol:
+            u1, u2 = unpack(xt, o, v)
+            return u1, u2, ccsd_energy(H, u1, u2), it
+        Xs, Rs = X[-(nsub - 1):] + [xt], R[-(nsub - 1):] + [rt]
+        m = len(Rs)
+        B = np.zeros((m + 1, m + 1), dtype=np.complex128)
+        for a in range(m):
+            for b in range(m):
+                B[a, b] = np.vdot(Rs[a], Rs[b])
+        B[m, :m] = B[:m, m] = 1.0
+        rhs = np.zeros(m + 1, dtype=np.complex128)
+        rhs[m] = 1.0
+        c = np.linalg.solve(B, rhs)[:m]
+        X.append(sum(ci * xi for ci, xi in zip(c, Xs)))
+        R.append(sum(ci * ri for ci, ri in zip(c, Rs)))
+        X, R = X[-(nsub - 1):], R[-(nsub - 1):]
+    raise RuntimeError("CROP did not converge")
+
+
+# ------------------------------------------------------ Cholesky integrals
+def integrals_from_cholesky(o, L):
+    """The six canonical <pq||rs> blocks from Cholesky vectors (the paper forms
+    every integral class from them; section "Computational details").  L[P]
+    are n x n Hermitian with Mulliken integrals (pq|rs) = sum_P L[P,p,q] L[P,r,s];
+    <pq|rs> = (pr|qs), so <pq||rs> = sum_P (L[P,p,r] L[P,q,s] - L[P,p,s] L[P,q,r])."""
+    L = np.asarray(L, dtype=np.complex128)
+    sl = {"o": slice(0, o), "v": slice(o, None)}
+    out = {}
+    for kinds in ("oooo", "ooov", "oovv", "ovov", "ovvv", "vvvv"):
+        p, q, r, s_ = (sl[k] for k in kinds)
+        out[kinds] = (einsum("Ppr,Pqs->pqrs", L[:, p, r], L[:, q, s_])
+                      - einsum("Pps,Pqr->pqrs", L[:, p, s_], L[:, q, r]))
+    return out
 
 
 # ------------------------------------------------------ excitation vectors

@@ -293,3 +293,30 @@ def fci_response(sp: Space, H, X, Y, z, state):
         wn = w[k] - w[state]
         tot += X0[k] * Yn[k] / (wn - z) + Y0[k] * Xn[k] / (wn + z)
     return -tot
+
+
+def hamiltonian_mulliken(sp: Space, h, eri):
+    """H = sum h_pq p+ q + 1/2 sum (pq|rs) p+ r+ s q from Mulliken-ordered
+    integrals eri[p,q,r,s] = (pq|rs) (no antisymmetrized integrals used)."""
+    n = sp.n
+    M = sp.one_body(np.asarray(h))
+    for c, d in enumerate(sp.dets):
+        for q in range(n):
+            a1 = _ann(d, q)
+            if a1 is None:
+                continue
+            for s in range(n):
+                a2 = _ann(a1[1], s)
+                if a2 is None:
+                    continue
+                for r in range(n):
+                    c1 = _cre(a2[1], r)
+                    if c1 is None:
+                        continue
+                    for p in range(n):
+                        c2 = _cre(c1[1], p)
+                        if c2 is None:
+                            continue
+                        sg = a1[0] * a2[0] * c1[0] * c2[0]
+                        M[sp.index[c2[1]], c] += 0.5 * eri[p, q, r, s] * sg
+    return M
