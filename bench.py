@@ -95,6 +95,77 @@ def cpu_baseline(seconds_target=15.0):
     }
 
 
+def ground_bench(cc, dev, o, v, seed, tol=1e-8, nchol_per_orbital=3):
+    """CCSD ground state at the benchmark size: CROP from the MP2-seeded start
+    on the benchmark Hamiltonian (iterations, residual evaluations, time per
+    residual), and the formation of the six integral blocks from Cholesky
+    vectors (nchol = nchol_per_orbital * n)."""
+    import torch
+    from gen import synth as s
+    pb, f, V, t1, t2, X = make_inputs(o, v, seed, dev)
+    del X
+    ctx = cc.cclr_create(o, v, cc.cclr_default_options())
+    out = {}
+    try:
+        cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+        del V
+        torch.cuda.empty_cache()
+        # one residual evaluation first (packs <ab||ef> and tunes the ladder product)
+        o1, o2 = torch.empty_like(t1), torch.empty_like(t2)
+        cc.cclr_ccsd_residual(ctx, t1, t2, o1, o2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cc.cclr_ccsd_residual(ctx, t1, t2, o1, o2)
+        torch.cuda.synchronize()
+        t_res = time.perf_counter() - t0
+        del o1, o2
+        log(f"ground state: one CCSD residual in {1e3 * t_res:.1f} ms")
+        t0 = time.perf_counter()
+        rc, E, info = cc.cclr_solve_ccsd(ctx, t1, t2, tol=tol, maxiter=80, nsub=3)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        log(f"ground state: CROP rc {rc}, {info.iters} iterations, {t_solve:.2f} s")
+        out.update({"workload": f"CCSD ground state o={o} v={v} complex128 (CROP, 3 vectors), MP2-seeded start",
+                    "residual_ms": round(1e3 * t_res, 2), "crop_rc": rc, "crop_iterations": info.iters,
+                    "residual_evaluations": info.nsigma, "resnorm": info.resnorm, "tol": tol,
+                    "solve_s_including_intermediates": round(t_solve, 3),
+                    "correlation_energy": [E.real, E.imag]})
+    finally:
+        cc.cclr_destroy(ctx)
+    del f, t1, t2
+    torch.cuda.empty_cache()
+    n = o + v
+    nchol = nchol_per_orbital * n
+    with torch.no_grad():
+        Lc = s.cholesky_vectors(pb, nchol, dev)
+        fd = s.fock(pb, dev)
+    ctx = cc.cclr_create(o, v, cc.cclr_default_options())
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cc.cclr_set_hamiltonian_cholesky(ctx, fd, Lc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        flop = 0
+        for k in s.CANONICAL_BLOCKS:
+            sz = 1
+            for c in k:
+                sz *= o if c == "o" else v
+            flop += 2 * 8 * sz * nchol
+        out["cholesky_integrals"] = {"nchol": nchol, "seconds": round(dt, 3),
+                                     "tflops": round(flop / dt / 1e12, 2),
+                                     "input_gb": round(Lc.numel() * 16 / 1e9, 3),
+                                     "blocks_gb": round(sum((o if k[0] == "o" else v) * (o if k[1] == "o" else v) *
+                                                            (o if k[2] == "o" else v) * (o if k[3] == "o" else v)
+                                                            for k in s.CANONICAL_BLOCKS) * 16 / 1e9, 2)}
+        log(f"Cholesky integral blocks (nchol {nchol}) formed in {dt:.2f} s")
+    finally:
+        cc.cclr_destroy(ctx)
+    del Lc, fd
+    torch.cuda.empty_cache()
+    return out
+
+
 def batching_bench(cc, dev, nvec=3, reps=3):
     """Four problems of uneven size, (o, v) = (8, 60), (12, 90), (16, 120),
     (20, 150), nvec right transforms each: one cclr_jacobian_right_multi call
@@ -200,6 +271,8 @@ def main():
                     help="skip the mixed-precision runs (reduced-precision products + FP64 refinement)")
     ap.add_argument("--no-batching", dest="batching", action="store_false",
                     help="skip the uneven multi-problem transform comparison")
+    ap.add_argument("--no-ground", dest="ground", action="store_false",
+                    help="skip the CCSD ground-state (CROP) and Cholesky-integral timings")
     ap.add_argument("--mixed-precs", default="fp32,bf16x3",
                     help="comma list of reduced precisions to run after the FP64 run")
     args = ap.parse_args()
@@ -375,6 +448,8 @@ def main():
         line["mixed_precision"][p] = mx
     if args.batching and args.mode == "response":
         line["batching"] = batching_bench(cc, dev)
+    if args.ground and args.mode == "response":
+        line["ground_state"] = ground_bench(cc, dev, o, v, args.seed)
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline()

@@ -102,6 +102,47 @@ int cclr_set_hamiltonian(cclr_ctx* ctx, const cclr_c64* f,
                          const cclr_c64* oooo, const cclr_c64* ooov, const cclr_c64* oovv,
                          const cclr_c64* ovov, const cclr_c64* ovvv, const cclr_c64* vvvv);
 
+/* Form the six canonical <pq||rs> blocks from Cholesky vectors of the
+ * Coulomb integrals, as the paper does for every integral class
+ * (computational details), and copy f.  L: DEVICE array nchol x n x n,
+ * L[P][p][q] Hermitian in (p, q) for each P, with the Mulliken integrals
+ * (pq|rs) = sum_P L[P][p][q] L[P][r][s], so
+ *   <pq||rs> = sum_P ( L[P][p][r] L[P][q][s] - L[P][p][s] L[P][q][r] ).
+ * The blocks are built on the device (products over P) and kept in the
+ * layouts of cclr_set_hamiltonian; L is not retained.  Invalidates
+ * amplitudes, intermediates and lambda.  CCLR_EINVAL for nchol < 1 or
+ * non-finite input. */
+int cclr_set_hamiltonian_cholesky(cclr_ctx* ctx, const cclr_c64* f, int nchol, const cclr_c64* L);
+
+/* The CCSD residual Omega_mu = <mu| e^-T H_N e^T |R> for amplitudes t1
+ * [o][v], t2 [o][o][v][v] (antisymmetric; DEVICE), written to o1, o2 in the
+ * same layouts (DEVICE), and the correlation energy
+ * f_ia t^a_i + 1/4 <ij||ab> tau^ab_ij to *energy (HOST, may be NULL).  The
+ * ground-state equations that the implementation section solves first (not
+ * printed in the paper; spin-orbital CCSD in the intermediate form of
+ * Stanton and Gauss, J. Chem. Phys. 94, 4334 (1991)).  Needs
+ * cclr_set_hamiltonian; does not change the context's amplitudes. */
+int cclr_ccsd_residual(cclr_ctx* ctx, const cclr_c64* t1, const cclr_c64* t2, cclr_c64* o1, cclr_c64* o2,
+                       cclr_c64* energy);
+
+/* Solve Omega(t) = 0 by CROP (conjugate residual with optimal trial
+ * vectors; Ziolkowski et al., J. Chem. Phys. 128, 204105 (2008)), the
+ * ground-state solver the implementation section names.  t1, t2 (DEVICE,
+ * layouts of cclr_ccsd_residual) hold the start on entry and the solution
+ * on return; each iteration takes a Jacobi step with the Fock diagonal from
+ * the current optimal vector, evaluates the residual there, and combines
+ * the last nsub - 1 optimal vectors and the new one with weights summing to
+ * one that minimize the norm of the combined residual (nsub in [2, 8];
+ * 3 is the usual CROP).  Converged when the residual's 2-norm over unique
+ * amplitudes is <= tol.  The solution becomes the context's amplitudes
+ * (as by cclr_set_amplitudes).  energy (HOST, may be NULL) receives the
+ * correlation energy.  info: iters, converged, resnorm, nsigma = residual
+ * evaluations.  Returns CCLR_ENOTCONV (results written) after maxiter
+ * iterations without convergence, and without writing anything if the
+ * iteration diverges to non-finite values. */
+int cclr_solve_ccsd(cclr_ctx* ctx, double tol, int maxiter, int nsub, cclr_c64* t1, cclr_c64* t2,
+                    cclr_c64* energy, cclr_solve_info* info);
+
 /* Copy t1 and t2 and build the property-independent Hbar intermediates
  * F^i_m, F^a_e, F^m_e, W^ij_mn, W^mb_ej, W^ie_mn, W^ef_am, W^ef_ab, W^mn_ie,
  * W^am_ef (SI, eqs. F_im ... W_amef).  Needs cclr_set_hamiltonian first

@@ -24,7 +24,8 @@ CCLR_FP64, CCLR_FP32, CCLR_BF16X3 = 0, 1, 2
 CCLR_RIGHT, CCLR_LEFT = 0, 1
 
 EXPORTED = (
-    "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_amplitudes",
+    "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_hamiltonian_cholesky",
+    "cclr_set_amplitudes", "cclr_ccsd_residual", "cclr_solve_ccsd",
     "cclr_jacobian_right", "cclr_jacobian_left", "cclr_jacobian_right_multi", "cclr_solve_damped", "cclr_eom_ee", "cclr_solve_lambda", "cclr_get_lambda",
     "cclr_response_function", "cclr_response_function_ci", "cclr_response_function_asym", "cclr_response_backward",
     "cclr_last_error",
@@ -67,6 +68,9 @@ def lib():
     L.cclr_destroy.argtypes = [P]
     L.cclr_set_hamiltonian.argtypes = [P] + [P] * 7
     L.cclr_set_amplitudes.argtypes = [P, P, P]
+    L.cclr_set_hamiltonian_cholesky.argtypes = [P, P, I, P]
+    L.cclr_ccsd_residual.argtypes = [P, P, P, P, P, P]
+    L.cclr_solve_ccsd.argtypes = [P, ctypes.c_double, I, I, P, P, P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_jacobian_right.argtypes = [P, I, D, D, P, P, P, P]
     L.cclr_jacobian_left.argtypes = [P, I, D, D, P, P, P, P]
     PP = ctypes.POINTER(P)
@@ -152,6 +156,31 @@ def cclr_set_hamiltonian(ctx, f, oooo, ooov, oovv, ovov, ovvv, vvvv):
 
 def cclr_set_amplitudes(ctx, t1, t2):
     return _check(ctx, lib().cclr_set_amplitudes(ctx, _ptr(t1, "t1"), _ptr(t2, "t2")))
+
+
+def cclr_set_hamiltonian_cholesky(ctx, f, L):
+    """Integral blocks from Cholesky vectors L[nchol][n][n] (device tensor)."""
+    return _check(ctx, lib().cclr_set_hamiltonian_cholesky(ctx, _ptr(f, "f"), int(L.shape[0]), _ptr(L, "L")))
+
+
+def cclr_ccsd_residual(ctx, t1, t2, o1, o2):
+    """Omega(t) into o1, o2 (device tensors); returns the correlation energy."""
+    import numpy as np
+    e = np.zeros(1, dtype=np.complex128)
+    _check(ctx, lib().cclr_ccsd_residual(ctx, _ptr(t1, "t1"), _ptr(t2, "t2"), _ptr(o1, "o1"), _ptr(o2, "o2"),
+                                         ctypes.c_void_p(e.ctypes.data)))
+    return complex(e[0])
+
+
+def cclr_solve_ccsd(ctx, t1, t2, tol=1e-10, maxiter=100, nsub=3):
+    """CROP solve in place on the device tensors t1, t2; returns (rc, energy, info)."""
+    import numpy as np
+    e = np.zeros(1, dtype=np.complex128)
+    info = cclr_solve_info()
+    rc = lib().cclr_solve_ccsd(ctx, float(tol), int(maxiter), int(nsub), _ptr(t1, "t1"), _ptr(t2, "t2"),
+                               ctypes.c_void_p(e.ctypes.data), ctypes.byref(info))
+    _check(ctx, rc, allow_notconv=True)
+    return rc, complex(e[0]), info
 
 
 def cclr_jacobian_right(ctx, omega, gamma, r1, r2, s1, s2):

@@ -181,6 +181,7 @@ int cclr_set_hamiltonian(cclr_ctx* c, const cclr_c64* f, const cclr_c64* oooo, c
   return guarded(c, [&]() -> int {
     const i64 o = c->o, v = c->v, n = o + v;
     c->have_H = c->have_t = c->have_lam = false;
+    c->Vpk.release();
     copy_in(c, c->f, f, n * n, "f");
     copy_in(c, c->Voooo, oooo, o * o * o * o, "oooo");
     copy_in(c, c->Vooov, ooov, o * o * o * v, "ooov");
@@ -191,6 +192,69 @@ int cclr_set_hamiltonian(cclr_ctx* c, const cclr_c64* f, const cclr_c64* oooo, c
     HIPCHK(hipStreamSynchronize(c->stream));
     c->have_H = true;
     return CCLR_OK;
+  });
+}
+
+int cclr_set_hamiltonian_cholesky(cclr_ctx* c, const cclr_c64* f, int nchol, const cclr_c64* L) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    const i64 o = c->o, v = c->v, n = o + v;
+    REQUIRE(nchol >= 1, CCLR_EINVAL, "need nchol >= 1");
+    c->have_H = c->have_t = c->have_lam = false;
+    c->Vpk.release();
+    copy_in(c, c->f, f, n * n, "f");
+    check_ptr(L, "L");
+    {
+      Arena::Mark mk = c->arena.mark();
+      check_finite(c, (const cplx*)L, (i64)nchol * n * n, "L");
+      c->arena.reset(mk);
+    }
+    integrals_from_cholesky(c, nchol, (const cplx*)L);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->have_H = true;
+    return CCLR_OK;
+  });
+}
+
+int cclr_ccsd_residual(cclr_ctx* c, const cclr_c64* t1, const cclr_c64* t2, cclr_c64* o1, cclr_c64* o2,
+                       cclr_c64* energy) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    REQUIRE(c->have_H, CCLR_ESTATE, "cclr_set_hamiltonian has not been called");
+    Arena::Mark mk = c->arena.mark();
+    VecSet t = packed_buf(c, 1), out = packed_buf(c, 1);
+    pack_in(c, 1, t1, t2, t, "t");
+    const std::complex<double> E = ccsd_residual(c, t, out);
+    unpack_out(c, out, o1, o2, "output");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->arena.reset(mk);
+    if (energy) *energy = cclr_c64{E.real(), E.imag()};
+    return CCLR_OK;
+  });
+}
+
+int cclr_solve_ccsd(cclr_ctx* c, double tol, int maxiter, int nsub, cclr_c64* t1, cclr_c64* t2, cclr_c64* energy,
+                    cclr_solve_info* info) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    REQUIRE(c->have_H, CCLR_ESTATE, "cclr_set_hamiltonian has not been called");
+    const i64 o = c->o, v = c->v;
+    Arena::Mark mk = c->arena.mark();
+    VecSet t = packed_buf(c, 1);
+    pack_in(c, 1, t1, t2, t, "t");
+    std::complex<double> E;
+    const int rc = ccsd_crop(c, tol, maxiter, nsub, t, &E, info);
+    unpack_out(c, t, t1, t2, "t");
+    c->arena.reset(mk);
+    // the solution becomes the context's amplitudes
+    c->have_t = c->have_lam = false;
+    copy_in(c, c->t1, t1, o * v, "t1");
+    copy_in(c, c->t2, t2, o * o * v * v, "t2");
+    build_intermediates(c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->have_t = true;
+    if (energy) *energy = cclr_c64{E.real(), E.imag()};
+    return rc;
   });
 }
 

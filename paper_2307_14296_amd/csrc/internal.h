@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <string>
 #include <algorithm>
+#include <complex>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -203,6 +204,7 @@ struct cclr_ctx {
   SplitMat wsplit_m[4];
   DevBuf diag;       // Fock-like diagonal for preconditioning: singles then doubles (packed)
   DevBuf lam_s, lam_d;  // lambda, packed
+  DevBuf Vpk;         // packed <ab||ef> (a>b, e>f) of the ground-state residual, made on first use
   Arena arena;
   // arithmetic of the ladder and ring products in the transforms being applied
   // (CCLR_FP64 for the FP64 path and every true residual; opt.prec inside the
@@ -265,7 +267,7 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_
 // ------------------------------------------------- solver and response pieces
 void launch_check_finite(const cplx* p, i64 n, int* flag, hipStream_t s);
 void launch_bdot(int npair, const cplx* const* xs, const cplx* const* xd, const cplx* const* ys,
-                 const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s);
+                 const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s, bool conjx = false);
 void launch_caxpy(i64 n, cplx a, const cplx* x, cplx* y, hipStream_t s);
 void launch_conj_inplace(i64 n, cplx* x, hipStream_t s);
 // (A - z_k) x_k = -rhs_k (right) or x_k (A - z_k) = -rhs_k (left) in the context's precision
@@ -281,6 +283,13 @@ void density_eta(cclr_ctx* c, const VecSet& y, cplx* D, cplx alpha);
 // gradient with respect to f and the integral blocks (see adjoint.hip)
 void hamiltonian_adjoint(cclr_ctx* c, int nx, const cplx* Xs, const VecSet& sol, const VecSet& xl, const VecSet& Y,
                          const VecSet& PA, const VecSet& PB, cplx* df, cplx* const* dV, cclr_solve_info* info);
+// CCSD ground state (ground.hip): residual of one packed amplitude vector
+// (returns the correlation energy), the CROP solve (t: start in, solution
+// out), and the integral blocks from Cholesky vectors L[nchol][n][n]
+std::complex<double> ccsd_residual(cclr_ctx* c, const VecSet& t, const VecSet& out);
+int ccsd_crop(cclr_ctx* c, double tol, int maxit, int nsub, const VecSet& t, std::complex<double>* energy,
+              cclr_solve_info* info);
+void integrals_from_cholesky(cclr_ctx* c, int nchol, const cplx* L);
 // lowest EOM-EE eigenpairs (right: A x = w x, left: x A = w x); omega by increasing real part
 int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit, std::vector<cplx>& omega,
                  const VecSet& xout, cclr_solve_info* info);

@@ -927,17 +927,18 @@ __global__ __launch_bounds__(256) void k_check_finite(const cplx* __restrict__ p
 }
 
 constexpr int kDotChunks = 256;
-// partial[p][chunk] = sum over chunk of x_p * y_p (bilinear, packed vectors)
+// partial[p][chunk] = sum over chunk of x_p * y_p (bilinear, packed vectors; x conjugated if conjx)
 __global__ __launch_bounds__(256) void k_bdot(const cplx* const* xs, const cplx* const* xd, const cplx* const* ys,
-                                              const cplx* const* yd, i64 ov, i64 nd, cplx* partial) {
+                                              const cplx* const* yd, i64 ov, i64 nd, cplx* partial, int conjx) {
   const int p = blockIdx.y, chunk = blockIdx.x;
   const i64 n = ov + nd;
   const i64 per = (n + kDotChunks - 1) / kDotChunks;
   const i64 lo = chunk * per, hi = min(n, lo + per);
   double ar = 0.0, ai = 0.0;
   for (i64 e = lo + threadIdx.x; e < hi; e += 256) {
-    const cplx x = e < ov ? xs[p][e] : xd[p][e - ov];
+    cplx x = e < ov ? xs[p][e] : xd[p][e - ov];
     const cplx y = e < ov ? ys[p][e] : yd[p][e - ov];
+    if (conjx) x.y = -x.y;
     ar += x.x * y.x - x.y * y.y;
     ai += x.x * y.y + x.y * y.x;
   }
@@ -997,9 +998,9 @@ void launch_check_finite(const cplx* p, i64 n, int* flag, hipStream_t s) {
 
 // out[p] = sum x_p y_p for npair packed-vector pairs given by device pointer arrays
 void launch_bdot(int npair, const cplx* const* xs, const cplx* const* xd, const cplx* const* ys,
-                 const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s) {
+                 const cplx* const* yd, i64 ov, i64 nd, cplx* partial, cplx* out, hipStream_t s, bool conjx) {
   if (npair <= 0) return;
-  hipLaunchKernelGGL(k_bdot, dim3(kDotChunks, npair), dim3(256), 0, s, xs, xd, ys, yd, ov, nd, partial);
+  hipLaunchKernelGGL(k_bdot, dim3(kDotChunks, npair), dim3(256), 0, s, xs, xd, ys, yd, ov, nd, partial, (int)conjx);
   hipLaunchKernelGGL(k_bdot_reduce, dim3(npair), dim3(256), 0, s, partial, out);
   HIPCHK(hipGetLastError());
 }

@@ -539,22 +539,6 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
 }
 
 // ------------------------------------------------------- precision driver
-namespace {
-__global__ __launch_bounds__(256) void k_axpy_set(cplx* x, const cplx* y, i64 n, double a) {
-  // x = x + a*y
-  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (i64)gridDim.x * blockDim.x) {
-    x[e].x += a * y[e].x;
-    x[e].y += a * y[e].y;
-  }
-}
-void axpy(cclr_ctx* c, cplx* x, const cplx* y, i64 n, double a) {
-  if (n <= 0) return;
-  i64 g = std::min<i64>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_axpy_set, dim3((unsigned)g), dim3(256), 0, c->stream, x, y, n, a);
-  HIPCHK(hipGetLastError());
-}
-}  // namespace
-
 // Solve with the context's precision.  FP64: one Davidson solve.  FP32 /
 // split-BF16: the Davidson solve with iterative refinement and subspace
 // recycling (see davidson): reduced-precision ladder and ring products for
