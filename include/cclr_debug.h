@@ -19,6 +19,16 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
                    int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn, int conjB, cclr_c64* C,
                    long long sCb, long long sCm, long long sCn, double alpha_re, double alpha_im, int beta);
 
+/* C[b] (+)= alpha * op(A[b]) op(B[b]) for b < batch with one FP64 kernel
+ * variant (0: simple; 1..4: MFMA tiles 128x64 / 64x64 with three or four
+ * real products per complex block; 4 + k: variant k in the XCD-grouped tile
+ * order).  All pointers are device memory; strides in elements.  For tests
+ * of every variant (the autotuner otherwise runs only the fastest). */
+int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c64* A, long long sAb, long long sAm,
+                       long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
+                       int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,
+                       int beta);
+
 /* The same product (batch 1) in reduced arithmetic: prec = CCLR_FP32 (FP32
  * MFMA) or CCLR_BF16X3 (split-BF16 MFMA, three bf16 products per real
  * product, FP32 accumulation); operands and C stay complex128. */

@@ -111,8 +111,9 @@ struct GemmArgs {
   i64 sAb2, sBb2, sCb2;
 };
 void launch_zgemm(const GemmArgs& g, hipStream_t s);
-// FP64 kernel variants (tile shape, three or four real products per complex block)
-enum { GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4, GEMM_NVAR = 5 };
+// FP64 kernel variants (tile shape, three or four real products per complex
+// block); variants 4 + k run variant k (k = 1..4) in the XCD-grouped tile order
+enum { GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4, GEMM_NVAR = 9 };
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);
 int gemm_default_variant(const GemmArgs& g);
 // Several products (same operand layouts: ak = unit-stride k in A, bn = unit-

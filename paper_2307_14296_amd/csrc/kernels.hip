@@ -375,9 +375,32 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
       }
 }
 
+// Tile order of the one-dimensional launch.  The hardware deals workgroups
+// round-robin over the 8 XCDs (each with its own L2), so workgroup w is
+// mapped to a contiguous run of the tile sequence on XCD w % 8.  In the
+// sequence the batch index is slowest; inside a batch, groups of gm M-tiles
+// sweep the N-tiles with M fastest, so the tiles that run together on one
+// XCD share both their B column panels (gm of them per panel) and their A
+// row panels (across the N-tiles in flight).
+// With xcd = 0 and gm = tm this is the plain order (M fastest, then N, then
+// the batch index) in which consecutive tiles land on different XCDs.
+__device__ __forceinline__ void tile_of(int w, int T, int tm, int tn, int gm, int xcd, int& mi, int& ni, int& bz) {
+  const int x = w & 7, l = w >> 3, per = T >> 3, rem = T & 7;
+  const int t = xcd ? (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + l : w;
+  const int per_b = tm * tn;
+  bz = t / per_b;
+  const int r = t - bz * per_b;
+  const int grp = r / (gm * tn), within = r - grp * gm * tn;
+  const int gme = min(gm, tm - grp * gm);
+  mi = grp * gm + within % gme;
+  ni = within / gme;
+}
+
 template <int BM, int BN, bool AK, bool BNF, bool G3>
-__global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g) {
-  zgemm_tile<BM, BN, AK, BNF, G3>(g, blockIdx.x * BM, blockIdx.y * BN, blockIdx.z);
+__global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g, int tm, int tn, int gm, int xcd) {
+  int mi, ni, bz;
+  tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
+  zgemm_tile<BM, BN, AK, BNF, G3>(g, mi * BM, ni * BN, bz);
 }
 
 // Grouped persistent form: one launch walks the tiles of several products
@@ -727,23 +750,30 @@ inline unsigned grid_for(i64 total) {
 }  // namespace
 
 // FP64 GEMM variants: tile 128x64 or 64x64, three or four real products
+// (M-tiles per group of the tile order)
+constexpr int kGroupM = 8;
 template <int BM, int BN, bool G3>
-static void launch_p(const GemmArgs& g, hipStream_t s) {
+static void launch_p(const GemmArgs& g, bool grouped, hipStream_t s) {
   const bool ak = g.sAk == 1, bn = g.sBn == 1;
-  dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
-  if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, true, G3>), grid, dim3(256), 0, s, g);
-  else if (ak) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, false, G3>), grid, dim3(256), 0, s, g);
-  else if (bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, true, G3>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, false, G3>), grid, dim3(256), 0, s, g);
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN, gm = grouped ? std::min(tm, kGroupM) : tm;
+  const int xcd = grouped ? 1 : 0;
+  const i64 total = (i64)tm * tn * g.batch;
+  REQUIRE(total >= 1 && total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
+  dim3 grid((unsigned)total);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, true, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, false, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, true, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, false, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
 }
 
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
-  switch (variant) {
-    case GEMM_128x64_G3: launch_p<128, 64, true>(g, s); break;
-    case GEMM_64x64_G3: launch_p<64, 64, true>(g, s); break;
-    case GEMM_128x64_G4: launch_p<128, 64, false>(g, s); break;
-    case GEMM_64x64_G4: launch_p<64, 64, false>(g, s); break;
+  const bool grouped = variant > GEMM_64x64_G4;
+  switch (grouped ? variant - GEMM_64x64_G4 : variant) {
+    case GEMM_128x64_G3: launch_p<128, 64, true>(g, grouped, s); break;
+    case GEMM_64x64_G3: launch_p<64, 64, true>(g, grouped, s); break;
+    case GEMM_128x64_G4: launch_p<128, 64, false>(g, grouped, s); break;
+    case GEMM_64x64_G4: launch_p<64, 64, false>(g, grouped, s); break;
     default: {
       dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
       hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);

@@ -71,6 +71,39 @@ def test_zgemm(gpu, M, N, K, ta, tb):
         assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (conjA, conjB, beta)
 
 
+VARIANT_CASES = [(1, 1, 1, 1), (130, 70, 33, 3), (300, 200, 50, 1), (257, 1, 64, 2), (64, 640, 17, 5),
+                 (1100, 65, 40, 1)]
+
+
+@pytest.mark.parametrize("M,N,K,batch", VARIANT_CASES)
+def test_zgemm_every_variant(gpu, M, N, K, batch):
+    """Every FP64 kernel variant and tile order (the autotuner runs only the
+    fastest), batched, ragged tails, both operand orientations."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_zgemm_f64.argtypes = [ctypes.c_int] * 5 + [P, LL, LL, LL, ctypes.c_int, P, LL, LL, LL, ctypes.c_int,
+                                                          P, LL, LL, LL, ctypes.c_double, ctypes.c_double,
+                                                          ctypes.c_int]
+    rng = np.random.default_rng(M * 31 + N * 7 + K + batch)
+    A = crand(rng, batch, M, K)
+    B = crand(rng, batch, K, N)
+    C0 = crand(rng, batch, M, N)
+    alpha = 0.3 + 1.1j
+    for variant in range(9):
+        for ta, tb, beta in [(False, False, 0), (True, True, 1), (False, True, 1), (True, False, 0)]:
+            Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
+            Bd = dev(B.transpose(0, 2, 1).copy() if tb else B)
+            Cd = dev(C0)
+            sAm, sAk = (1, M) if ta else (K, 1)
+            sBk, sBn = (1, K) if tb else (N, 1)
+            rc = L.cclr_dbg_zgemm_f64(variant, batch, M, N, K, Ad.data_ptr(), M * K, sAm, sAk, 0, Bd.data_ptr(),
+                                      K * N, sBk, sBn, 1, Cd.data_ptr(), M * N, N, 1, alpha.real, alpha.imag, beta)
+            assert rc == 0
+            ref = alpha * (A @ B.conj()) + (C0 if beta else 0)
+            err = np.abs(Cd.cpu().numpy() - ref).max() / max(1.0, np.abs(ref).max())
+            assert err <= 1e-12, (variant, ta, tb, beta, err)
+
+
 def test_zgemm_batched_and_transposed_output(gpu):
     cc, L = _cc()
     rng = np.random.default_rng(5)
