@@ -95,6 +95,57 @@ def cpu_baseline(seconds_target=15.0):
     }
 
 
+def spectrum_bench(cc, dev, o=16, v=120, seed=2, nfreq=16):
+    """Damped spectrum: 3 dipoles x nfreq frequencies on [0, 0.5] Eh, gamma
+    0.005, solved in one call (every right-hand side in lockstep) against one
+    call per frequency."""
+    import numpy as np
+    import torch
+    from gen import synth as s
+    pb, f, V, t1, t2, X = make_inputs(o, v, seed, dev)
+    opt = cc.cclr_default_options()
+    opt.max_subspace = 24
+    opt.tol = 1e-8
+    ctx = cc.cclr_create(o, v, opt)
+    try:
+        cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+        del V
+        torch.cuda.empty_cache()
+        cc.cclr_set_amplitudes(ctx, t1, t2)
+        om = [float(x) for x in np.linspace(0.0, 0.5, nfreq)]
+        ga = [0.005] * nfreq
+        # warm-up of both forms (Lambda solve; first-use GEMM tuning of their product shapes)
+        cc.cclr_response_function(ctx, X, om, ga)
+        cc.cclr_response_function(ctx, X, om[1:2], ga[1:2])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, out, info = cc.cclr_response_function(ctx, X, om, ga)
+        torch.cuda.synchronize()
+        t_lock = time.perf_counter() - t0
+        log(f"spectrum: lockstep call {t_lock:.2f} s, {info.nsigma} transforms")
+        n_single, outs = 0, []
+        t0 = time.perf_counter()
+        for w in range(nfreq):
+            rc1, one, info1 = cc.cclr_response_function(ctx, X, [om[w]], [ga[w]])
+            n_single += info1.nsigma
+            outs.append(one[0])
+        torch.cuda.synchronize()
+        t_single = time.perf_counter() - t0
+        log(f"spectrum: one call per frequency {t_single:.2f} s, {n_single} transforms")
+        diff = max(float(np.linalg.norm(out[w] - outs[w]) / np.linalg.norm(outs[w])) for w in range(nfreq))
+        return {"workload": f"damped spectrum o={o} v={v} complex128, 3 dipoles x {nfreq} frequencies on [0, 0.5] Eh, "
+                            f"gamma 0.005, tol 1e-8",
+                "lockstep": {"seconds": round(t_lock, 3), "transforms": info.nsigma,
+                             "transforms_per_s": round(info.nsigma / t_lock, 2), "iterations": info.iters, "rc": rc},
+                "one_call_per_frequency": {"seconds": round(t_single, 3), "transforms": n_single,
+                                           "transforms_per_s": round(n_single / t_single, 2)},
+                "speedup_lockstep": round(t_single / t_lock, 3), "max_rel_diff_alpha": diff}
+    finally:
+        cc.cclr_destroy(ctx)
+        del f, t1, t2, X
+        torch.cuda.empty_cache()
+
+
 def ground_bench(cc, dev, o, v, seed, tol=1e-8, nchol_per_orbital=3, v_std=0.002):
     """CCSD ground state at the benchmark size: CROP from the MP2-seeded start
     (iterations, residual evaluations, time per residual), and the formation
@@ -282,6 +333,8 @@ def main():
                     help="skip the mixed-precision runs (reduced-precision products + FP64 refinement)")
     ap.add_argument("--no-batching", dest="batching", action="store_false",
                     help="skip the uneven multi-problem transform comparison")
+    ap.add_argument("--no-spectrum", dest="spectrum", action="store_false",
+                    help="skip the damped-spectrum lockstep vs per-frequency comparison (o=16, v=120)")
     ap.add_argument("--no-ground", dest="ground", action="store_false",
                     help="skip the CCSD ground-state (CROP) and Cholesky-integral timings")
     ap.add_argument("--mixed-precs", default="fp32,bf16x3",
@@ -459,6 +512,8 @@ def main():
         line["mixed_precision"][p] = mx
     if args.batching and args.mode == "response":
         line["batching"] = batching_bench(cc, dev)
+    if args.spectrum and args.mode == "response":
+        line["spectrum"] = spectrum_bench(cc, dev)
     if args.ground and args.mode == "response":
         line["ground_state"] = ground_bench(cc, dev, o, v, args.seed)
     if not args.no_cpu:

@@ -63,7 +63,9 @@ int cclr_dbg_profile_read(cclr_ctx* ctx, int largest_only, long long* launches, 
 int cclr_dbg_set_sigma_prec(cclr_ctx* ctx, int prec);
 
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
- * GEMM shape class: "MxNxK bB layoutL: ms of each variant -> chosen".
+ * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
+ * the variant in use, which within 2% of the fastest prefers the grouped
+ * tile order).
  * enable >= 0 switches tuning on (1) or off (0) for later products. */
 int cclr_dbg_tuning(cclr_ctx* ctx, int enable, char* buf, long long cap);
 

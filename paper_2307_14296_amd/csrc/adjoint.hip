@@ -258,6 +258,12 @@ struct Env {
   std::map<std::string, Ten> cot;  // cotangents
   cplx* gf = nullptr;              // holomorphic cotangent of f (n x n)
   std::map<std::string, cplx*> gv; // ... and of each canonical integral block
+  // W^ef_ab exists only packed.  Its cotangent is accumulated directly in the
+  // vvvv block of the integral gradient (W^ef_ab = V^ef_ab + ..., so that
+  // block receives exactly this cotangent), and the one product that needs
+  // its value (the lambda cotangent of the t^X F ladder term) runs on the
+  // packed operator.
+  bool w4_in_gv = false;
 };
 
 Ten value(Env& e, const std::string& n) {
@@ -312,6 +318,12 @@ void add_cot(Env& e, const std::string& name, const std::string& la, cplx alpha,
     tgt.si = 0.0;
   } else {
     auto it = e.cot.find(name);
+    if (it == e.cot.end() && name == "Wvvvv") {
+      const i64 v = c->v;
+      REQUIRE(e.gv.count("vvvv"), CCLR_EINVAL, "adjoint: W^ef_ab cotangent needs the integral gradient");
+      it = e.cot.emplace(name, ten(e.gv.at("vvvv"), {v, v, v, v})).first;
+      e.w4_in_gv = true;
+    }
     if (it == e.cot.end()) {
       const Ten v = value(e, name);
       i64 n = v.size();
@@ -337,6 +349,11 @@ void add_cot(Env& e, const std::string& name, const std::string& la, cplx alpha,
   einsum_acc(c, alpha, ops, tgt, la);
 }
 
+// cot(l2)_kief += coef sum_(Z,c,a) cot(out)_Zkc W^ef_ca x1_Zia on the packed
+// operator: U_kica = sum_Z cot_Zkc x1_Zia, antisymmetrized and packed in
+// (c,a), times Wp[EF][CA], unpacked with antisymmetry in (e,f).
+void ladder_lambda_cot(Env& e, const Term& t, const Ten& cot_out);
+
 // Backward pass through a term table: for every term whose output has a
 // cotangent, the cotangent of each operand selected by `want`.
 void reverse(Env& e, const Term* terms, int nt, const std::function<bool(const std::string&)>& want) {
@@ -347,6 +364,16 @@ void reverse(Env& e, const Term* terms, int nt, const std::function<bool(const s
     const int no = nops(t);
     for (int j = 0; j < no; ++j) {
       if (!want(t.ops[j].name)) continue;
+      // W^ef_ab = V^ef_ab + ...: the vvvv gradient block already holds the cotangent
+      if (e.w4_in_gv && std::string(t.out) == "Wvvvv" && std::string(t.ops[j].name) == "V:vvvv") continue;
+      bool w4_value = false;
+      for (int k = 0; k < no; ++k)
+        if (k != j && std::string(t.ops[k].name) == "Wvvvv") w4_value = true;
+      if (w4_value) {
+        REQUIRE(std::string(t.ops[j].name) == "l2", CCLR_EINVAL, "adjoint: unsupported use of W^ef_ab");
+        ladder_lambda_cot(e, t, co->second);
+        continue;
+      }
       std::vector<Opnd> ops;
       ops.push_back(Opnd{co->second, t.lo});
       for (int k = 0; k < no; ++k)
@@ -354,6 +381,39 @@ void reverse(Env& e, const Term* terms, int nt, const std::function<bool(const s
       add_cot(e, t.ops[j].name, t.ops[j].lab, cx(t.coef), ops);
     }
   }
+}
+
+void ladder_lambda_cot(Env& e, const Term& t, const Ten& cot_out) {
+  cclr_ctx* c = e.c;
+  const i64 o = c->o, v = c->v, V2 = c->V2();
+  REQUIRE(nops(t) == 3 && std::string(t.lo) == "Zkc" && std::string(t.ops[0].lab) == "kief" &&
+              std::string(t.ops[1].lab) == "efca" && std::string(t.ops[2].name) == "x1" &&
+              std::string(t.ops[2].lab) == "Zia",
+          CCLR_EINVAL, "adjoint: unexpected form of the ladder term");
+  auto it = e.cot.find("l2");
+  if (it == e.cot.end()) {
+    Ten z = tmp(c, {o, o, v, v});
+    launch_fill(z.p, z.size(), cx(0.0), c->stream);
+    it = e.cot.emplace("l2", z).first;
+  }
+  Arena::Mark mk = c->arena.mark();
+  Ten U = tmp(c, {o, o, v, v});
+  contract(c, cx(1.0), cot_out, "Zkc", value(e, "x1"), "Zia", U, "kica", false);
+  Ten Ua = tmp(c, {o, o, v, v});
+  tcopy(c, Ua, "kica", U, "kica", cx(1.0), false);
+  tcopy(c, Ua, "kica", U, "kiac", cx(-1.0), true);
+  cplx* Up = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(o * o * V2));
+  launch_pack_pairs(o * o, (int)v, Ua.p, Up, c->stream);
+  cplx* R = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(o * o * V2));
+  GemmArgs g{};
+  g.M = (int)(o * o); g.N = (int)V2; g.K = (int)V2; g.batch = 1;
+  g.A = Up; g.sAm = V2; g.sAk = 1;
+  g.B = c->Wp.c(); g.sBk = 1; g.sBn = V2;
+  g.C = R; g.sCm = V2; g.sCn = 1;
+  g.ar = 1.0; g.ai = 0.0; g.beta = 0;
+  run_gemm(c, g);
+  launch_unpack_pairs_acc(o * o, (int)v, R, it->second.p, t.coef, c->stream);
+  c->arena.reset(mk);
 }
 
 // group cotangents of a doubles output paired with the antisymmetric y2
@@ -463,7 +523,6 @@ void hamiltonian_adjoint(cclr_ctx* c, int nx, const cplx* Xs, const VecSet& sol,
   e.val["Wbar"] = ten(c->Wbar, {o, v, v, o});
   e.val["Wooov"] = ten(c->Wooov, {o, o, o, v});
   e.val["Wvovv"] = ten(c->Wvovv, {v, o, v, v});
-  e.val["Wvvvv"] = ten(c->Wvvvv, {v, v, v, v});
   e.val["Wovoo"] = ten(c->Wovoo, {o, v, o, o});
   e.val["Wvvvo"] = ten(c->Wvvvo, {v, v, v, o});
   Ten l1 = dense(c, {o, v}), l2 = dense(c, {o, o, v, v});

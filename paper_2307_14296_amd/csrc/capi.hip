@@ -334,7 +334,7 @@ void grouped_products(cclr_ctx* c0, std::vector<GemmArgs> g) {
   if (it == c0->group_choice.end()) {
     int best = GEMM_128x64_G4;
     double best_ms = -1;
-    std::vector<double> ms_all;
+    std::vector<std::pair<int, double>> ms_all;
     for (int var : {GEMM_128x64_G3, GEMM_64x64_G3, GEMM_128x64_G4, GEMM_64x64_G4}) {
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
@@ -347,11 +347,11 @@ void grouped_products(cclr_ctx* c0, std::vector<GemmArgs> g) {
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
-      ms_all.push_back(ms);
+      ms_all.push_back({var, ms});
       if (best_ms < 0 || ms < best_ms) best_ms = ms, best = var;
     }
     c0->group_choice[key] = best;
-    c0->gemm_tuning_log.push_back({"group " + key, ms_all});
+    c0->gemm_tuning_log.push_back({"group " + key, ms_all, best});
     it = c0->group_choice.find(key);
   }
   launch(it->second);

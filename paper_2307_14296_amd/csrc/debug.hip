@@ -119,8 +119,21 @@ int cclr_dbg_get(cclr_ctx* c, const char* name, cclr_c64* dst, long long* count)
   else if (n == "Wvovv") b = &c->Wvovv;
   else if (n == "Wovoo") b = &c->Wovoo;
   else if (n == "Wvvvo") b = &c->Wvvvo;
-  else if (n == "Wvvvv") b = &c->Wvvvv;
-  else if (n == "Wp") b = &c->Wp;
+  else if (n == "Wvvvv") {
+    // unpacked on request from the packed operator
+    const i64 v = c->v;
+    if (count) *count = (long long)(v * v * v * v);
+    if (dst && c->Wp.p) {
+      try {
+        launch_unpack_vvvv(c->v, c->Wp.c(), (cplx*)dst, c->stream);
+        HIPCHK(hipStreamSynchronize(c->stream));
+      } catch (const CclrError& e) {
+        c->err = e.what();
+        return e.code;
+      }
+    }
+    return CCLR_OK;
+  } else if (n == "Wp") b = &c->Wp;
   else if (n == "diag") b = &c->diag;
   if (!b) {
     c->err = "unknown intermediate " + n;
@@ -180,14 +193,10 @@ int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {
   if (!c) return CCLR_EINVAL;
   if (enable >= 0) c->autotune = enable != 0;
   std::string out;
-  for (const auto& kv : c->gemm_tuning_log) {
-    out += kv.first + ":";
-    int best = 0;
-    for (size_t v = 0; v < kv.second.size(); ++v) {
-      out += " " + std::to_string(kv.second[v]);
-      if (kv.second[v] < kv.second[best]) best = (int)v;
-    }
-    out += " -> " + std::to_string(best) + "\n";
+  for (const auto& r : c->gemm_tuning_log) {
+    out += r.shape + ":";
+    for (const auto& vm : r.ms) out += " " + std::to_string(vm.first) + "=" + std::to_string(vm.second);
+    out += " -> " + std::to_string(r.chosen) + "\n";
   }
   if (buf && cap > 0) {
     const size_t n = std::min<size_t>(out.size(), (size_t)cap - 1);

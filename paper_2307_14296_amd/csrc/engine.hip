@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <cmath>
+
 #include "internal.h"
 
 // ------------------------------------------------------------ allocation
@@ -83,6 +85,23 @@ void Arena::trim() {
     chunks.pop_back();
     used.pop_back();
   }
+}
+
+// How many of n vectors, each needing bytes_per_vec of working memory, fit
+// in the device memory that is still free (and under the context's cap).
+// Unused arena chunks are released first so that they count as free.
+int fit_vectors(cclr_ctx* c, double bytes_per_vec, int n) {
+  if (n <= 1) return n;
+  c->arena.trim();
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  double budget = 0.8 * (double)fr;
+  if (c->opt.device_mem_cap) {
+    const double left = c->opt.device_mem_cap > c->allocated ? (double)(c->opt.device_mem_cap - c->allocated) : 0.0;
+    budget = std::min(budget, left);
+  }
+  const double k = budget / std::max(bytes_per_vec, 1.0);
+  return (int)std::max(1.0, std::min((double)n, std::floor(k)));
 }
 
 // ------------------------------------------------------------------ views
@@ -497,9 +516,28 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
 }
 
 // Autotuner.  The first time a large product of a given shape class (M, N,
-// K, batch, operand layouts) is requested, every FP64 kernel variant is
+// K, batch, operand layouts) is requested, every MFMA kernel variant is
 // timed once with HIP events on a scratch output of the same strides, and
 // the fastest is cached in the context.  Small products use the default.
+// The row count M and the batch count carry the number of vectors a
+// transform is applied to, which changes from call to call (a lockstep
+// solve whose active right-hand sides converge one by one): they are timed
+// on at most kTuneRows rows and kTuneBatch batch entries and classed by
+// octave; N and K are classed by quarter octave.
+constexpr int kTuneRows = 8192, kTuneBatch = 16;
+int octave_bucket(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+int shape_bucket(int x) {
+  if (x <= 64) return x;
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  const int q = p / 4;
+  return ((x + q - 1) / q) * q;
+}
+
 void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   const double flops = 8.0 * g.M * (double)g.N * g.K * g.batch;
@@ -507,18 +545,21 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
     launch_zgemm(g, c->stream);
     return;
   }
-  const auto key = std::make_tuple(g.M, g.N, g.K, g.batch,
+  const int tmr = std::min(g.M, kTuneRows), tbt = g.nb2 > 1 ? g.batch : std::min(g.batch, kTuneBatch);
+  const auto key = std::make_tuple(octave_bucket(tmr), shape_bucket(g.N), shape_bucket(g.K), octave_bucket(tbt),
                                    (g.sAk == 1 ? 1 : 0) + (g.sBn == 1 ? 2 : 0) + (g.nb2 > 1 ? 4 : 0));
   auto it = c->gemm_choice.find(key);
   if (it != c->gemm_choice.end()) {
     launch_zgemm_variant(g, it->second, c->stream);
     return;
   }
-  // scratch output covering the same index range
-  const i64 nb2 = g.nb2 > 1 ? g.nb2 : 1, nb1 = g.batch / nb2;
-  const i64 extent = (i64)(g.M - 1) * g.sCm + (i64)(g.N - 1) * g.sCn + (nb1 - 1) * g.sCb + (nb2 - 1) * g.sCb2 + 1;
-  Arena::Mark mk = c->arena.mark();
+  // the timed product: the leading rows and batch entries, on a scratch output covering their index range
   GemmArgs h = g;
+  h.M = tmr;
+  h.batch = tbt;
+  const i64 nb2 = h.nb2 > 1 ? h.nb2 : 1, nb1 = h.batch / nb2;
+  const i64 extent = (i64)(h.M - 1) * h.sCm + (i64)(h.N - 1) * h.sCn + (nb1 - 1) * h.sCb + (nb2 - 1) * h.sCb2 + 1;
+  Arena::Mark mk = c->arena.mark();
   h.C = (cplx*)c->arena.get(sizeof(cplx) * (size_t)extent);
   h.beta = 0;
   hipEvent_t e0, e1;
@@ -528,7 +569,7 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   launch_zgemm_variant(h, gemm_default_variant(g), c->stream);  // warm caches and clocks
   int best = gemm_default_variant(g);
   double tbest = 1e300;
-  for (int v = 0; v < GEMM_NVAR; ++v) {
+  for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) {  // the simple kernel (variant 0) never competes
     HIPCHK(hipEventRecord(e0, c->stream));
     launch_zgemm_variant(h, v, c->stream);
     HIPCHK(hipEventRecord(e1, c->stream));
@@ -553,9 +594,11 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   }
   c->arena.reset(mk);
   c->gemm_choice[key] = best;
+  std::vector<std::pair<int, double>> rec;
+  for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) rec.push_back({v, ms[v]});
   c->gemm_tuning_log.push_back({std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + " b" +
                                     std::to_string(g.batch) + " layout" + std::to_string(std::get<4>(key)),
-                                ms});
+                                rec, best});
   launch_zgemm_variant(g, best, c->stream);
 }
 

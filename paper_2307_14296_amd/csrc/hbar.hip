@@ -1,8 +1,9 @@
 // Property-independent Hbar intermediates (SI, "EOM-EE sigma-vectors and
 // intermediates": eqs. F_im, F_ea, F_me, W_ijmn, W_mbej, W_iemn, W_efam,
 // W_efab, barW_mbej, W_mnie, W_amef and tau).  Stored unpacked with
-// W[p][q][r][s] = W^pq_rs (bra pq, ket rs) and F[p][q] = F^p_q; W^ef_ab is
-// also kept packed (a>b, e>f) for the particle-particle ladder.
+// W[p][q][r][s] = W^pq_rs (bra pq, ket rs) and F[p][q] = F^p_q, except
+// W^ef_ab, which is built and kept only packed (e>f, a>b) for the
+// particle-particle ladder: no v^4 tensor is formed beyond the integrals.
 //
 // Sign/index readings of the printed equations (each decided by second-
 // quantization brute force on random complex data): F^a_e is the Hbar
@@ -10,7 +11,6 @@
 // carries -P(ef) V^en_ag t^gf_mn.
 #include "internal.h"
 
-void launch_pack_vvvv(int v, const cplx* W, cplx* Wp, hipStream_t s);
 void launch_diag(int o, int v, const cplx* Foo, const cplx* Fvv, cplx* diag, hipStream_t s);
 
 void build_intermediates(cclr_ctx* c) {
@@ -43,12 +43,11 @@ void build_intermediates(cclr_ctx* c) {
   alloc(c->Wvovv, v * o * v * v);
   alloc(c->Wovoo, o * v * o * o);
   alloc(c->Wvvvo, v * v * v * o);
-  alloc(c->Wvvvv, v * v * v * v);
 
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o}), Wbar = ten(c->Wbar, {o, v, v, o});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
-  Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o}), Wvvvv = ten(c->Wvvvv, {v, v, v, v});
+  Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
   Ten Voovv = Vblk(c, "oovv");
 
   // F^i_m = f^i_m + f^i_e t^e_m + V^in_me t^e_n + 1/2 V^in_ef tau^ef_mn
@@ -92,15 +91,41 @@ void build_intermediates(cclr_ctx* c) {
   // W^am_ef = V^am_ef - V^nm_ef t^a_n
   tcopy(c, Wvovv, "amef", Vblk(c, "vovv"), "amef", one);
   contract(c, mone, Voovv, "nmef", t1, "na", Wvovv, "amef");
-  // W^ef_ab = V^ef_ab - P(ef) V^mf_ab t^e_m + 1/2 V^mn_ab tau^ef_mn
-  tcopy(c, Wvvvv, "efab", Vblk(c, "vvvv"), "efab", one);
+  // W^ef_ab = V^ef_ab - P(ef) V^mf_ab t^e_m + 1/2 V^mn_ab tau^ef_mn, packed: Wp[EF][AB]
   {
-    Ten w = tmp(c, {v, v, v, v});
-    contract(c, one, Vblk(c, "ovvv"), "mfab", t1, "me", w, "efab", false);
-    tcopy(c, Wvvvv, "efab", w, "efab", mone);
-    tcopy(c, Wvvvv, "efab", w, "feab", one);
+    const i64 V2 = c->V2(), O2 = c->O2();
+    c->Wp.alloc(c, sizeof(cplx) * (size_t)(V2 * V2));
+    launch_pack_vvvv((int)v, c->Vvvvv.c(), c->Wp.c(), c->stream);
+    Arena::Mark m2 = c->arena.mark();
+    // - P(ef) t^e_m V^mf_ab: Y[e][f][AB] = t^e_m V^mf_ab over column blocks of AB
+    cplx* P = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(o * v * V2));  // P[m][f][AB] = V^mf_ab
+    launch_pack_pairs(o * v, (int)v, c->Vovvv.c(), P, c->stream);
+    const i64 nc = std::max<i64>(1, std::min<i64>(V2, (i64)(size_t(1) << 27) / (v * v)));  // Y block <= 2 GiB
+    Ten Y = tmp(c, {v, v, nc});
+    for (i64 c0 = 0; c0 < V2; c0 += nc) {
+      const i64 n = std::min(nc, V2 - c0);
+      Ten Pb;
+      Pb.p = P + c0;
+      Pb.nd = 3;
+      Pb.dim[0] = o, Pb.dim[1] = v, Pb.dim[2] = n;
+      Pb.st[0] = v * V2, Pb.st[1] = V2, Pb.st[2] = 1;
+      Ten Yb = ten(Y.p, {v, v, n});
+      contract(c, one, t1, "me", Pb, "mfX", Yb, "efX", false);
+      launch_pair_antisym_acc((int)v, (int)n, Yb.p, c->Wp.c() + c0, V2, -1.0, c->stream);
+    }
+    // + sum_(m>n) tau^ef_mn V^mn_ab: packed product over the occupied pairs
+    VecSet tp = packed_buf(c, 1), vp = packed_buf(c, 1);
+    launch_pack_full(1, (int)o, (int)v, t1.p, tau.p, tp.s, tp.d, c->stream);
+    launch_pack_full(1, (int)o, (int)v, t1.p, c->Voovv.c(), vp.s, vp.d, c->stream);
+    GemmArgs g{};
+    g.M = (int)V2; g.N = (int)V2; g.K = (int)O2; g.batch = 1;
+    g.A = tp.d; g.sAm = 1; g.sAk = V2;
+    g.B = vp.d; g.sBk = V2; g.sBn = 1;
+    g.C = c->Wp.c(); g.sCm = V2; g.sCn = 1;
+    g.ar = 1.0; g.ai = 0.0; g.beta = 1;
+    tuned_gemm(c, g);
+    c->arena.reset(m2);
   }
-  contract(c, half, Voovv, "mnab", tau, "mnef", Wvvvv, "efab");
   // W^ie_mn = V^ie_mn - F^i_f t^ef_mn - W^io_mn t^e_o + 1/2 V^ie_fg tau^fg_mn
   //          + P(mn) barW^ie_fn t^f_m + P(mn) V^io_mf t^ef_no
   tcopy(c, Wovoo, "iemn", Vblk(c, "ovoo"), "iemn", one);
@@ -117,14 +142,24 @@ void build_intermediates(cclr_ctx* c) {
   // W^ef_am = V^ef_am - P(ef) V^en_ag t^gf_mn + W^ef_ag t^g_m + F^n_a t^ef_mn
   //          + 1/2 V^no_am tau^ef_no - P(ef) barW^nf_am t^e_n
   tcopy(c, Wvvvo, "efam", Vblk(c, "vvvo"), "efam", one);
+  // W^ef_ag t^g_m is formed from the pieces of W^ef_ag (no unpacked W^ef_ab):
+  //   V^ef_ag t^g_m - P(ef) t^e_n (V^nf_ag t^g_m) + 1/2 tau^ef_no (V^no_ag t^g_m)
   {
     Ten w = tmp(c, {v, v, v, o});
     contract(c, mone, Vblk(c, "vovv"), "enag", t2, "mngf", w, "efam", false);
     contract(c, mone, Wbar, "nfam", t1, "ne", w, "efam");
+    Ten Q = tmp(c, {o, v, v, o});
+    contract(c, one, Vblk(c, "ovvv"), "nfag", t1, "mg", Q, "nfam", false);
+    contract(c, mone, t1, "ne", Q, "nfam", w, "efam");
     tcopy(c, Wvvvo, "efam", w, "efam", one);
     tcopy(c, Wvvvo, "efam", w, "feam", mone);
   }
-  contract(c, one, Wvvvv, "efag", t1, "mg", Wvvvo, "efam");
+  contract(c, one, Vblk(c, "vvvv"), "efag", t1, "mg", Wvvvo, "efam");
+  {
+    Ten R = tmp(c, {o, o, v, o});
+    contract(c, one, Voovv, "noag", t1, "mg", R, "noam", false);
+    contract(c, half, tau, "noef", R, "noam", Wvvvo, "efam");
+  }
   contract(c, one, Fov, "na", t2, "mnef", Wvvvo, "efam");
   contract(c, half, Vblk(c, "oovo"), "noam", tau, "noef", Wvvvo, "efam");
 
@@ -141,9 +176,7 @@ void build_intermediates(cclr_ctx* c) {
   tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
   c->WvovvL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
   tcopy(c, ten(c->WvovvL, {o, v, v, v}), "iafe", Wvovv, "eifa", one, false);
-  // packed ladder operator and preconditioner diagonal
-  c->Wp.alloc(c, sizeof(cplx) * (size_t)(c->V2() * c->V2()));
-  launch_pack_vvvv((int)v, c->Wvvvv.c(), c->Wp.c(), c->stream);
+  // preconditioner diagonal
   c->diag.alloc(c, sizeof(cplx) * (size_t)(c->ns() + c->nd()));
   launch_diag((int)o, (int)v, c->Foo.c(), c->Fvv.c(), c->diag.c(), c->stream);
   HIPCHK(hipStreamSynchronize(c->stream));

@@ -149,6 +149,9 @@ void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i
 void run_gemm(cclr_ctx* c, const GemmArgs& g);
 // FP64 GEMM through the autotuner (large products: variant timed once per shape class)
 void tuned_gemm(cclr_ctx* c, const GemmArgs& g);
+// extent rounded up to the autotuner's quarter-octave and octave shape classes
+int shape_bucket(int x);
+int octave_bucket(int x);
 
 struct CopyArgs {
   int nd;
@@ -174,6 +177,15 @@ void launch_unpack(int nvec, int o, int v, const cplx* s, const cplx* d, cplx* r
 // packed doubles -> ring layout rr[k][i][a][m][e] = r^ae_im
 void launch_unpack_ring(int nvec, int o, int v, const cplx* d, cplx* rr, hipStream_t st);
 void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cplx* s, cplx* d, hipStream_t st);
+// pair packing of the last two indices: dst[r][AB] = src[r][a][b] (a > b)
+void launch_pack_pairs(i64 rows, int v, const cplx* src, cplx* dst, hipStream_t s);
+// dst[r][a][b] += alpha src[r][AB], dst[r][b][a] -= alpha src[r][AB]
+void launch_unpack_pairs_acc(i64 rows, int v, const cplx* src, cplx* dst, double alpha, hipStream_t s);
+// W[EF][X] += alpha (Y[e][f][X] - Y[f][e][X]), e > f, X < nc; W row stride ldw
+void launch_pair_antisym_acc(int v, int nc, const cplx* Y, cplx* W, i64 ldw, double alpha, hipStream_t s);
+// dst[e][f][a][b] = W^ef_ab from Wp[EF][AB]
+void launch_unpack_vvvv(int v, const cplx* Wp, cplx* dst, hipStream_t s);
+void launch_pack_vvvv(int v, const cplx* W, cplx* Wp, hipStream_t s);
 // out(packed) += X0 + P(ab)Xa + P(ij)Xi + P(ab)P(ij)Xai  (any X may be null),
 // singles out += S1; then out -= z_k * r_k  (z may be null).  X0, Xa, Xi are
 // [k][i][j][a][b]; Xai is [k][i][j][a][b], or [k][i][a][j][b] if xai_ring.
@@ -194,8 +206,8 @@ struct cclr_ctx {
   DevBuf f, Voooo, Vooov, Voovv, Vovov, Vovvv, Vvvvv, t1, t2;
   bool have_H = false, have_t = false, have_lam = false;
   // intermediates (unpacked, W[p][q][r][s] = W^pq_rs)
-  DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo, Wvvvv;
-  DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f
+  DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo;
+  DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f (the only copy of W^ab_ef)
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
   DevBuf WvvvoT;     // WvvvoT[j][e][a][b] = W^ab_ej
   DevBuf WvvvoL, WvovvL;  // WvvvoL[a][m][e][f] = W^ef_am, WvovvL[i][a][f][e] = W^ei_fa (left transform)
@@ -214,7 +226,12 @@ struct cclr_ctx {
   // GEMM autotuner: best FP64 kernel variant per shape class, and a record of
   // the timings that decided it (variant -> ms)
   std::map<std::tuple<int, int, int, int, int>, int> gemm_choice;
-  std::vector<std::pair<std::string, std::vector<double>>> gemm_tuning_log;
+  struct TuneRecord {
+    std::string shape;
+    std::vector<std::pair<int, double>> ms;  // (variant, ms) of every timed variant
+    int chosen;
+  };
+  std::vector<TuneRecord> gemm_tuning_log;
   bool autotune = true;
   // kernel variant of grouped multi-context launches, per set of product shapes
   std::map<std::string, int> group_choice;
@@ -276,6 +293,8 @@ int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rh
                  cclr_solve_info* info);
 // nvec packed vectors from the arena
 VecSet packed_buf(cclr_ctx* c, int n);
+// how many of n vectors with the given working memory each fit in free device memory (>= 1)
+int fit_vectors(cclr_ctx* c, double bytes_per_vec, int n);
 void build_xi(cclr_ctx* c, const cplx* X, const VecSet& out);
 void build_eta(cclr_ctx* c, const cplx* X, const VecSet& out);
 void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out);

@@ -122,7 +122,19 @@ struct HessPre {
 };
 
 // (x F)_mu for nv packed response vectors x -> packed out  (SI, (t^X F)^k_c and (t^X F)^kl_cd)
+static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out);
+
+// t^X F for several vectors, in groups whose temporaries fit in device memory
 void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
+  const i64 ov = c->ns(), nd = c->nd(), oovv = (i64)c->o * c->o * c->v * c->v;
+  const int chunk = fit_vectors(c, 10.0 * (double)oovv * sizeof(cplx) + 2.0 * (ov + nd) * sizeof(cplx), xin.n);
+  for (int k0 = 0; k0 < xin.n; k0 += chunk) {
+    const int n = std::min(chunk, xin.n - k0);
+    hessian_block(c, VecSet{xin.s + k0 * ov, xin.d + k0 * nd, n}, VecSet{out.s + k0 * ov, out.d + k0 * nd, n});
+  }
+}
+
+static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
   const i64 o = c->o, v = c->v, nv = xin.n;
   Arena::Mark mk = c->arena.mark();
   const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5), qtr = cx(0.25), mqtr = cx(-0.25);

@@ -56,7 +56,7 @@ void op_gemm(cclr_ctx* c, const GemmArgs& g, int which) {
   void* ws = c->arena.get(split_bytes(g.M, g.K));
   const SplitMat A = launch_split_bf16(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, ws, c->stream);
   // kernel variant (wave layout) timed once per shape
-  const auto key = std::make_tuple(g.M, g.N, g.K, 1, 200 + which);
+  const auto key = std::make_tuple(octave_bucket(g.M), shape_bucket(g.N), shape_bucket(g.K), 1, 200 + which);
   auto it = c->gemm_choice.find(key);
   int var = 0;
   if (it != c->gemm_choice.end()) {
@@ -80,9 +80,11 @@ void op_gemm(cclr_ctx* c, const GemmArgs& g, int which) {
       if (t < best) best = t, var = v;
     }
     c->gemm_choice[key] = var;
+    std::vector<std::pair<int, double>> rec;
+    for (int v = 0; v < (int)ms.size(); ++v) rec.push_back({v, ms[v]});
     c->gemm_tuning_log.push_back({"bf16x3 " + std::to_string(g.M) + "x" + std::to_string(g.N) + "x" +
                                       std::to_string(g.K) + " op" + std::to_string(which),
-                                  ms});
+                                  rec, var});
   }
   launch_cgemm_bf16x3(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream, var);
   c->arena.reset(mk);

@@ -543,16 +543,39 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
 // split-BF16: the Davidson solve with iterative refinement and subspace
 // recycling (see davidson): reduced-precision ladder and ring products for
 // the trial vectors, FP64 true residuals, until ||R|| <= tol ||b||.
+// Right-hand sides advance in lockstep; when the subspaces and transform
+// temporaries of all of them do not fit in free device memory they are
+// solved in consecutive groups that do.
 int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
                  cclr_solve_info* info) {
   const double tol = c->opt.tol;
-  if (c->opt.prec == CCLR_FP64) {
-    c->sigma_prec = CCLR_FP64;
-    return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter, CCLR_FP64, 0.0);
-  }
+  const int lowp = c->opt.prec;
   // inner accuracy: what the reduced-precision products can deliver
-  const double inner = c->opt.prec == CCLR_FP32 ? 1e-6 : 1e-4;
-  return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter, c->opt.prec, inner);
+  const double inner = lowp == CCLR_FP64 ? 0.0 : (lowp == CCLR_FP32 ? 1e-6 : 1e-4);
+  if (lowp == CCLR_FP64) c->sigma_prec = CCLR_FP64;
+  const i64 ov = c->ns(), nd = c->nd(), oovv = (i64)c->o * c->o * c->v * c->v;
+  const int ms = std::max(4, std::min(c->opt.max_subspace, 120));
+  const double per = (2.0 * ms + 10.0) * (double)(ov + nd) * sizeof(cplx) + 10.0 * (double)oovv * sizeof(cplx);
+  const int chunk = fit_vectors(c, per, nr);
+  if (chunk >= nr) return davidson(c, side, nr, zh, rhs, xout, info, tol, c->opt.maxiter, lowp, inner);
+  cclr_solve_info all{};
+  all.converged = 1;
+  int rc = CCLR_OK;
+  auto t0 = std::chrono::steady_clock::now();
+  for (int k0 = 0; k0 < nr; k0 += chunk) {
+    const int n = std::min(chunk, nr - k0);
+    const VecSet r{rhs.s + k0 * ov, rhs.d + k0 * nd, n}, x{xout.s + k0 * ov, xout.d + k0 * nd, n};
+    cclr_solve_info part{};
+    const int pr = davidson(c, side, n, zh + k0, r, x, &part, tol, c->opt.maxiter, lowp, inner);
+    if (pr == CCLR_ENOTCONV) rc = CCLR_ENOTCONV;
+    all.iters = std::max(all.iters, part.iters);
+    all.converged = all.converged && part.converged;
+    all.resnorm = std::max(all.resnorm, part.resnorm);
+    all.nsigma += part.nsigma;
+  }
+  all.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = all;
+  return rc;
 }
 
 // ------------------------------------------------------------ EOM-EE roots
