@@ -146,6 +146,69 @@ def spectrum_bench(cc, dev, o=16, v=120, seed=2, nfreq=16):
         torch.cuda.empty_cache()
 
 
+def diff_bench(cc, dev, o=24, v=240, seed=5, omega=0.0774):
+    """Differentiation at o=24, v=240: <<mu; m>>(omega) with an electric
+    dipole mu and the magnetic-like m = i(A - A^T)/2, gamma = 0; forward, then
+    the backward of Re and of Im <<mu; m>> with respect to the perturbation
+    matrices, the Fock matrix and all six integral blocks."""
+    import numpy as np
+    import torch
+    from gen import synth as s
+    t0 = time.perf_counter()
+    pb, f, V, t1, t2, X = make_inputs(o, v, seed, dev)
+    mu, m = X[0], s.magnetic_like(pb, 0, dev)
+    del X
+    opt = cc.cclr_default_options()
+    opt.max_subspace = 24
+    opt.tol = 1e-8
+    ctx = cc.cclr_create(o, v, opt)
+    out = {"workload": f"<<mu; m>> backward o={o} v={v} complex128, omega {omega}, gamma 0 (Re and Im, "
+                       f"gradients w.r.t. mu, m, f and the six integral blocks)"}
+    try:
+        cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+        shapes = [tuple(V[k].shape) for k in s.CANONICAL_BLOCKS]
+        del V
+        torch.cuda.empty_cache()
+        tb = time.perf_counter()
+        cc.cclr_set_amplitudes(ctx, t1, t2)
+        torch.cuda.synchronize()
+        out["setup_s"] = round(time.perf_counter() - t0, 2)
+        out["intermediates_s"] = round(time.perf_counter() - tb, 2)
+        log(f"diff: o={o} v={v} set up in {out['setup_s']} s")
+        tf = time.perf_counter()
+        rc, val, info = cc.cclr_response_function(ctx, [mu, m], [omega], [0.0])
+        torch.cuda.synchronize()
+        out["forward_s"] = round(time.perf_counter() - tf, 2)
+        out["forward_transforms"] = info.nsigma
+        out["mu_m"] = [val[0][0][1].real, val[0][0][1].imag]
+        log(f"diff: forward {out['forward_s']} s, <<mu;m>> = {val[0][0][1]}")
+        n = o + v
+        dX = [torch.empty((n, n), dtype=torch.complex128, device=dev) for _ in range(2)]
+        df = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        dV = [torch.empty(sh, dtype=torch.complex128, device=dev) for sh in shapes]
+        for part, w in (("re", 1.0), ("im", 1j)):
+            G = np.zeros((1, 2, 2), dtype=np.complex128)
+            G[0, 0, 1] = w
+            tg = time.perf_counter()
+            rcb, binfo = cc.cclr_response_backward(ctx, [mu, m], [omega], [0.0], G, dX=dX, df=df, dV=dV)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tg
+            out[f"backward_{part}_s"] = round(dt, 2)
+            out[f"backward_{part}_transforms"] = binfo.nsigma
+            out[f"grad_{part}_norms"] = {"d_mu": torch.linalg.norm(dX[0]).item(), "d_m": torch.linalg.norm(dX[1]).item(),
+                                         "df": torch.linalg.norm(df).item(),
+                                         "dV": float(sum(torch.linalg.norm(d).item() ** 2 for d in dV) ** 0.5)}
+            log(f"diff: backward ({part}) {dt:.2f} s, rc {rcb}")
+        free, total = torch.cuda.mem_get_info()
+        out["device_memory_in_use_gb"] = round((total - free) / 1e9, 1)
+        del dX, df, dV
+    finally:
+        cc.cclr_destroy(ctx)
+        del f, t1, t2, mu, m
+        torch.cuda.empty_cache()
+    return out
+
+
 def ground_bench(cc, dev, o, v, seed, tol=1e-8, nchol_per_orbital=3, v_std=0.002):
     """CCSD ground state at the benchmark size: CROP from the MP2-seeded start
     (iterations, residual evaluations, time per residual), and the formation
@@ -335,6 +398,8 @@ def main():
                     help="skip the uneven multi-problem transform comparison")
     ap.add_argument("--no-spectrum", dest="spectrum", action="store_false",
                     help="skip the damped-spectrum lockstep vs per-frequency comparison (o=16, v=120)")
+    ap.add_argument("--no-diff", dest="diff", action="store_false",
+                    help="skip the backward of <<mu; m>> at o=24, v=240 (about 240 GB of device memory)")
     ap.add_argument("--no-ground", dest="ground", action="store_false",
                     help="skip the CCSD ground-state (CROP) and Cholesky-integral timings")
     ap.add_argument("--mixed-precs", default="fp32,bf16x3",
@@ -510,12 +575,23 @@ def main():
             mx["ladder_tflops_fp64_equivalent"] = round(mres["fl"] / (mres["ms"] * 1e-3) / 1e12, 3)
             mx["ladder_avg_launch_ms"] = round(mres["ms"] / max(1, mres["nl"]), 4)
         line["mixed_precision"][p] = mx
+    def section(name, fn):
+        """Extra measurements: a failure is recorded in the line, not fatal to it."""
+        try:
+            line[name] = fn()
+        except Exception as e:  # noqa: BLE001
+            log(f"{name}: failed: {e}")
+            line[name] = {"error": str(e)}
+        torch.cuda.empty_cache()
+
     if args.batching and args.mode == "response":
-        line["batching"] = batching_bench(cc, dev)
+        section("batching", lambda: batching_bench(cc, dev))
     if args.spectrum and args.mode == "response":
-        line["spectrum"] = spectrum_bench(cc, dev)
+        section("spectrum", lambda: spectrum_bench(cc, dev))
     if args.ground and args.mode == "response":
-        line["ground_state"] = ground_bench(cc, dev, o, v, args.seed)
+        section("ground_state", lambda: ground_bench(cc, dev, o, v, args.seed))
+    if args.diff and args.mode == "response":
+        section("differentiation", lambda: diff_bench(cc, dev))
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline()
