@@ -62,6 +62,10 @@ int cclr_dbg_profile_read(cclr_ctx* ctx, int largest_only, long long* launches, 
  * the solvers set it themselves. */
 int cclr_dbg_set_sigma_prec(cclr_ctx* ctx, int prec);
 
+/* Relative residual at which a reduced-precision inner solve hands over to
+ * an FP64 refinement step (0: the default of the context's precision). */
+int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
+
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
  * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
  * the variant in use, which within 2% of the fastest prefers the grouped

@@ -189,6 +189,12 @@ int cclr_dbg_set_sigma_prec(cclr_ctx* c, int prec) {
   return CCLR_OK;
 }
 
+int cclr_dbg_set_inner_tol(cclr_ctx* c, double tol) {
+  if (!c || !(tol >= 0.0) || tol >= 1.0) return CCLR_EINVAL;
+  c->inner_tol = tol;
+  return CCLR_OK;
+}
+
 int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {
   if (!c) return CCLR_EINVAL;
   if (enable >= 0) c->autotune = enable != 0;

@@ -525,6 +525,7 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
 // on at most kTuneRows rows and kTuneBatch batch entries and classed by
 // octave; N and K are classed by quarter octave.
 constexpr int kTuneRows = 8192, kTuneBatch = 16;
+bool gemm_variant_grouped(int variant) { return variant > GEMM_64x64_G4 && variant < GEMM_NVAR; }
 int octave_bucket(int x) {
   int p = 1;
   while (p < x) p *= 2;
@@ -586,10 +587,10 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   (void)hipEventDestroy(e1);
   // within the timing noise (2%) of the fastest, prefer the XCD-grouped tile
   // order: it re-reads the operands from HBM far less for the same time
-  if (best <= GEMM_64x64_G4) {
+  if (!gemm_variant_grouped(best)) {
     int grp = -1;
-    for (int v = GEMM_64x64_G4 + 1; v < GEMM_NVAR; ++v)
-      if (ms[v] <= 1.02 * tbest && (grp < 0 || ms[v] < ms[grp])) grp = v;
+    for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v)
+      if (gemm_variant_grouped(v) && ms[v] <= 1.02 * tbest && (grp < 0 || ms[v] < ms[grp])) grp = v;
     if (grp >= 0) best = grp;
   }
   c->arena.reset(mk);

@@ -114,6 +114,7 @@ void launch_zgemm(const GemmArgs& g, hipStream_t s);
 // FP64 kernel variants (tile shape, three or four real products per complex
 // block); variants 4 + k run variant k (k = 1..4) in the XCD-grouped tile order
 enum { GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4, GEMM_NVAR = 9 };
+bool gemm_variant_grouped(int variant);
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);
 int gemm_default_variant(const GemmArgs& g);
 // Several products (same operand layouts: ak = unit-stride k in A, bn = unit-
@@ -223,6 +224,8 @@ struct cclr_ctx {
   // (CCLR_FP64 for the FP64 path and every true residual; opt.prec inside the
   // low-precision inner solves)
   int sigma_prec = CCLR_FP64;
+  // relative residual at which a reduced-precision inner solve is refined (0: default)
+  double inner_tol = 0.0;
   // GEMM autotuner: best FP64 kernel variant per shape class, and a record of
   // the timings that decided it (variant -> ms)
   std::map<std::tuple<int, int, int, int, int>, int> gemm_choice;

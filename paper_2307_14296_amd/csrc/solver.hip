@@ -551,7 +551,7 @@ int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rh
   const double tol = c->opt.tol;
   const int lowp = c->opt.prec;
   // inner accuracy: what the reduced-precision products can deliver
-  const double inner = lowp == CCLR_FP64 ? 0.0 : (lowp == CCLR_FP32 ? 1e-6 : 1e-4);
+  const double inner = lowp == CCLR_FP64 ? 0.0 : c->inner_tol > 0.0 ? c->inner_tol : (lowp == CCLR_FP32 ? 1e-6 : 1e-4);
   if (lowp == CCLR_FP64) c->sigma_prec = CCLR_FP64;
   const i64 ov = c->ns(), nd = c->nd(), oovv = (i64)c->o * c->o * c->v * c->v;
   const int ms = std::max(4, std::min(c->opt.max_subspace, 120));
