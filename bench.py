@@ -350,7 +350,7 @@ def batching_bench(cc, dev, nvec=3, reps=3):
 
 
 LADDER_TRAFFIC = os.path.join(ROOT, "profiles", "ladder_gemm_o20v200_traffic.md")
-GEMM_SOURCE = os.path.join(ROOT, "paper_2307_14296_amd", "csrc", "kernels.hip")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2307_14296_amd", "csrc", "gemm_f64.hip")
 
 
 def ladder_traffic(variant):

@@ -1,0 +1,687 @@
+// Complex GEMM kernels of libcclr for gfx950: FP64 MFMA (three or four real
+// products per complex block), FP32 MFMA, the short-reduction VALU form and the split-K reduction.
+#include "internal.h"
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+// output row of v_mfma_f32_16x16x4_f32 for (lane, register)
+#define F32_ROW(lane, r) (4 * ((lane) >> 4) + (r))
+
+// --------------------------------------------------------------------------
+// Complex GEMM  C[b][m][n] (+)= alpha * sum_k A[b][m][k] * B[b][k][n]
+// with arbitrary element strides, lowered to four real FP64 MFMA products
+// per 16x16x4 complex block (Re*Re - Im*Im, Re*Im + Im*Re).
+// Workgroup tile 64x64 (complex), k-step 16; four waves, each owning a 32x32
+// sub-tile as 2x2 MFMA blocks.  v_mfma_f64_16x16x4_f64 operand layout:
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
+// j + 16*(i%4), register i/4 (measured on gfx950).
+// --------------------------------------------------------------------------
+namespace {
+constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 1;
+
+// element offset of batch bz (one or two batch indices)
+__device__ __forceinline__ i64 boff(const GemmArgs& g, i64 bz, i64 s1, i64 s2) {
+  if (g.nb2 <= 1) return bz * s1;
+  return (bz / g.nb2) * s1 + (bz % g.nb2) * s2;
+}
+
+__global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
+  __shared__ double sAr[GBK][GBM + GPAD], sAi[GBK][GBM + GPAD];
+  __shared__ double sBr[GBK][GBN + GPAD], sBi[GBK][GBN + GPAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const i64 bz = blockIdx.z;
+  int kbeg = 0, kend = g.K;
+  i64 bb = bz;  // batch index of the operands (the K chunk is folded into bz when splitting)
+  if (g.kchunk > 0) {
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
+  }
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const bool a_kfast = (g.sAk == 1);
+  const bool b_nfast = (g.sBn == 1);
+
+  d4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = d4{0, 0, 0, 0};
+      accI[i][j] = d4{0, 0, 0, 0};
+    }
+
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      int mm, kk;
+      if (a_kfast) { kk = e % GBK; mm = e / GBK; }
+      else { mm = e % GBM; kk = e / GBM; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      cplx x = make_double2(0.0, 0.0);
+      if (gm < g.M && gk < kend) x = A[(i64)gm * g.sAm + (i64)gk * g.sAk];
+      sAr[kk][mm] = x.x;
+      sAi[kk][mm] = g.conjA ? -x.y : x.y;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      int nn, kk;
+      if (b_nfast) { nn = e % GBN; kk = e / GBN; }
+      else { kk = e % GBK; nn = e / GBK; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      cplx x = make_double2(0.0, 0.0);
+      if (gn < g.N && gk < kend) x = B[(i64)gk * g.sBk + (i64)gn * g.sBn];
+      sBr[kk][nn] = x.x;
+      sBi[kk][nn] = g.conjB ? -x.y : x.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GBK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = sAr[kk][wm + i * 16 + (lane & 15)];
+        ai[i] = sAi[kk][wm + i * 16 + (lane & 15)];
+        br[i] = sBr[kk][wn + i * 16 + (lane & 15)];
+        bi[i] = sBi[kk][wn + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
+// W[b][s][m][n] summed over s in a fixed order into C[b][m][n]
+__global__ __launch_bounds__(256) void k_splitk_reduce(int nb, int S, int M, int N, const cplx* __restrict__ W,
+                                                       cplx* __restrict__ C, i64 sCb, i64 sCm, i64 sCn, double ar,
+                                                       double ai, int beta) {
+  const i64 mn = (i64)M * N, total = mn * nb, stride = (i64)gridDim.x * blockDim.x;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const i64 b = e / mn, r = e % mn;
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < S; ++q) {
+      const cplx w = W[(b * S + q) * mn + r];
+      sr += w.x;
+      si += w.y;
+    }
+    const i64 m = r / N, n = r % N;
+    cplx y = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+    cplx* dst = C + b * sCb + m * sCm + n * sCn;
+    if (beta) {
+      const cplx o = *dst;
+      y.x += o.x;
+      y.y += o.y;
+    }
+    *dst = y;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Short reductions (K <= 32): memory-bound products such as the o-index
+// terms of the doubles.  FP64 on the vector ALU: the threads of a workgroup
+// run along n (coalesced B and C), each keeps its column of B in registers
+// and sweeps a block of 32 rows of A held in LDS, so every element of B and
+// C moves once.
+// --------------------------------------------------------------------------
+constexpr int SK_MAX = 32, SK_MB = 32;
+
+__global__ __launch_bounds__(256) void k_zgemm_smallk(GemmArgs g) {
+  __shared__ cplx sA[SK_MB][SK_MAX];
+  const i64 bz = blockIdx.z;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int m0 = blockIdx.y * SK_MB;
+  const cplx* __restrict__ A = g.A + boff(g, bz, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bz, g.sBb, g.sBb2);
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+  const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+  for (int e = threadIdx.x; e < SK_MB * SK_MAX; e += 256) {
+    const int mm = e / SK_MAX, kk = e % SK_MAX;
+    cplx x = make_double2(0.0, 0.0);
+    if (m0 + mm < g.M && kk < g.K) {
+      x = A[(i64)(m0 + mm) * g.sAm + (i64)kk * g.sAk];
+      x.y *= sa;
+    }
+    sA[mm][kk] = x;
+  }
+  __syncthreads();
+  if (n >= g.N) return;
+  cplx b[SK_MAX];
+#pragma unroll
+  for (int k = 0; k < SK_MAX; ++k) {
+    b[k] = make_double2(0.0, 0.0);
+    if (k < g.K) {
+      b[k] = B[(i64)k * g.sBk + (i64)n * g.sBn];
+      b[k].y *= sb;
+    }
+  }
+  const int mend = min(SK_MB, g.M - m0);
+  for (int mm = 0; mm < mend; ++mm) {
+    double xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int k = 0; k < SK_MAX; ++k) {
+      const cplx a = sA[mm][k];
+      xr += a.x * b[k].x - a.y * b[k].y;
+      xi += a.x * b[k].y + a.y * b[k].x;
+    }
+    cplx y = make_double2(g.ar * xr - g.ai * xi, g.ar * xi + g.ai * xr);
+    cplx* dst = C + (i64)(m0 + mm) * g.sCm + (i64)n * g.sCn;
+    if (g.beta) {
+      const cplx o = *dst;
+      y.x += o.x;
+      y.y += o.y;
+    }
+    *dst = y;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pipelined complex GEMM with three real products per complex block (Gauss):
+//   k1 = (Ar + Ai) Br,  k2 = Ar (Bi - Br),  k3 = Ai (Br + Bi),
+//   Re C = k1 - k3,     Im C = k1 + k2.
+// Same contract as k_zgemm; specialised on the operand layouts (which index
+// is unit-stride in A and in B).  The LDS holds the three planes of each
+// operand; the next K-tile is fetched into registers while the MFMAs consume
+// the current one, and LDS is double buffered so each K-tile costs one
+// barrier.  Four waves in a 2x2 arrangement, each owning a (BM/2)x(BN/2)
+// sub-tile.
+// --------------------------------------------------------------------------
+template <int BM, int BN, bool AK, bool BNF, bool G3>
+__device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, const int n0, const i64 bz) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  constexpr int NP = G3 ? 3 : 2;
+  __shared__ double sA[2][NP][BK][BM + 1];  // Ar, Ai (, Ar + Ai)
+  __shared__ double sB[2][NP][BK][BN + 1];  // Br, Bi - Br (, Br + Bi)  |  Br, Bi
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int kbeg = 0, kend = g.K;
+  i64 bb = bz;  // batch index of the operands (the K chunk is folded into bz when splitting)
+  if (g.kchunk > 0) {
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
+  }
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+
+  cplx ra[LA], rb[LB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[r] = (gm < g.M && gk < kend) ? A[(i64)gm * g.sAm + (i64)gk * g.sAk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      const int gn = n0 + nn, gk = k0 + kk;
+      rb[r] = (gn < g.N && gk < kend) ? B[(i64)gk * g.sBk + (i64)gn * g.sBn] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const double re = ra[r].x, im = sa * ra[r].y;
+      sA[buf][0][kk][mm] = re;
+      sA[buf][1][kk][mm] = im;
+      if (G3) sA[buf][2][kk][mm] = re + im;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      const double re = rb[r].x, im = sb * rb[r].y;
+      sB[buf][0][kk][nn] = re;
+      sB[buf][1][kk][nn] = G3 ? im - re : im;
+      if (G3) sB[buf][2][kk][nn] = re + im;
+    }
+  };
+
+  d4 k1[FM][FN], k2[FM][FN], k3[G3 ? FM : 1][G3 ? FN : 1];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      k1[i][j] = d4{0, 0, 0, 0};
+      k2[i][j] = d4{0, 0, 0, 0};
+      if (G3) k3[G3 ? i : 0][G3 ? j : 0] = d4{0, 0, 0, 0};
+    }
+
+  gload(kbeg);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double ar[FM], ai[FM], as[FM], br[FN], bd[FN], bs[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int mm = wm + i * 16 + (lane & 15);
+        ar[i] = sA[buf][0][kk][mm];
+        ai[i] = sA[buf][1][kk][mm];
+        as[i] = G3 ? sA[buf][NP - 1][kk][mm] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int nn = wn + j * 16 + (lane & 15);
+        br[j] = sB[buf][0][kk][nn];
+        bd[j] = sB[buf][1][kk][nn];
+        bs[j] = G3 ? sB[buf][NP - 1][kk][nn] : 0.0;
+      }
+      if (G3) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], br[j], k1[i][j], 0, 0, 0);
+            k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bd[j], k2[i][j], 0, 0, 0);
+            k3[G3 ? i : 0][G3 ? j : 0] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bs[j], k3[G3 ? i : 0][G3 ? j : 0], 0, 0, 0);
+          }
+      } else {
+        // four products: k1 = Re, k2 = Im  (bd holds Bi here)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], k1[i][j], 0, 0, 0);
+            k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bd[j], k2[i][j], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bd[j], k1[i][j], 0, 0, 0);
+            k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], k2[i][j], 0, 0, 0);
+          }
+      }
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double cr = G3 ? k1[i][j][r] - k3[G3 ? i : 0][G3 ? j : 0][r] : k1[i][j][r];
+          const double ci = G3 ? k1[i][j][r] + k2[i][j][r] : k2[i][j][r];
+          cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            const cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
+// Tile order of the one-dimensional launch.  The hardware deals workgroups
+// round-robin over the 8 XCDs (each with its own L2), so workgroup w is
+// mapped to a contiguous run of the tile sequence on XCD w % 8.  In the
+// sequence the batch index is slowest; inside a batch, groups of gm M-tiles
+// sweep the N-tiles with M fastest, so the tiles that run together on one
+// XCD share both their B column panels (gm of them per panel) and their A
+// row panels (across the N-tiles in flight).
+// With xcd = 0 and gm = tm this is the plain order (M fastest, then N, then
+// the batch index) in which consecutive tiles land on different XCDs.
+__device__ __forceinline__ void tile_of(int w, int T, int tm, int tn, int gm, int xcd, int& mi, int& ni, int& bz) {
+  const int x = w & 7, l = w >> 3, per = T >> 3, rem = T & 7;
+  const int t = xcd ? (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + l : w;
+  const int per_b = tm * tn;
+  bz = t / per_b;
+  const int r = t - bz * per_b;
+  const int grp = r / (gm * tn), within = r - grp * gm * tn;
+  const int gme = min(gm, tm - grp * gm);
+  mi = grp * gm + within % gme;
+  ni = within / gme;
+}
+
+template <int BM, int BN, bool AK, bool BNF, bool G3>
+__global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g, int tm, int tn, int gm, int xcd) {
+  int mi, ni, bz;
+  tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
+  zgemm_tile<BM, BN, AK, BNF, G3>(g, mi * BM, ni * BN, bz);
+}
+
+// Grouped persistent form: one launch walks the tiles of several products
+// (problem p owns tiles [tstart[p], tstart[p+1])), each workgroup taking
+// every gridDim.x-th tile.  The LDS of a tile is released by the barrier
+// that ends its last K step, so consecutive tiles reuse it safely.
+template <int BM, int BN, bool AK, bool BNF, bool G3>
+__global__ __launch_bounds__(256) void k_zgemm_group(const GemmArgs* __restrict__ probs, const int* __restrict__ tstart,
+                                                     int nprob, int total) {
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int p = 0;
+    while (p + 1 < nprob && t >= tstart[p + 1]) ++p;
+    const GemmArgs g = probs[p];
+    const int lt = t - tstart[p];
+    const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    const int mi = lt % tm, rest = lt / tm;
+    zgemm_tile<BM, BN, AK, BNF, G3>(g, mi * BM, (rest % tn) * BN, rest / tn);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Low-precision complex GEMM: operands and C are complex128 in memory, the
+// products run on FP32 MFMA (v_mfma_f32_16x16x4_f32) with FP32 accumulation,
+// three real products per complex block as in k_zgemm_p.  Used for the
+// ladder and ring products inside the inner solves of the mixed-precision
+// path; residuals are always re-formed with the FP64 kernels.
+// --------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// row of the 16x16 f32 MFMA output held by lane `lane` in register r
+__device__ __forceinline__ int f32_out_row(int lane, int r) { return F32_ROW(lane, r); }
+
+template <int BM, int BN, bool AK, bool BNF>
+__global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  __shared__ float sA[2][3][BK][BM + 1];
+  __shared__ float sB[2][3][BK][BN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const i64 bz = blockIdx.z;
+  int kbeg = 0, kend = g.K;
+  i64 bb = bz;  // batch index of the operands (the K chunk is folded into bz when splitting)
+  if (g.kchunk > 0) {
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
+  }
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const float sa = g.conjA ? -1.f : 1.f, sb = g.conjB ? -1.f : 1.f;
+  cplx ra[LA], rb[LB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[r] = (gm < g.M && gk < kend) ? A[(i64)gm * g.sAm + (i64)gk * g.sAk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      const int gn = n0 + nn, gk = k0 + kk;
+      rb[r] = (gn < g.N && gk < kend) ? B[(i64)gk * g.sBk + (i64)gn * g.sBn] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + r * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const float re = (float)ra[r].x, im = sa * (float)ra[r].y;
+      sA[buf][0][kk][mm] = re;
+      sA[buf][1][kk][mm] = im;
+      sA[buf][2][kk][mm] = (float)(ra[r].x + (double)sa * ra[r].y);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + r * 256;
+      const int nn = BNF ? e % BN : e / BK;
+      const int kk = BNF ? e / BN : e % BK;
+      const double re = rb[r].x, im = (double)sb * rb[r].y;
+      sB[buf][0][kk][nn] = (float)re;
+      sB[buf][1][kk][nn] = (float)(im - re);
+      sB[buf][2][kk][nn] = (float)(re + im);
+    }
+  };
+  f4 k1[FM][FN], k2[FM][FN], k3[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      k1[i][j] = f4{0, 0, 0, 0};
+      k2[i][j] = f4{0, 0, 0, 0};
+      k3[i][j] = f4{0, 0, 0, 0};
+    }
+  gload(kbeg);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      float ar[FM], ai[FM], as[FM], br[FN], bd[FN], bs[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int mm = wm + i * 16 + (lane & 15);
+        ar[i] = sA[buf][0][kk][mm];
+        ai[i] = sA[buf][1][kk][mm];
+        as[i] = sA[buf][2][kk][mm];
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int nn = wn + j * 16 + (lane & 15);
+        br[j] = sB[buf][0][kk][nn];
+        bd[j] = sB[buf][1][kk][nn];
+        bs[j] = sB[buf][2][kk][nn];
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          k1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[i], br[j], k1[i][j], 0, 0, 0);
+          k2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bd[j], k2[i][j], 0, 0, 0);
+          k3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], bs[j], k3[i][j], 0, 0, 0);
+        }
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + f32_out_row(lane, r);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double cr = (double)k1[i][j][r] - (double)k3[i][j][r];
+          const double ci = (double)k1[i][j][r] + (double)k2[i][j][r];
+          cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            const cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
+inline unsigned grid_for(i64 total) {
+  i64 g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+}  // namespace
+
+// FP64 GEMM variants: tile 128x64 or 64x64, three or four real products
+// (M-tiles per group of the tile order)
+constexpr int kGroupM = 8;
+template <int BM, int BN, bool G3>
+static void launch_p(const GemmArgs& g, bool grouped, hipStream_t s) {
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN, gm = grouped ? std::min(tm, kGroupM) : tm;
+  const int xcd = grouped ? 1 : 0;
+  const i64 total = (i64)tm * tn * g.batch;
+  REQUIRE(total >= 1 && total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
+  dim3 grid((unsigned)total);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, true, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_p<BM, BN, true, false, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, true, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, false, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+}
+
+void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  const bool grouped = variant > GEMM_64x64_G4;
+  switch (grouped ? variant - GEMM_64x64_G4 : variant) {
+    case GEMM_128x64_G3: launch_p<128, 64, true>(g, grouped, s); break;
+    case GEMM_64x64_G3: launch_p<64, 64, true>(g, grouped, s); break;
+    case GEMM_128x64_G4: launch_p<128, 64, false>(g, grouped, s); break;
+    case GEMM_64x64_G4: launch_p<64, 64, false>(g, grouped, s); break;
+    default: {
+      dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
+      hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
+    }
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <int BM, int BN, bool G3>
+static void launch_group(const GemmArgs* probs, const int* tstart, int nprob, int total, bool ak, bool bn,
+                         hipStream_t s) {
+  // persistent grid: as many workgroups as fit on the 256 CUs at once (LDS bound)
+  constexpr int NP = G3 ? 3 : 2;
+  constexpr int lds = 2 * NP * 16 * (BM + 1 + BN + 1) * 8;
+  const int per_cu = (160 * 1024) / lds;
+  const int grid = std::min(total, 256 * std::max(1, per_cu));
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_group<BM, BN, true, true, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_group<BM, BN, true, false, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_group<BM, BN, false, true, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+  else hipLaunchKernelGGL((k_zgemm_group<BM, BN, false, false, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
+}
+
+int gemm_tile_rows(int variant) { return (variant == GEMM_128x64_G3 || variant == GEMM_128x64_G4) ? 128 : 64; }
+
+void launch_zgemm_group(const GemmArgs* probs, const int* tstart, int nprob, int total, int variant, bool ak, bool bn,
+                        hipStream_t s) {
+  if (total <= 0) return;
+  switch (variant) {
+    case GEMM_128x64_G3: launch_group<128, 64, true>(probs, tstart, nprob, total, ak, bn, s); break;
+    case GEMM_64x64_G3: launch_group<64, 64, true>(probs, tstart, nprob, total, ak, bn, s); break;
+    case GEMM_128x64_G4: launch_group<128, 64, false>(probs, tstart, nprob, total, ak, bn, s); break;
+    default: launch_group<64, 64, false>(probs, tstart, nprob, total, ak, bn, s); break;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+int gemm_default_variant(const GemmArgs& g) {
+  return (i64)g.M * g.N * g.batch >= (i64)128 * 64 * 1024 ? GEMM_128x64_G4 : GEMM_64x64_G4;
+}
+
+void launch_zgemm(const GemmArgs& g, hipStream_t s) { launch_zgemm_variant(g, gemm_default_variant(g), s); }
+
+void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  REQUIRE(prec == CCLR_FP32, CCLR_EINVAL, "low-precision GEMM: only CCLR_FP32 is available");
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  dim3 grid((g.M + 127) / 128, (g.N + 63) / 64, g.batch);
+  if (ak && bn) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, true>), grid, dim3(256), 0, s, g);
+  else if (ak) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, false>), grid, dim3(256), 0, s, g);
+  else if (bn) hipLaunchKernelGGL((k_cgemm_f32<128, 64, false, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_cgemm_f32<128, 64, false, false>), grid, dim3(256), 0, s, g);
+  HIPCHK(hipGetLastError());
+}
+
+bool launch_zgemm_smallk(const GemmArgs& g0, hipStream_t s) {
+  if (g0.K > SK_MAX || g0.kchunk > 0 || g0.M <= 0 || g0.N <= 0 || g0.batch <= 0 || g0.K <= 0) return false;
+  GemmArgs g = g0;
+  // run the threads along the unit-stride index of C (transpose the product if that is m)
+  if (g0.sCn != 1 && g0.sCm == 1) {
+    g.M = g0.N; g.N = g0.M;
+    g.A = g0.B; g.sAb = g0.sBb; g.sAb2 = g0.sBb2; g.sAm = g0.sBn; g.sAk = g0.sBk; g.conjA = g0.conjB;
+    g.B = g0.A; g.sBb = g0.sAb; g.sBb2 = g0.sAb2; g.sBk = g0.sAk; g.sBn = g0.sAm; g.conjB = g0.conjA;
+    g.sCm = g0.sCn; g.sCn = g0.sCm;
+  }
+  if (g.batch >= 65536 || (g.M + SK_MB - 1) / SK_MB >= 65536) return false;
+  dim3 grid((g.N + 255) / 256, (g.M + SK_MB - 1) / SK_MB, g.batch);
+  hipLaunchKernelGGL(k_zgemm_smallk, grid, dim3(256), 0, s, g);
+  HIPCHK(hipGetLastError());
+  return true;
+}
+
+void launch_zgemm_simple(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
+  hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i64 sCb, i64 sCm, i64 sCn, double ar,
+                          double ai, int beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((i64)M * N * nb)), dim3(256), 0, s, nb, S, M, N, W, C, sCb, sCm,
+                     sCn, ar, ai, beta);
+  HIPCHK(hipGetLastError());
+}
