@@ -290,6 +290,53 @@ def ground_bench(cc, dev, o, v, seed, tol=1e-8, nchol_per_orbital=3, v_std=0.002
     return out
 
 
+# The paper's sigma-vector benchmark (SI, "CPU vs GPU benchmarks", table of
+# sigma-vector timings): wall seconds of one sigma evaluation on one
+# Xeon Gold 6240 core and on one V100-PCIe, per (O, V).  Context only.
+PAPER_SIGMA_S = {(10, 102): (6, 1), (10, 130): (13, 2), (10, 160): (26, 5), (10, 200): (58, 10),
+                 (20, 102): (20, 2), (20, 130): (43, 4), (20, 160): (85, 8), (20, 200): (183, 16),
+                 (30, 102): (48, 5), (30, 130): (103, 8), (30, 160): (203, 14), (30, 200): (429, 25),
+                 (40, 102): (96, 8), (40, 130): (203, 13), (40, 160): (395, 21), (40, 200): (821, 37)}
+
+
+def sweep_bench(cc, dev, seed=3, reps=3):
+    """One right transform of one vector (FP64) at each of the paper's sigma
+    benchmark shapes: median of reps timed calls after a warm-up call."""
+    import statistics
+    import torch
+    from gen import synth as s
+    rows = []
+    for (o, v), (cpu_s, gpu_s) in PAPER_SIGMA_S.items():
+        pb, f, V, t1, t2, X = make_inputs(o, v, seed, dev)
+        ctx = cc.cclr_create(o, v, cc.cclr_default_options())
+        try:
+            cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+            del V
+            torch.cuda.empty_cache()
+            cc.cclr_set_amplitudes(ctx, t1, t2)
+            a, b = s.excitation_vector(pb, 0, dev)
+            r1, r2 = a[None].contiguous(), b[None].contiguous()
+            s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
+            cc.cclr_jacobian_right(ctx, [0.0774], [0.005], r1, r2, s1, s2)
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                cc.cclr_jacobian_right(ctx, [0.0774], [0.005], r1, r2, s1, s2)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = statistics.median(ts)
+            fl = sigma_flops(o, v)["total"]
+            rows.append({"O": o, "V": v, "ms": round(1e3 * t, 3), "tflops": round(fl / t / 1e12, 2),
+                         "paper_v100_s": gpu_s, "paper_cpu_1core_s": cpu_s, "ratio_vs_paper_gpu": round(gpu_s / t, 1)})
+            log(f"sweep O={o} V={v}: {1e3 * t:.2f} ms ({fl / t / 1e12:.1f} TFLOP/s)")
+        finally:
+            cc.cclr_destroy(ctx)
+            del f, t1, t2, X
+            torch.cuda.empty_cache()
+    return rows
+
+
 def batching_bench(cc, dev, nvec=3, reps=3):
     """Four problems of uneven size, (o, v) = (8, 60), (12, 90), (16, 120),
     (20, 150), nvec right transforms each: one cclr_jacobian_right_multi call
@@ -385,7 +432,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--omega", type=float, default=0.0774)
     ap.add_argument("--gamma", type=float, default=0.005)
-    ap.add_argument("--mode", choices=["response", "sigma"], default="response")
+    ap.add_argument("--mode", choices=["response", "sigma", "sweep"], default="response",
+                    help="response: the whole job (default); sigma: transforms of --nvec vectors; sweep: one "
+                         "transform at each of the paper's sigma-benchmark shapes")
     ap.add_argument("--nvec", type=int, default=12, help="vectors per transform call in --mode sigma")
     ap.add_argument("--max-subspace", type=int, default=24)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -494,6 +543,17 @@ def main():
         res.update({"transforms": ntr, "dt": dt, "nl": nl.value, "ms": ms.value, "fl": fl.value})
         return res
 
+    if args.mode == "sweep":
+        rows = sweep_bench(cc, dev)
+        tot_ms = sum(r["ms"] for r in rows)
+        print(json.dumps({"metric": "Jacobian transforms/s (one vector, the paper's sigma-benchmark shapes)",
+                          "value": len(rows) / (tot_ms * 1e-3), "unit": "Jacobian transforms/s", "n_gpus": 1,
+                          "steps": len(rows), "warmup": 1, "ms_per_step": tot_ms / len(rows),
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128 (f64)",
+                          "data": "synthetic (seeded generators)",
+                          "config": {"workload": "sigma-benchmark sweep O in {10,20,30,40} x V in {102,130,160,200}",
+                                     "rows": rows}}), flush=True)
+        return
     if args.copy_probe_gib > 0:
         nel = int(args.copy_probe_gib * (1 << 30) / 16)
         a = torch.ones(nel, dtype=torch.complex128, device=dev)
