@@ -303,6 +303,7 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
       double score = -1;
     } best;
     const int nm = (int)Lm.size(), nn = (int)Ln.size();
+    const bool kshort = merge(A, la, Lk).size <= 32;
     for (int ca = 0; ca < 2; ++ca)
       for (int cbq = 0; cbq < 2; ++cbq) {
         if ((ca && A.size() > small) || (cbq && B.size() > small)) continue;
@@ -319,7 +320,13 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
             if (mm == 0 && mn == 0 && !ca && !cbq) continue;  // the plain plan below handles it
             const i64 nbat = merge(C, lc, sm).size * merge(C, lc, sn).size;
             if (nbat >= 65536) continue;
-            const double score = (double)merge(C, lc, rm).size * (double)merge(C, lc, rn).size;
+            double score = (double)merge(C, lc, rm).size * (double)merge(C, lc, rn).size;
+            // a short reduction runs on the vector ALU and is bound by its output
+            // traffic: prefer plans whose output has a unit-stride M or N index
+            if (kshort) {
+              const Group gm = merge(C, lc, rm), gn = merge(C, lc, rn);
+              if ((gm.size > 1 && gm.stride == 1) || (gn.size > 1 && gn.stride == 1)) score *= 64.0;
+            }
             const bool fewer = (ca + cbq) < (int)best.ca + (int)best.cb;
             if (best.score < 0 || fewer || score > best.score) best = Plan{sm, rm, sn, rn, ca != 0, cbq != 0, score};
           }
