@@ -22,7 +22,8 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
 /* C[b] (+)= alpha * op(A[b]) op(B[b]) for b < batch with one FP64 kernel
  * variant (0: simple; 1..4: MFMA tiles 128x64 / 64x64 with three or four
  * real products per complex block; 4 + k: variant k in the XCD-grouped tile
- * order).  All pointers are device memory; strides in elements.  For tests
+ * order; 9, 10 and 11, 12: 64x64 and 128x64 four-product tiles with one LDS
+ * buffer, plain and grouped order).  All pointers are device memory; strides in elements.  For tests
  * of every variant (the autotuner otherwise runs only the fastest). */
 int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c64* A, long long sAb, long long sAm,
                        long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
@@ -68,8 +69,8 @@ int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
 
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
  * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
- * the variant in use, which within 2% of the fastest prefers the grouped
- * tile order).
+ * the variant in use: within 2% of the fastest, the grouped tile order, then
+ * 128-row tiles, are preferred).
  * enable >= 0 switches tuning on (1) or off (0) for later products. */
 int cclr_dbg_tuning(cclr_ctx* ctx, int enable, char* buf, long long cap);
 

@@ -532,7 +532,10 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
 // on at most kTuneRows rows and kTuneBatch batch entries and classed by
 // octave; N and K are classed by quarter octave.
 constexpr int kTuneRows = 8192, kTuneBatch = 16;
-bool gemm_variant_grouped(int variant) { return variant > GEMM_64x64_G4 && variant < GEMM_NVAR; }
+bool gemm_variant_grouped(int variant) {
+  return (variant > GEMM_64x64_G4 && variant <= 2 * GEMM_64x64_G4) || variant == GEMM_64x64_G4_SB_GROUPED ||
+         variant == GEMM_128x64_G4_SB_GROUPED;
+}
 int octave_bucket(int x) {
   int p = 1;
   while (p < x) p *= 2;
@@ -592,13 +595,22 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  // within the timing noise (2%) of the fastest, prefer the XCD-grouped tile
-  // order: it re-reads the operands from HBM far less for the same time
-  if (!gemm_variant_grouped(best)) {
-    int grp = -1;
-    for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v)
-      if (gemm_variant_grouped(v) && ms[v] <= 1.02 * tbest && (grp < 0 || ms[v] < ms[grp])) grp = v;
-    if (grp >= 0) best = grp;
+  // within the timing noise (2%) of the fastest, prefer the variant that
+  // re-reads its operands from HBM least for the same time: the XCD-grouped
+  // tile order first, then 128-row tiles, then the faster one
+  {
+    auto rereads = [](int v) {
+      const int base = gemm_variant_grouped(v) && v <= 2 * GEMM_64x64_G4 ? v - GEMM_64x64_G4 : v;
+      const bool rows128 = base == GEMM_128x64_G3 || base == GEMM_128x64_G4 || v == GEMM_128x64_G4_SB ||
+                           v == GEMM_128x64_G4_SB_GROUPED;
+      return (gemm_variant_grouped(v) ? 0 : 2) + (rows128 ? 0 : 1);
+    };
+    int pick = best;
+    for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) {
+      if (ms[v] > 1.02 * tbest) continue;
+      if (rereads(v) < rereads(pick) || (rereads(v) == rereads(pick) && ms[v] < ms[pick])) pick = v;
+    }
+    best = pick;
   }
   c->arena.reset(mk);
   c->gemm_choice[key] = best;

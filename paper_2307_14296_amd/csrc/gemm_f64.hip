@@ -219,15 +219,20 @@ __global__ __launch_bounds__(256) void k_zgemm_smallk(GemmArgs g) {
 // barrier.  Four waves in a 2x2 arrangement, each owning a (BM/2)x(BN/2)
 // sub-tile.
 // --------------------------------------------------------------------------
-template <int BM, int BN, bool AK, bool BNF, bool G3>
+template <int BM, int BN, bool AK, bool BNF, bool G3, bool SB = false>
 __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, const int n0, const i64 bz) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-  constexpr int NP = G3 ? 3 : 2;
-  __shared__ double sA[2][NP][BK][BM + 1];  // Ar, Ai (, Ar + Ai)
-  __shared__ double sB[2][NP][BK][BN + 1];  // Br, Bi - Br (, Br + Bi)  |  Br, Bi
+  // three products: planes Ar, Ai, Ar + Ai and Br, Bi - Br, Br + Bi; four
+  // products: interleaved (re, im) pairs, read as one 16-byte LDS access
+  constexpr int NP = G3 ? 3 : 1;
+  constexpr int EW = G3 ? 1 : 2;  // doubles per LDS element
+  // SB: one LDS buffer (two barriers per K-tile) for a smaller footprint and more resident workgroups
+  constexpr int NB = SB ? 1 : 2;
+  __shared__ double sA[NB][NP][BK][(BM + 1) * EW];
+  __shared__ double sB[NB][NP][BK][(BN + 1) * EW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int kbeg = 0, kend = g.K;
   i64 bb = bz;  // batch index of the operands (the K chunk is folded into bz when splitting)
@@ -268,9 +273,13 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
       const int mm = AK ? e / BK : e % BM;
       const int kk = AK ? e % BK : e / BM;
       const double re = ra[r].x, im = sa * ra[r].y;
-      sA[buf][0][kk][mm] = re;
-      sA[buf][1][kk][mm] = im;
-      if (G3) sA[buf][2][kk][mm] = re + im;
+      if (G3) {
+        sA[buf][0][kk][mm] = re;
+        sA[buf][G3 ? 1 : 0][kk][mm] = im;
+        sA[buf][G3 ? 2 : 0][kk][mm] = re + im;
+      } else {
+        *(double2*)&sA[buf][0][kk][2 * mm] = make_double2(re, im);
+      }
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
@@ -278,9 +287,13 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
       const int nn = BNF ? e % BN : e / BK;
       const int kk = BNF ? e / BN : e % BK;
       const double re = rb[r].x, im = sb * rb[r].y;
-      sB[buf][0][kk][nn] = re;
-      sB[buf][1][kk][nn] = G3 ? im - re : im;
-      if (G3) sB[buf][2][kk][nn] = re + im;
+      if (G3) {
+        sB[buf][0][kk][nn] = re;
+        sB[buf][G3 ? 1 : 0][kk][nn] = im - re;
+        sB[buf][G3 ? 2 : 0][kk][nn] = re + im;
+      } else {
+        *(double2*)&sB[buf][0][kk][2 * nn] = make_double2(re, im);
+      }
     }
   };
 
@@ -301,23 +314,33 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) gload(k0 + BK);
-#pragma unroll
+#pragma unroll(SB ? 2 : 4)
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + (lane >> 4);
       double ar[FM], ai[FM], as[FM], br[FN], bd[FN], bs[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         const int mm = wm + i * 16 + (lane & 15);
-        ar[i] = sA[buf][0][kk][mm];
-        ai[i] = sA[buf][1][kk][mm];
-        as[i] = G3 ? sA[buf][NP - 1][kk][mm] : 0.0;
+        if (G3) {
+          ar[i] = sA[buf][0][kk][mm];
+          ai[i] = sA[buf][G3 ? 1 : 0][kk][mm];
+          as[i] = sA[buf][G3 ? 2 : 0][kk][mm];
+        } else {
+          const double2 x = *(const double2*)&sA[buf][0][kk][2 * mm];
+          ar[i] = x.x, ai[i] = x.y, as[i] = 0.0;
+        }
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int nn = wn + j * 16 + (lane & 15);
-        br[j] = sB[buf][0][kk][nn];
-        bd[j] = sB[buf][1][kk][nn];
-        bs[j] = G3 ? sB[buf][NP - 1][kk][nn] : 0.0;
+        if (G3) {
+          br[j] = sB[buf][0][kk][nn];
+          bd[j] = sB[buf][G3 ? 1 : 0][kk][nn];
+          bs[j] = sB[buf][G3 ? 2 : 0][kk][nn];
+        } else {
+          const double2 x = *(const double2*)&sB[buf][0][kk][2 * nn];
+          br[j] = x.x, bd[j] = x.y, bs[j] = 0.0;
+        }
       }
       if (G3) {
 #pragma unroll
@@ -347,9 +370,17 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
           }
       }
     }
-    if (more) sstore(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+    if (SB) {
+      if (more) {
+        __syncthreads();  // every wave is done reading the buffer
+        sstore(0);
+        __syncthreads();
+      }
+    } else {
+      if (more) sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
   cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
 #pragma unroll
@@ -401,6 +432,15 @@ __global__ __launch_bounds__(256) void k_zgemm_p(GemmArgs g, int tm, int tn, int
   int mi, ni, bz;
   tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
   zgemm_tile<BM, BN, AK, BNF, G3>(g, mi * BM, ni * BN, bz);
+}
+
+// single-buffered LDS, registers capped for three (64-row tiles) or two
+// (128-row tiles) waves per SIMD
+template <int BM, int BN, bool AK, bool BNF, bool G3>
+__global__ __launch_bounds__(256, BM == 64 ? 3 : 2) void k_zgemm_p1(GemmArgs g, int tm, int tn, int gm, int xcd) {
+  int mi, ni, bz;
+  tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
+  zgemm_tile<BM, BN, AK, BNF, G3, true>(g, mi * BM, ni * BN, bz);
 }
 
 // Grouped persistent form: one launch walks the tiles of several products
@@ -593,8 +633,32 @@ static void launch_p(const GemmArgs& g, bool grouped, hipStream_t s) {
   else hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, false, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
 }
 
+template <int BM>
+static void launch_p1(const GemmArgs& g, bool grouped, hipStream_t s) {
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + 63) / 64, gm = grouped ? std::min(tm, kGroupM) : tm;
+  const int xcd = grouped ? 1 : 0;
+  const i64 total = (i64)tm * tn * g.batch;
+  REQUIRE(total >= 1 && total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
+  dim3 grid((unsigned)total);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_p1<BM, 64, true, true, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_p1<BM, 64, true, false, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_p1<BM, 64, false, true, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else hipLaunchKernelGGL((k_zgemm_p1<BM, 64, false, false, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+}
+
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  if (variant == GEMM_64x64_G4_SB || variant == GEMM_64x64_G4_SB_GROUPED) {
+    launch_p1<64>(g, variant == GEMM_64x64_G4_SB_GROUPED, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  if (variant == GEMM_128x64_G4_SB || variant == GEMM_128x64_G4_SB_GROUPED) {
+    launch_p1<128>(g, variant == GEMM_128x64_G4_SB_GROUPED, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   const bool grouped = variant > GEMM_64x64_G4;
   switch (grouped ? variant - GEMM_64x64_G4 : variant) {
     case GEMM_128x64_G3: launch_p<128, 64, true>(g, grouped, s); break;

@@ -112,8 +112,15 @@ struct GemmArgs {
 };
 void launch_zgemm(const GemmArgs& g, hipStream_t s);
 // FP64 kernel variants (tile shape, three or four real products per complex
-// block); variants 4 + k run variant k (k = 1..4) in the XCD-grouped tile order
-enum { GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4, GEMM_NVAR = 9 };
+// block); variants 4 + k run variant k (k = 1..4) in the XCD-grouped tile
+// order; 9, 10: the 64x64 four-product tile with one LDS buffer (three
+// waves per SIMD), plain and grouped order; 11, 12: the same for 128x64
+// tiles (two waves per SIMD)
+enum {
+  GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4,
+  GEMM_64x64_G4_SB = 9, GEMM_64x64_G4_SB_GROUPED = 10, GEMM_128x64_G4_SB = 11, GEMM_128x64_G4_SB_GROUPED = 12,
+  GEMM_NVAR = 13
+};
 bool gemm_variant_grouped(int variant);
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);
 int gemm_default_variant(const GemmArgs& g);

@@ -89,7 +89,7 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
     B = crand(rng, batch, K, N)
     C0 = crand(rng, batch, M, N)
     alpha = 0.3 + 1.1j
-    for variant in range(9):
+    for variant in range(13):
         for ta, tb, beta in [(False, False, 0), (True, True, 1), (False, True, 1), (True, False, 0)]:
             Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
             Bd = dev(B.transpose(0, 2, 1).copy() if tb else B)
