@@ -534,7 +534,7 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
 constexpr int kTuneRows = 8192, kTuneBatch = 16;
 bool gemm_variant_grouped(int variant) {
   return (variant > GEMM_64x64_G4 && variant <= 2 * GEMM_64x64_G4) || variant == GEMM_64x64_G4_SB_GROUPED ||
-         variant == GEMM_128x64_G4_SB_GROUPED;
+         variant == GEMM_128x64_G4_SB_GROUPED || variant == GEMM_128x128_G4_GROUPED;
 }
 int octave_bucket(int x) {
   int p = 1;
@@ -597,13 +597,15 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   (void)hipEventDestroy(e1);
   // within the timing noise (2%) of the fastest, prefer the variant that
   // re-reads its operands from HBM least for the same time: the XCD-grouped
-  // tile order first, then 128-row tiles, then the faster one
+  // tile order first, then larger tiles (128x128, 128x64, 64x64), then the
+  // faster one
   {
     auto rereads = [](int v) {
       const int base = gemm_variant_grouped(v) && v <= 2 * GEMM_64x64_G4 ? v - GEMM_64x64_G4 : v;
       const bool rows128 = base == GEMM_128x64_G3 || base == GEMM_128x64_G4 || v == GEMM_128x64_G4_SB ||
-                           v == GEMM_128x64_G4_SB_GROUPED;
-      return (gemm_variant_grouped(v) ? 0 : 2) + (rows128 ? 0 : 1);
+                           v == GEMM_128x64_G4_SB_GROUPED || v >= GEMM_128x128_G4;
+      const bool cols128 = v >= GEMM_128x128_G4;
+      return (gemm_variant_grouped(v) ? 0 : 3) + (rows128 ? 0 : 1) + (cols128 ? 0 : 1);
     };
     int pick = best;
     for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) {

@@ -3,6 +3,9 @@
 #include "internal.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+// last operand of the FP64 MFMA builtin: on CDNA3/CDNA4 its bits are the
+// DGEMM negate modifiers of the A, B and C operands; 1 negates A
+constexpr int kNegA = 1;
 // output row of v_mfma_f32_16x16x4_f32 for (lane, register)
 #define F32_ROW(lane, r) (4 * ((lane) >> 4) + (r))
 
@@ -19,6 +22,12 @@ namespace {
 constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 1;
 
 // element offset of batch bz (one or two batch indices)
+// complex value with the sign bit of its imaginary part xor-ed with sgn
+// (0 or 0x80000000): the conjugate, or the value itself, without arithmetic
+__device__ __forceinline__ cplx flip_im(cplx v, unsigned sgn) {
+  v.y = __hiloint2double(__double2hiint(v.y) ^ (int)sgn, __double2loint(v.y));
+  return v;
+}
 __device__ __forceinline__ i64 boff(const GemmArgs& g, i64 bz, i64 s1, i64 s2) {
   if (g.nb2 <= 1) return bz * s1;
   return (bz / g.nb2) * s1 + (bz % g.nb2) * s2;
@@ -246,53 +255,53 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
   const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
   const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
   const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+  const unsigned sgnA = g.conjA ? 0x80000000u : 0u, sgnB = g.conjB ? 0x80000000u : 0u;
+  const i64 sAk = AK ? 1 : g.sAk, sBn = BNF ? 1 : g.sBn;
+  // element r of this thread's share of a K-tile: A row mA + r*dmA, column kA + r*dkA (and alike for B)
+  const int mA = AK ? tid / BK : tid % BM, kA = AK ? tid % BK : tid / BM;
+  const int dmA = AK ? 256 / BK : 0, dkA = AK ? 0 : 256 / BM;
+  const int nB = BNF ? tid % BN : tid / BK, kB = BNF ? tid / BN : tid % BK;
+  const int dnB = BNF ? 0 : 256 / BK, dkB = BNF ? 256 / BN : 0;
+  const cplx* __restrict__ pA = A + (i64)(m0 + mA) * g.sAm + (i64)kA * sAk;
+  const cplx* __restrict__ pB = B + (i64)kB * g.sBk + (i64)(n0 + nB) * sBn;
+  const i64 stA = (i64)dmA * g.sAm + (i64)dkA * sAk, stB = (i64)dkB * g.sBk + (i64)dnB * sBn;
 
   cplx ra[LA], rb[LB];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
-      const int e = tid + r * 256;
-      const int mm = AK ? e / BK : e % BM;
-      const int kk = AK ? e % BK : e / BM;
-      const int gm = m0 + mm, gk = k0 + kk;
-      ra[r] = (gm < g.M && gk < kend) ? A[(i64)gm * g.sAm + (i64)gk * g.sAk] : make_double2(0.0, 0.0);
+      const int gm = m0 + mA + r * dmA, gk = k0 + kA + r * dkA;
+      ra[r] = (gm < g.M && gk < kend) ? pA[r * stA + (i64)k0 * sAk] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
-      const int e = tid + r * 256;
-      const int nn = BNF ? e % BN : e / BK;
-      const int kk = BNF ? e / BN : e % BK;
-      const int gn = n0 + nn, gk = k0 + kk;
-      rb[r] = (gn < g.N && gk < kend) ? B[(i64)gk * g.sBk + (i64)gn * g.sBn] : make_double2(0.0, 0.0);
+      const int gn = n0 + nB + r * dnB, gk = k0 + kB + r * dkB;
+      rb[r] = (gn < g.N && gk < kend) ? pB[r * stB + (i64)k0 * g.sBk] : make_double2(0.0, 0.0);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
-      const int e = tid + r * 256;
-      const int mm = AK ? e / BK : e % BM;
-      const int kk = AK ? e % BK : e / BM;
+      const int mm = mA + r * dmA, kk = kA + r * dkA;
       const double re = ra[r].x, im = sa * ra[r].y;
       if (G3) {
         sA[buf][0][kk][mm] = re;
         sA[buf][G3 ? 1 : 0][kk][mm] = im;
         sA[buf][G3 ? 2 : 0][kk][mm] = re + im;
       } else {
-        *(double2*)&sA[buf][0][kk][2 * mm] = make_double2(re, im);
+        *(double2*)&sA[buf][0][kk][2 * mm] = flip_im(ra[r], sgnA);
       }
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
-      const int e = tid + r * 256;
-      const int nn = BNF ? e % BN : e / BK;
-      const int kk = BNF ? e / BN : e % BK;
+      const int nn = nB + r * dnB, kk = kB + r * dkB;
       const double re = rb[r].x, im = sb * rb[r].y;
       if (G3) {
         sB[buf][0][kk][nn] = re;
         sB[buf][G3 ? 1 : 0][kk][nn] = im - re;
         sB[buf][G3 ? 2 : 0][kk][nn] = re + im;
       } else {
-        *(double2*)&sB[buf][0][kk][2 * nn] = make_double2(re, im);
+        *(double2*)&sB[buf][0][kk][2 * nn] = flip_im(rb[r], sgnB);
       }
     }
   };
@@ -365,7 +374,7 @@ __device__ __forceinline__ void zgemm_tile(const GemmArgs& g, const int m0, cons
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
-            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bd[j], k1[i][j], 0, 0, 0);
+            k1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bd[j], k1[i][j], 0, 0, kNegA);
             k2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], k2[i][j], 0, 0, 0);
           }
       }
@@ -441,6 +450,145 @@ __global__ __launch_bounds__(256, BM == 64 ? 3 : 2) void k_zgemm_p1(GemmArgs g, 
   int mi, ni, bz;
   tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
   zgemm_tile<BM, BN, AK, BNF, G3, true>(g, mi * BM, ni * BN, bz);
+}
+
+// --------------------------------------------------------------------------
+// Large-tile form: 128x128 tiles, four real products, double-buffered LDS
+// (132 KB, so one workgroup per CU) and eight waves (two per SIMD), each
+// owning a 64x32 complex sub-tile.  One barrier per K-tile; the operand
+// fragments of the next 4-deep K step are read from LDS while the MFMAs of
+// the current one run, and the next K-tile is fetched into registers during
+// the whole tile.
+// --------------------------------------------------------------------------
+template <bool AK, bool BNF>
+__device__ __forceinline__ void zgemm_tile_w1(const GemmArgs& g, const int m0, const int n0, const i64 bz) {
+  constexpr int BM = 128, BN = 128, BK = 16;
+  constexpr int NT = 512, WM = 64, WN = 32, FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+  __shared__ double sA[2][BK][(BM + 1) * 2];
+  __shared__ double sB[2][BK][(BN + 1) * 2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int kbeg = 0, kend = g.K;
+  i64 bb = bz;
+  if (g.kchunk > 0) {
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
+  }
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const unsigned sgnA = g.conjA ? 0x80000000u : 0u, sgnB = g.conjB ? 0x80000000u : 0u;
+  const i64 sAk = AK ? 1 : g.sAk, sBn = BNF ? 1 : g.sBn;
+  // element r of this thread's share of a K-tile: A row mA + r*dmA, column kA + r*dkA (and alike for B)
+  const int mA = AK ? tid / BK : tid % BM, kA = AK ? tid % BK : tid / BM;
+  const int dmA = AK ? NT / BK : 0, dkA = AK ? 0 : NT / BM;
+  const int nB = BNF ? tid % BN : tid / BK, kB = BNF ? tid / BN : tid % BK;
+  const int dnB = BNF ? 0 : NT / BK, dkB = BNF ? NT / BN : 0;
+  const cplx* __restrict__ pA = A + (i64)(m0 + mA) * g.sAm + (i64)kA * sAk;
+  const cplx* __restrict__ pB = B + (i64)kB * g.sBk + (i64)(n0 + nB) * sBn;
+  const i64 stA = (i64)dmA * g.sAm + (i64)dkA * sAk, stB = (i64)dkB * g.sBk + (i64)dnB * sBn;
+
+  cplx ra[LA], rb[LB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int gm = m0 + mA + r * dmA, gk = k0 + kA + r * dkA;
+      ra[r] = (gm < g.M && gk < kend) ? pA[r * stA + (i64)k0 * sAk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int gn = n0 + nB + r * dnB, gk = k0 + kB + r * dkB;
+      rb[r] = (gn < g.N && gk < kend) ? pB[r * stB + (i64)k0 * g.sBk] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r)
+      *(double2*)&sA[buf][kA + r * dkA][2 * (mA + r * dmA)] = flip_im(ra[r], sgnA);
+#pragma unroll
+    for (int r = 0; r < LB; ++r)
+      *(double2*)&sB[buf][kB + r * dkB][2 * (nB + r * dnB)] = flip_im(rb[r], sgnB);
+  };
+  double2 fa[2][FM], fb[2][FN];
+  auto fread = [&](int buf, int ks, int s) {
+    const int kk = ks + (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < FM; ++i) fa[s][i] = *(const double2*)&sA[buf][kk][2 * (wm + i * 16 + (lane & 15))];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) fb[s][j] = *(const double2*)&sB[buf][kk][2 * (wn + j * 16 + (lane & 15))];
+  };
+
+  d4 cr[FM][FN], ci[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      cr[i][j] = d4{0, 0, 0, 0};
+      ci[i][j] = d4{0, 0, 0, 0};
+    }
+
+  gload(kbeg);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  fread(0, 0, 0);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK);
+#pragma unroll
+    for (int q = 0; q < BK / 4; ++q) {
+      const int s = q & 1;
+      if (q + 1 < BK / 4) fread(buf, 4 * (q + 1), s ^ 1);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].x, fb[s][j].x, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].x, fb[s][j].y, ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].y, fb[s][j].y, cr[i][j], 0, 0, kNegA);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].y, fb[s][j].x, ci[i][j], 0, 0, 0);
+        }
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    if (more) fread(buf, 0, 0);
+  }
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double xr = cr[i][j][r], xi = ci[i][j][r];
+          cplx y = make_double2(g.ar * xr - g.ai * xi, g.ar * xi + g.ai * xr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            const cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
+template <bool AK, bool BNF>
+__global__ __launch_bounds__(512, 2) void k_zgemm_w1(GemmArgs g, int tm, int tn, int gm, int xcd) {
+  int mi, ni, bz;
+  tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
+  zgemm_tile_w1<AK, BNF>(g, mi * 128, ni * 128, bz);
 }
 
 // Grouped persistent form: one launch walks the tiles of several products
@@ -647,8 +795,26 @@ static void launch_p1(const GemmArgs& g, bool grouped, hipStream_t s) {
   else hipLaunchKernelGGL((k_zgemm_p1<BM, 64, false, false, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
 }
 
+static void launch_w1(const GemmArgs& g, bool grouped, hipStream_t s) {
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128, gm = grouped ? std::min(tm, kGroupM) : tm;
+  const int xcd = grouped ? 1 : 0;
+  const i64 total = (i64)tm * tn * g.batch;
+  REQUIRE(total >= 1 && total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
+  dim3 grid((unsigned)total);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_w1<true, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_w1<true, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_w1<false, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else hipLaunchKernelGGL((k_zgemm_w1<false, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+}
+
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  if (variant == GEMM_128x128_G4 || variant == GEMM_128x128_G4_GROUPED) {
+    launch_w1(g, variant == GEMM_128x128_G4_GROUPED, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   if (variant == GEMM_64x64_G4_SB || variant == GEMM_64x64_G4_SB_GROUPED) {
     launch_p1<64>(g, variant == GEMM_64x64_G4_SB_GROUPED, s);
     HIPCHK(hipGetLastError());

@@ -72,7 +72,7 @@ def test_zgemm(gpu, M, N, K, ta, tb):
 
 
 VARIANT_CASES = [(1, 1, 1, 1), (130, 70, 33, 3), (300, 200, 50, 1), (257, 1, 64, 2), (64, 640, 17, 5),
-                 (1100, 65, 40, 1)]
+                 (1100, 65, 40, 1), (260, 300, 70, 2)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", VARIANT_CASES)
@@ -89,7 +89,7 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
     B = crand(rng, batch, K, N)
     C0 = crand(rng, batch, M, N)
     alpha = 0.3 + 1.1j
-    for variant in range(13):
+    for variant in range(15):
         for ta, tb, beta in [(False, False, 0), (True, True, 1), (False, True, 1), (True, False, 0)]:
             Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
             Bd = dev(B.transpose(0, 2, 1).copy() if tb else B)
