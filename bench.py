@@ -418,6 +418,15 @@ def ladder_traffic(variant):
     return float(vals[key])
 
 
+def gemm_kernel_name(variant):
+    """HIP kernel behind an FP64 GEMM variant number of the autotuner."""
+    if variant is None:
+        return "FP64 GEMM"
+    if variant >= 13:
+        return "k_zgemm_w1"
+    return "k_zgemm_p1" if variant >= 9 else "k_zgemm_p"
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -582,7 +591,7 @@ def main():
     chosen = int(variant[0].rsplit("->", 1)[1]) if variant else None
     roofline = {
         "bound": "mfma",
-        "kernel": "k_zgemm_p (packed particle-particle ladder, FP64 MFMA), largest launches" +
+        "kernel": f"{gemm_kernel_name(chosen)} (packed particle-particle ladder, FP64 MFMA), largest launches" +
                   (f"; autotuner: {variant[0]}" if variant else ""),
         "achieved": round(achieved, 3),
         "peak": PEAK_FP64_TFLOPS,

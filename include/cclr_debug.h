@@ -30,6 +30,13 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
                        int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,
                        int beta);
 
+/* Several independent products C[p] = A[p] B[p] (A[p] row-major M[p] x K[p];
+ * B[p] row-major K[p] x N[p], or N[p] x K[p] when btrans; C[p] row-major
+ * M[p] x N[p]; all device pointers) in the one persistent grouped launch of
+ * FP64 variant 1, 2, 3, 4 or 13 (the tile shapes that have a grouped form). */
+int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N, const int* K,
+                             const cclr_c64* const* A, const cclr_c64* const* B, int btrans, cclr_c64* const* C);
+
 /* The same product (batch 1) in reduced arithmetic: prec = CCLR_FP32 (FP32
  * MFMA) or CCLR_BF16X3 (split-BF16 MFMA, three bf16 products per real
  * product, FP32 accumulation); operands and C stay complex128. */

@@ -321,9 +321,9 @@ void grouped_products(cclr_ctx* c0, std::vector<GemmArgs> g) {
   HIPCHK(hipMemcpyAsync(pd, g.data(), sizeof(GemmArgs) * g.size(), hipMemcpyHostToDevice, c0->stream));
   auto launch = [&](int variant) {
     std::vector<int> ts(g.size() + 1, 0);
-    const int bm = gemm_tile_rows(variant);
+    const int bm = gemm_tile_rows(variant), bn_ = gemm_tile_cols(variant);
     for (size_t p = 0; p < g.size(); ++p) {
-      const i64 tiles = (i64)((g[p].M + bm - 1) / bm) * ((g[p].N + 63) / 64) * g[p].batch;
+      const i64 tiles = (i64)((g[p].M + bm - 1) / bm) * ((g[p].N + bn_ - 1) / bn_) * g[p].batch;
       REQUIRE(ts[p] + tiles < (1ll << 31), CCLR_EINVAL, "grouped products: too many tiles");
       ts[p + 1] = ts[p] + (int)tiles;
     }
@@ -335,7 +335,7 @@ void grouped_products(cclr_ctx* c0, std::vector<GemmArgs> g) {
     int best = GEMM_128x64_G4;
     double best_ms = -1;
     std::vector<std::pair<int, double>> ms_all;
-    for (int var : {GEMM_128x64_G3, GEMM_64x64_G3, GEMM_128x64_G4, GEMM_64x64_G4}) {
+    for (int var : {GEMM_128x64_G3, GEMM_64x64_G3, GEMM_128x64_G4, GEMM_64x64_G4, GEMM_128x128_G4}) {
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));

@@ -1,6 +1,7 @@
 // Internal test hooks (include/cclr_debug.h).
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "../../include/cclr_debug.h"
 #include "internal.h"
@@ -44,6 +45,48 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
     return e.code;
   }
   return CCLR_OK;
+}
+
+int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N, const int* K,
+                             const cclr_c64* const* A, const cclr_c64* const* B, int btrans, cclr_c64* const* C) {
+  void* dev = nullptr;
+  int rc = CCLR_OK;
+  try {
+    REQUIRE(variant == GEMM_128x64_G3 || variant == GEMM_64x64_G3 || variant == GEMM_128x64_G4 ||
+                variant == GEMM_64x64_G4 || variant == GEMM_128x128_G4,
+            CCLR_EINVAL, "no grouped form of this GEMM variant");
+    REQUIRE(nprob > 0 && M && N && K && A && B && C, CCLR_EINVAL, "grouped GEMM: missing arguments");
+    std::vector<GemmArgs> g(nprob);
+    std::vector<int> ts(nprob + 1, 0);
+    const int bm = gemm_tile_rows(variant), bn = gemm_tile_cols(variant);
+    for (int p = 0; p < nprob; ++p) {
+      REQUIRE(M[p] > 0 && N[p] > 0 && K[p] > 0, CCLR_EINVAL, "grouped GEMM: empty product");
+      GemmArgs& x = g[p];
+      x = GemmArgs{};
+      x.M = M[p]; x.N = N[p]; x.K = K[p]; x.batch = 1;
+      x.A = (const cplx*)A[p]; x.sAm = K[p]; x.sAk = 1;
+      x.B = (const cplx*)B[p];
+      if (btrans) x.sBk = 1, x.sBn = K[p];
+      else x.sBk = N[p], x.sBn = 1;
+      x.C = (cplx*)C[p]; x.sCm = N[p]; x.sCn = 1;
+      x.ar = 1.0; x.ai = 0.0; x.beta = 0;
+      const long long tiles = (long long)((M[p] + bm - 1) / bm) * ((N[p] + bn - 1) / bn);
+      REQUIRE(ts[p] + tiles < (1ll << 31), CCLR_EINVAL, "grouped GEMM: too many tiles");
+      ts[p + 1] = ts[p] + (int)tiles;
+    }
+    const size_t bytes = sizeof(GemmArgs) * nprob + sizeof(int) * (nprob + 1);
+    HIPCHK(hipMalloc(&dev, bytes));
+    GemmArgs* pd = (GemmArgs*)dev;
+    int* td = (int*)((char*)dev + sizeof(GemmArgs) * nprob);
+    HIPCHK(hipMemcpy(pd, g.data(), sizeof(GemmArgs) * nprob, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(td, ts.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice));
+    launch_zgemm_group(pd, td, nprob, ts.back(), variant, true, !btrans, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+  } catch (const CclrError& e) {
+    rc = e.code;
+  }
+  if (dev) (void)hipFree(dev);
+  return rc;
 }
 
 int cclr_dbg_zgemm_lowp(int prec, int M, int N, int K, const cclr_c64* A, long long sAm, long long sAk, int conjA,

@@ -591,6 +591,21 @@ __global__ __launch_bounds__(512, 2) void k_zgemm_w1(GemmArgs g, int tm, int tn,
   zgemm_tile_w1<AK, BNF>(g, mi * 128, ni * 128, bz);
 }
 
+// grouped persistent form of the 128x128 tile (one workgroup per CU)
+template <bool AK, bool BNF>
+__global__ __launch_bounds__(512, 2) void k_zgemm_group_w1(const GemmArgs* __restrict__ probs,
+                                                          const int* __restrict__ tstart, int nprob, int total) {
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int p = 0;
+    while (p + 1 < nprob && t >= tstart[p + 1]) ++p;
+    const GemmArgs g = probs[p];
+    const int lt = t - tstart[p];
+    const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+    const int mi = lt % tm, rest = lt / tm;
+    zgemm_tile_w1<AK, BNF>(g, mi * 128, (rest % tn) * 128, rest / tn);
+  }
+}
+
 // Grouped persistent form: one launch walks the tiles of several products
 // (problem p owns tiles [tstart[p], tstart[p+1])), each workgroup taking
 // every gridDim.x-th tile.  The LDS of a tile is released by the barrier
@@ -853,11 +868,23 @@ static void launch_group(const GemmArgs* probs, const int* tstart, int nprob, in
   else hipLaunchKernelGGL((k_zgemm_group<BM, BN, false, false, G3>), dim3(grid), dim3(256), 0, s, probs, tstart, nprob, total);
 }
 
-int gemm_tile_rows(int variant) { return (variant == GEMM_128x64_G3 || variant == GEMM_128x64_G4) ? 128 : 64; }
+int gemm_tile_rows(int variant) {
+  return (variant == GEMM_128x64_G3 || variant == GEMM_128x64_G4 || variant == GEMM_128x128_G4) ? 128 : 64;
+}
+int gemm_tile_cols(int variant) { return variant == GEMM_128x128_G4 ? 128 : 64; }
 
 void launch_zgemm_group(const GemmArgs* probs, const int* tstart, int nprob, int total, int variant, bool ak, bool bn,
                         hipStream_t s) {
   if (total <= 0) return;
+  if (variant == GEMM_128x128_G4) {
+    const int grid = std::min(total, 256);
+    if (ak && bn) hipLaunchKernelGGL((k_zgemm_group_w1<true, true>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    else if (ak) hipLaunchKernelGGL((k_zgemm_group_w1<true, false>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    else if (bn) hipLaunchKernelGGL((k_zgemm_group_w1<false, true>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    else hipLaunchKernelGGL((k_zgemm_group_w1<false, false>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   switch (variant) {
     case GEMM_128x64_G3: launch_group<128, 64, true>(probs, tstart, nprob, total, ak, bn, s); break;
     case GEMM_64x64_G3: launch_group<64, 64, true>(probs, tstart, nprob, total, ak, bn, s); break;

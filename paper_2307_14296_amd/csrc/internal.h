@@ -128,10 +128,11 @@ int gemm_default_variant(const GemmArgs& g);
 // Several products (same operand layouts: ak = unit-stride k in A, bn = unit-
 // stride n in B; batch 1 or batched, no K splitting) in one persistent launch.
 // probs / tstart are DEVICE arrays: problem p owns tiles [tstart[p], tstart[p+1])
-// of the variant's tile shape (rows gemm_tile_rows(variant), 64 columns).
+// of the variant's tile shape (gemm_tile_rows(variant) x gemm_tile_cols(variant)).
 void launch_zgemm_group(const GemmArgs* probs, const int* tstart, int nprob, int total, int variant, bool ak, bool bn,
                         hipStream_t s);
 int gemm_tile_rows(int variant);
+int gemm_tile_cols(int variant);
 // the same product with FP32 (prec = CCLR_FP32) or split-BF16 (CCLR_BF16X3)
 // MFMA arithmetic and FP32 accumulation; operands and C stay complex128 in memory
 void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s);

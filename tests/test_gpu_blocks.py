@@ -104,6 +104,38 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
             assert err <= 1e-12, (variant, ta, tb, beta, err)
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 13])
+def test_zgemm_grouped_persistent_launch(gpu, variant):
+    """The persistent grouped launch (several products of different shapes
+    dealt as one tile sequence) in every tile shape that has a grouped form,
+    both B orientations, against numpy per product."""
+    cc, L = _cc()
+    P = ctypes.c_void_p
+    L.cclr_dbg_zgemm_group_f64.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(P)]
+    shapes = [(257, 300, 140), (130, 70, 33), (64, 129, 17), (300, 260, 50), (1, 1, 1)]
+    rng = np.random.default_rng(17 + variant)
+    for bt in (0, 1):
+        As = [crand(rng, m, k) for m, n, k in shapes]
+        Bs = [crand(rng, n, k) if bt else crand(rng, k, n) for m, n, k in shapes]
+        Ad, Bd = [dev(a) for a in As], [dev(b) for b in Bs]
+        Cd = [torch.full((m, n), 7.0 + 0j, dtype=torch.complex128, device="cuda") for m, n, k in shapes]
+        ints = lambda xs: (ctypes.c_int * len(xs))(*xs)
+        ptrs = lambda ts: (P * len(ts))(*[t.data_ptr() for t in ts])
+        rc = L.cclr_dbg_zgemm_group_f64(variant, len(shapes), ints([m for m, n, k in shapes]),
+                                        ints([n for m, n, k in shapes]), ints([k for m, n, k in shapes]),
+                                        ptrs(Ad), ptrs(Bd), bt, ptrs(Cd))
+        assert rc == 0
+        for (m, n, k), a, b, c in zip(shapes, As, Bs, Cd):
+            ref = a @ (b.T if bt else b)
+            err = np.abs(c.cpu().numpy() - ref).max() / max(1.0, np.abs(ref).max())
+            assert err <= 1e-12, (variant, bt, (m, n, k), err)
+    # the single-buffer tiles have no grouped form
+    assert L.cclr_dbg_zgemm_group_f64(9, 1, ints([1]), ints([1]), ints([1]), ptrs(Ad[:1]), ptrs(Bd[:1]), 0,
+                                      ptrs(Cd[:1])) == cc.CCLR_EINVAL
+
+
 def test_zgemm_batched_and_transposed_output(gpu):
     cc, L = _cc()
     rng = np.random.default_rng(5)
