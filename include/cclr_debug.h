@@ -74,10 +74,18 @@ int cclr_dbg_set_sigma_prec(cclr_ctx* ctx, int prec);
  * an FP64 refinement step (0: the default of the context's precision). */
 int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
 
+/* Per-product timing of the contraction engine's GEMMs: writes up to cap
+ * bytes of the record so far, one line per product: "MxNxK bB sA(m,k)
+ * sB(k,n) form F ms TFLOP/s" (F: FP64 variant >= 0, -1 short-reduction VALU
+ * kernel, -2 split-K, -3 reduced precision); then, for enable >= 0, clears
+ * the record and switches timing on (1) or off (0).  Timing synchronizes the
+ * stream after every product. */
+int cclr_dbg_gemm_trace(cclr_ctx* ctx, int enable, char* buf, long long cap);
+
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
  * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
  * the variant in use: within 2% of the fastest, the grouped tile order, then
- * 128-row tiles, are preferred).
+ * larger tiles, are preferred).
  * enable >= 0 switches tuning on (1) or off (0) for later products. */
 int cclr_dbg_tuning(cclr_ctx* ctx, int enable, char* buf, long long cap);
 

@@ -238,6 +238,22 @@ int cclr_dbg_set_inner_tol(cclr_ctx* c, double tol) {
   return CCLR_OK;
 }
 
+int cclr_dbg_gemm_trace(cclr_ctx* c, int enable, char* buf, long long cap) {
+  if (!c) return CCLR_EINVAL;
+  std::string out;
+  for (const auto& l : c->gemm_trace_log) out += l + "\n";
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>(out.size(), (size_t)cap - 1);
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  if (enable >= 0) {
+    c->gemm_trace = enable != 0;
+    c->gemm_trace_log.clear();
+  }
+  return CCLR_OK;
+}
+
 int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {
   if (!c) return CCLR_EINVAL;
   if (enable >= 0) c->autotune = enable != 0;

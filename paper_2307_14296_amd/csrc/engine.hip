@@ -485,8 +485,36 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
 // GEMM dispatch: products whose output covers too few 64x64 tiles to occupy
 // the 256 compute units split the reduction into chunks that write partial
 // products to a workspace, summed in a fixed order afterwards.
+// form: the kernel that ran (FP64 variant >= 0, -1 short-reduction VALU
+// kernel, -2 split-K with the default variant, -3 reduced precision)
+static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form);
 void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  int form = 0;
+  if (!c->gemm_trace) {
+    run_gemm_form(c, g, form);
+    return;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, c->stream));
+  run_gemm_form(c, g, form);
+  HIPCHK(hipEventRecord(e1, c->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  char line[256];
+  snprintf(line, sizeof line, "%dx%dx%d b%d sA(%lld,%lld) sB(%lld,%lld) form %d %.4f ms %.2f TFLOP/s", g.M, g.N, g.K,
+           g.batch, (long long)g.sAm, (long long)g.sAk, (long long)g.sBk, (long long)g.sBn, form, ms,
+           8.0 * g.M * (double)g.N * g.K * g.batch / (ms * 1e-3) / 1e12);
+  c->gemm_trace_log.push_back(line);
+}
+
+static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
+  form = -1;
   if (g.K <= 32 && launch_zgemm_smallk(g, c->stream)) return;
   // inside reduced-precision transforms the remaining products run on FP32 MFMA as well
   const bool lowp = c->sigma_prec != CCLR_FP64;
@@ -511,6 +539,7 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
       h.ar = 1.0;
       h.ai = 0.0;
       h.beta = 0;
+      form = lowp ? -3 : -2;
       if (lowp) launch_zgemm_lowp(h, CCLR_FP32, c->stream);
       else launch_zgemm(h, c->stream);
       launch_splitk_reduce(g.batch, (int)S, g.M, g.N, W, g.C, g.sCb, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
@@ -518,8 +547,12 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
       return;
     }
   }
-  if (lowp) launch_zgemm_lowp(g, CCLR_FP32, c->stream);
-  else tuned_gemm(c, g);
+  if (lowp) {
+    form = -3;
+    launch_zgemm_lowp(g, CCLR_FP32, c->stream);
+  } else {
+    form = tuned_gemm(c, g);
+  }
 }
 
 // Autotuner.  The first time a large product of a given shape class (M, N,
@@ -549,12 +582,12 @@ int shape_bucket(int x) {
   return ((x + q - 1) / q) * q;
 }
 
-void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return -1;
   const double flops = 8.0 * g.M * (double)g.N * g.K * g.batch;
   if (!c->autotune || flops < 5e10 || g.kchunk > 0) {
     launch_zgemm(g, c->stream);
-    return;
+    return gemm_default_variant(g);
   }
   const int tmr = std::min(g.M, kTuneRows), tbt = g.nb2 > 1 ? g.batch : std::min(g.batch, kTuneBatch);
   const auto key = std::make_tuple(octave_bucket(tmr), shape_bucket(g.N), shape_bucket(g.K), octave_bucket(tbt),
@@ -562,7 +595,7 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   auto it = c->gemm_choice.find(key);
   if (it != c->gemm_choice.end()) {
     launch_zgemm_variant(g, it->second, c->stream);
-    return;
+    return it->second;
   }
   // the timed product: the leading rows and batch entries, on a scratch output covering their index range
   GemmArgs h = g;
@@ -622,6 +655,7 @@ void tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
                                     std::to_string(g.batch) + " layout" + std::to_string(std::get<4>(key)),
                                 rec, best});
   launch_zgemm_variant(g, best, c->stream);
+  return best;
 }
 
 // -------------------------------------------------------- integral views

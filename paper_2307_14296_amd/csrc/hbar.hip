@@ -176,6 +176,11 @@ void build_intermediates(cclr_ctx* c) {
   tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
   c->WvovvL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
   tcopy(c, ten(c->WvovvL, {o, v, v, v}), "iafe", Wvovv, "eifa", one, false);
+  // W^mn_ij on packed pairs for the hole ladder of the transforms
+  if (o >= 2) {
+    c->Wop.alloc(c, sizeof(cplx) * (size_t)(c->O2() * c->O2()));
+    launch_pack_vvvv((int)o, c->Woooo.c(), c->Wop.c(), c->stream);
+  }
   // preconditioner diagonal
   c->diag.alloc(c, sizeof(cplx) * (size_t)(c->ns() + c->nd()));
   launch_diag((int)o, (int)v, c->Foo.c(), c->Fvv.c(), c->diag.c(), c->stream);

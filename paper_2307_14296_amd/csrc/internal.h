@@ -158,7 +158,7 @@ void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i
 // GEMM with automatic K splitting when the output has too few tiles to fill the GPU
 void run_gemm(cclr_ctx* c, const GemmArgs& g);
 // FP64 GEMM through the autotuner (large products: variant timed once per shape class)
-void tuned_gemm(cclr_ctx* c, const GemmArgs& g);
+int tuned_gemm(cclr_ctx* c, const GemmArgs& g);  // returns the variant launched
 // extent rounded up to the autotuner's quarter-octave and octave shape classes
 int shape_bucket(int x);
 int octave_bucket(int x);
@@ -218,6 +218,7 @@ struct cclr_ctx {
   // intermediates (unpacked, W[p][q][r][s] = W^pq_rs)
   DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo;
   DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f (the only copy of W^ab_ef)
+  DevBuf Wop;        // packed W^mn_ij, [O2][O2], m>n (rows), i>j (columns), for the hole ladder
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
   DevBuf WvvvoT;     // WvvvoT[j][e][a][b] = W^ab_ej
   DevBuf WvvvoL, WvovvL;  // WvvvoL[a][m][e][f] = W^ef_am, WvovvL[i][a][f][e] = W^ei_fa (left transform)
@@ -247,6 +248,9 @@ struct cclr_ctx {
   bool autotune = true;
   // kernel variant of grouped multi-context launches, per set of product shapes
   std::map<std::string, int> group_choice;
+  // optional per-product timing of run_gemm (shape, kernel form, ms), for diagnostics
+  bool gemm_trace = false;
+  std::vector<std::string> gemm_trace_log;
   // optional timing of the particle-particle ladder GEMM launches
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -281,7 +285,7 @@ void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z
 // The right sigma in two halves around its two large products, so that the
 // products of several contexts can be launched together: begin runs every
 // other term and returns the ring and ladder products (not yet launched);
-// finish packs the result once both have run.
+// finish adds the hole ladder and packs the result once both have run.
 struct SigmaAcc {
   Ten X0, Xa, Xi, Xai, S1, R1, R2;
 };

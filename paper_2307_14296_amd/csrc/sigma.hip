@@ -8,7 +8,8 @@
 // particle ladder 1/2 W^ab_ef r^ef_ij is evaluated directly on packed pairs:
 // sigma[IJ][AB] = sum_EF r[IJ][EF] W[AB][EF]  (right) and
 // sigma[IJ][AB] = sum_EF l[IJ][EF] W[EF][AB]  (left), with e>f so the 1/2
-// is absorbed.  Readings applied: the right-singles ring element is W^ma_ei;
+// is absorbed.  So is the hole ladder 1/2 W^mn_ij r^ab_mn:
+// sigma[IJ][AB] += sum_MN W[MN][IJ] r[MN][AB] (right; left: W[IJ][MN]).  Readings applied: the right-singles ring element is W^ma_ei;
 // the left doubles carry -P(ab) l^m_a W^ij_mb, P(ij) l^i_e W^ej_ab and
 // 1/2 l^ij_ef W^ef_ab.
 #include "internal.h"
@@ -21,13 +22,13 @@ SigmaAcc prepare(cclr_ctx* c, const VecSet& in) {
   a.R1 = ten(in.s, {k, o, v});
   a.R2 = tmp(c, {k, o, o, v, v});
   launch_unpack((int)k, (int)o, (int)v, in.s, in.d, nullptr, a.R2.p, c->stream);
-  a.X0 = tmp(c, {k, o, o, v, v});
+  // no group without a permutation operator remains outside the packed ladders (X0 stays empty)
   a.Xa = tmp(c, {k, o, o, v, v});
   a.Xi = tmp(c, {k, o, o, v, v});
   // P(ab)P(ij) group in the ring layout [k][i][a][j][b], seen through a kijab view
   a.Xai = reorder(tmp(c, {k, o, v, o, v}), "kiajb", "kijab");
   a.S1 = tmp(c, {k, o, v});
-  for (Ten* t : {&a.X0, &a.Xa, &a.Xi, &a.S1}) launch_fill(t->p, t->size(), cx(0.0), c->stream);
+  for (Ten* t : {&a.Xa, &a.Xi, &a.S1}) launch_fill(t->p, t->size(), cx(0.0), c->stream);
   return a;
 }
 
@@ -128,6 +129,26 @@ GemmArgs ladder_args(cclr_ctx* c, const VecSet& in, const VecSet& out, bool righ
   return g;
 }
 
+// Hole ladder on packed pairs, accumulated into the packed doubles of out
+// (after the particle-particle ladder, which overwrites them):
+// out[k][IJ][AB] += sum_MN Wop[MN][IJ] in[k][MN][AB] (right) or Wop[IJ][MN] (left).
+void hole_ladder(cclr_ctx* c, const VecSet& in, const VecSet& out, bool right) {
+  const i64 O2 = c->O2(), V2 = c->V2();
+  if (O2 == 0 || V2 == 0 || in.n == 0) return;
+  GemmArgs g{};
+  g.M = (int)O2;
+  g.N = (int)V2;
+  g.K = (int)O2;
+  g.batch = (int)in.n;
+  g.A = c->Wop.c(); g.sAb = 0;
+  if (right) { g.sAm = 1; g.sAk = O2; }
+  else { g.sAm = O2; g.sAk = 1; }
+  g.B = in.d; g.sBb = O2 * V2; g.sBk = V2; g.sBn = 1;
+  g.C = out.d; g.sCb = O2 * V2; g.sCm = V2; g.sCn = 1;
+  g.ar = 1.0; g.ai = 0.0; g.beta = 1;
+  run_gemm(c, g);
+}
+
 // launch with optional event timing (the debug profile hook)
 template <class F>
 void timed(cclr_ctx* c, double flops, F&& launch) {
@@ -157,7 +178,6 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   SigmaAcc& a = w.a;
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
-  Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
   Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
   Ten WR = ten(c->WR, {o, v, o, v});
@@ -191,7 +211,6 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   }
   contract(c, one, Fvv, "be", a.R2, "kijae", a.Xa, "kijab");
   contract(c, mone, Foo, "mj", a.R2, "kimab", a.Xi, "kijab");
-  contract(c, half, Woooo, "mnij", a.R2, "kmnab", a.X0, "kijab");
   w.ring = ring_args(c, in, a.Xai, true);
   w.ladder = ladder_args(c, in, out, true);
   return w;
@@ -199,6 +218,7 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
 
 void sigma_finish(cclr_ctx* c, SigmaWork& w, const VecSet& in, const VecSet& out, const cplx* z) {
   const i64 o = c->o, v = c->v, nv = in.n;
+  hole_ladder(c, in, out, true);
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, w.a.X0.p, w.a.Xa.p, w.a.Xi.p, w.a.Xai.p, w.a.S1.p, out.s, out.d, z, in.s,
                     in.d, c->stream, true);
@@ -219,7 +239,6 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   SigmaAcc a = prepare(c, in);
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
-  Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
   Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
   Ten Voovv = Vblk(c, "oovv");
@@ -239,7 +258,6 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   // doubles
   contract(c, one, a.R2, "kijae", Fvv, "eb", a.Xa, "kijab");
   contract(c, mone, a.R2, "kimab", Foo, "jm", a.Xi, "kijab");
-  contract(c, half, a.R2, "kmnab", Woooo, "ijmn", a.X0, "kijab");
   op_gemm(c, ring_args(c, in, a.Xai, false), 3);
   contract(c, one, Voovv, "ijae", Gvv, "keb", a.Xa, "kijab");
   contract(c, mone, a.R1, "kma", Wooov, "ijmb", a.Xa, "kijab");
@@ -250,6 +268,7 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
     const GemmArgs g = ladder_args(c, in, out, false);
     timed(c, gemm_flops(g), [&]() { op_gemm(c, g, 1); });
   }
+  hole_ladder(c, in, out, false);
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
                     c->stream, true);
