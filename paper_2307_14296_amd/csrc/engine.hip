@@ -541,7 +541,7 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
       h.beta = 0;
       form = lowp ? -3 : -2;
       if (lowp) launch_zgemm_lowp(h, CCLR_FP32, c->stream);
-      else launch_zgemm(h, c->stream);
+      else tuned_gemm(c, h);
       launch_splitk_reduce(g.batch, (int)S, g.M, g.N, W, g.C, g.sCb, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
       c->arena.reset(mk);
       return;
@@ -563,7 +563,8 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
 // transform is applied to, which changes from call to call (a lockstep
 // solve whose active right-hand sides converge one by one): they are timed
 // on at most kTuneRows rows and kTuneBatch batch entries and classed by
-// octave; N and K are classed by quarter octave.
+// octave; N and K are classed by quarter octave.  Split-K products (the
+// partial products of run_gemm) are timed whole and classed by chunk length.
 constexpr int kTuneRows = 8192, kTuneBatch = 16;
 bool gemm_variant_grouped(int variant) {
   return (variant > GEMM_64x64_G4 && variant <= 2 * GEMM_64x64_G4) || variant == GEMM_64x64_G4_SB_GROUPED ||
@@ -584,14 +585,19 @@ int shape_bucket(int x) {
 
 int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return -1;
-  const double flops = 8.0 * g.M * (double)g.N * g.K * g.batch;
-  if (!c->autotune || flops < 5e10 || g.kchunk > 0) {
+  const double flops = 8.0 * g.M * (double)g.N * (g.kchunk > 0 ? g.kchunk : g.K) * g.batch;
+  if (!c->autotune || flops < 5e10) {
     launch_zgemm(g, c->stream);
     return gemm_default_variant(g);
   }
-  const int tmr = std::min(g.M, kTuneRows), tbt = g.nb2 > 1 ? g.batch : std::min(g.batch, kTuneBatch);
-  const auto key = std::make_tuple(octave_bucket(tmr), shape_bucket(g.N), shape_bucket(g.K), octave_bucket(tbt),
-                                   (g.sAk == 1 ? 1 : 0) + (g.sBn == 1 ? 2 : 0) + (g.nb2 > 1 ? 4 : 0));
+  // a split-K product keeps its whole batch (it carries the parallelism of the launch)
+  const int tmr = std::min(g.M, kTuneRows),
+            tbt = (g.nb2 > 1 || g.kchunk > 0) ? g.batch : std::min(g.batch, kTuneBatch);
+  // split-K products (kchunk > 0: the batch index carries the K chunk) are classed by the chunk length
+  const auto key = std::make_tuple(octave_bucket(tmr), shape_bucket(g.N), shape_bucket(g.kchunk > 0 ? g.kchunk : g.K),
+                                   octave_bucket(tbt),
+                                   (g.sAk == 1 ? 1 : 0) + (g.sBn == 1 ? 2 : 0) + (g.nb2 > 1 ? 4 : 0) +
+                                       (g.kchunk > 0 ? 8 : 0));
   auto it = c->gemm_choice.find(key);
   if (it != c->gemm_choice.end()) {
     launch_zgemm_variant(g, it->second, c->stream);
