@@ -37,6 +37,15 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
 int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N, const int* K,
                              const cclr_c64* const* A, const cclr_c64* const* B, int btrans, cclr_c64* const* C);
 
+/* The same product (device pointers, the context's stream) through the
+ * context's GEMM dispatch: the short-reduction vector-ALU kernel, split-K,
+ * or the autotuned MFMA kernels, chosen by shape as for the contractions of
+ * a transform. */
+int cclr_dbg_run_gemm(cclr_ctx* ctx, int M, int N, int K, int batch, const cclr_c64* A, long long sAb, long long sAm,
+                      long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
+                      int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double alpha_re,
+                      double alpha_im, int beta);
+
 /* The same product (batch 1) in reduced arithmetic: prec = CCLR_FP32 (FP32
  * MFMA) or CCLR_BF16X3 (split-BF16 MFMA, three bf16 products per real
  * product, FP32 accumulation); operands and C stay complex128. */

@@ -26,6 +26,27 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
   }
 }
 
+int cclr_dbg_run_gemm(cclr_ctx* c, int M, int N, int K, int batch, const cclr_c64* A, long long sAb, long long sAm,
+                      long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
+                      int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,
+                      int beta) {
+  if (!c) return CCLR_EINVAL;
+  try {
+    REQUIRE(M > 0 && N > 0 && K > 0 && batch > 0, CCLR_EINVAL, "empty product");
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    g.A = (const cplx*)A; g.sAb = sAb; g.sAm = sAm; g.sAk = sAk; g.conjA = conjA;
+    g.B = (const cplx*)B; g.sBb = sBb; g.sBk = sBk; g.sBn = sBn; g.conjB = conjB;
+    g.C = (cplx*)C; g.sCb = sCb; g.sCm = sCm; g.sCn = sCn;
+    g.ar = ar; g.ai = ai; g.beta = beta;
+    run_gemm(c, g);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const CclrError& e) {
+    return e.code;
+  }
+  return CCLR_OK;
+}
+
 int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c64* A, long long sAb, long long sAm,
                        long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
                        int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,

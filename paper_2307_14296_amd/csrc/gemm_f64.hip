@@ -21,13 +21,13 @@ constexpr int kNegA = 1;
 namespace {
 constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 1;
 
-// element offset of batch bz (one or two batch indices)
 // complex value with the sign bit of its imaginary part xor-ed with sgn
 // (0 or 0x80000000): the conjugate, or the value itself, without arithmetic
 __device__ __forceinline__ cplx flip_im(cplx v, unsigned sgn) {
   v.y = __hiloint2double(__double2hiint(v.y) ^ (int)sgn, __double2loint(v.y));
   return v;
 }
+// element offset of batch bz (one or two batch indices)
 __device__ __forceinline__ i64 boff(const GemmArgs& g, i64 bz, i64 s1, i64 s2) {
   if (g.nb2 <= 1) return bz * s1;
   return (bz / g.nb2) * s1 + (bz % g.nb2) * s2;

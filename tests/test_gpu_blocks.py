@@ -136,6 +136,53 @@ def test_zgemm_grouped_persistent_launch(gpu, variant):
                                       ptrs(Cd[:1])) == cc.CCLR_EINVAL
 
 
+# (M, N, K, batch): narrow outputs (either side, with and without the split
+# along K), short reductions, split-K and plain MFMA products
+DISPATCH_CASES = [(20, 300, 5000, 1), (300, 20, 700, 3), (3, 1000, 700, 2), (1, 240, 4000, 5), (40, 16, 100000, 1),
+                  (4000, 12, 4000, 1), (33, 2000, 900, 1), (200, 200, 20, 7), (150, 140, 30000, 2),
+                  (500, 300, 260, 2)]
+
+
+@pytest.mark.parametrize("M,N,K,batch", DISPATCH_CASES)
+def test_run_gemm_dispatch(gpu, M, N, K, batch):
+    """The context's GEMM dispatch (the path every contraction takes) on the
+    shapes that select each kernel form, with conjugation, complex alpha and
+    accumulation, and a transposed output layout."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_run_gemm.argtypes = [P] + [ctypes.c_int] * 4 + [P, LL, LL, LL, ctypes.c_int, P, LL, LL, LL,
+                                                               ctypes.c_int, P, LL, LL, LL, ctypes.c_double,
+                                                               ctypes.c_double, ctypes.c_int]
+    ctx = cc.cclr_create(3, 6, cc.cclr_default_options())
+    try:
+        rng = np.random.default_rng(M + 7 * N + K + batch)
+        for ta, conjA, conjB, beta, tc in [(False, 0, 1, 0, False), (True, 1, 0, 1, True)]:
+            A = crand(rng, batch, M, K)
+            B = crand(rng, batch, K, N)
+            C0 = crand(rng, batch, M, N)
+            Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
+            Bd = dev(B)
+            Cd = dev(C0.transpose(0, 2, 1).copy() if tc else C0)
+            sAm, sAk = (1, M) if ta else (K, 1)
+            sCm, sCn = (1, M) if tc else (N, 1)
+            alpha = 0.7 - 0.4j
+            rc = L.cclr_dbg_run_gemm(ctx, M, N, K, batch, Ad.data_ptr(), M * K, sAm, sAk, conjA, Bd.data_ptr(), K * N,
+                                     N, 1, conjB, Cd.data_ptr(), M * N, sCm, sCn, alpha.real, alpha.imag, beta)
+            assert rc == 0
+            Ae = A.conj() if conjA else A
+            Be = B.conj() if conjB else B
+            ref = alpha * (Ae @ Be) + (C0 if beta else 0)
+            got = Cd.cpu().numpy()
+            if tc:
+                got = got.transpose(0, 2, 1)
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print(f"run_gemm {M}x{N}x{K} b{batch} ta={ta} conj=({conjA},{conjB}) beta={beta}: rel err {err:.1e}",
+                  flush=True)
+            assert err <= 1e-12
+    finally:
+        cc.cclr_destroy(ctx)
+
+
 def test_zgemm_batched_and_transposed_output(gpu):
     cc, L = _cc()
     rng = np.random.default_rng(5)
