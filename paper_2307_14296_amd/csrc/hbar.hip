@@ -176,10 +176,15 @@ void build_intermediates(cclr_ctx* c) {
   tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
   c->WvovvL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
   tcopy(c, ten(c->WvovvL, {o, v, v, v}), "iafe", Wvovv, "eifa", one, false);
-  // W^mn_ij on packed pairs for the hole ladder of the transforms
+  // hole-ladder operator of the transforms on packed pairs: W^mn_ij plus the
+  // doubles term -P(ij) F^m_j r^ab_im written as a pair operator,
+  //   E^mn_ij = -(d_im F^n_j - d_in F^m_j - d_jm F^n_i + d_jn F^m_i),
+  // so that 1/2 sum_mn (W + E)^mn_ij r^ab_mn carries both (the same array read
+  // as [IJ][MN] gives the left-transform terms 1/2 l^mn_ab W^ij_mn - P(ij) l^im_ab F^j_m)
   if (o >= 2) {
     c->Wop.alloc(c, sizeof(cplx) * (size_t)(c->O2() * c->O2()));
     launch_pack_vvvv((int)o, c->Woooo.c(), c->Wop.c(), c->stream);
+    launch_pair_fold((int)o, c->Foo.c(), c->Wop.c(), -1.0, c->stream);
   }
   // preconditioner diagonal
   c->diag.alloc(c, sizeof(cplx) * (size_t)(c->ns() + c->nd()));

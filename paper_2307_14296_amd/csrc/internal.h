@@ -188,6 +188,9 @@ void launch_unpack(int nvec, int o, int v, const cplx* s, const cplx* d, cplx* r
 void launch_unpack_ring(int nvec, int o, int v, const cplx* d, cplx* rr, hipStream_t st);
 void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cplx* s, cplx* d, hipStream_t st);
 // pair packing of the last two indices: dst[r][AB] = src[r][a][b] (a > b)
+// X[P][Q] += alpha (d(p1,q1) F[p2][q2] - d(p1,q2) F[p2][q1] - d(p2,q1) F[p1][q2] + d(p2,q2) F[p1][q1])
+// for pairs P = (p1 > p2), Q = (q1 > q2) of n indices; X is [n(n-1)/2][n(n-1)/2], F is n x n
+void launch_pair_fold(int n, const cplx* F, cplx* X, double alpha, hipStream_t s);
 void launch_pack_pairs(i64 rows, int v, const cplx* src, cplx* dst, hipStream_t s);
 // dst[r][a][b] += alpha src[r][AB], dst[r][b][a] -= alpha src[r][AB]
 void launch_unpack_pairs_acc(i64 rows, int v, const cplx* src, cplx* dst, double alpha, hipStream_t s);
@@ -218,7 +221,8 @@ struct cclr_ctx {
   // intermediates (unpacked, W[p][q][r][s] = W^pq_rs)
   DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo;
   DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f (the only copy of W^ab_ef)
-  DevBuf Wop;        // packed W^mn_ij, [O2][O2], m>n (rows), i>j (columns), for the hole ladder
+  DevBuf Wop;        // packed hole-ladder operator, [O2][O2], m>n (rows), i>j (columns): W^mn_ij with
+                     // the doubles' F^m_j term folded in
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
   DevBuf WvvvoT;     // WvvvoT[j][e][a][b] = W^ab_ej
   DevBuf WvvvoL, WvovvL;  // WvvvoL[a][m][e][f] = W^ef_am, WvovvL[i][a][f][e] = W^ei_fa (left transform)

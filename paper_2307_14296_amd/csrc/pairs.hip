@@ -80,7 +80,41 @@ __global__ __launch_bounds__(256) void k_unpack_vvvv(int v, const cplx* __restri
   }
 }
 
+// One-body operator folded into a packed pair operator:
+//   X[P][Q] += s (d(p1,q1) F[p2][q2] - d(p1,q2) F[p2][q1] - d(p2,q1) F[p1][q2] + d(p2,q2) F[p1][q1])
+// for pairs P = (p1 > p2), Q = (q1 > q2) of n indices, X row-major [n2][n2].
+// Thread (P, x) updates the pairs Q = {p1, x} (x != p1) and Q = {p2, x}
+// (x != p1, p2), which are all the Q that share an index with P, once each.
+__global__ __launch_bounds__(256) void k_pair_fold(int n, const cplx* __restrict__ F, cplx* __restrict__ X, double s) {
+  const i64 n2 = (i64)n * (n - 1) / 2, total = n2 * n;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (i64)gridDim.x * blockDim.x) {
+    const i64 P = e / n;
+    const int x = (int)(e % n);
+    int p1, p2;
+    unpair(P, p1, p2);
+    auto add = [&](int y, int z) {
+      const int q1 = y > z ? y : z, q2 = y > z ? z : y;
+      double tr = 0.0, ti = 0.0;
+      if (p1 == q1) tr += F[p2 * n + q2].x, ti += F[p2 * n + q2].y;
+      if (p1 == q2) tr -= F[p2 * n + q1].x, ti -= F[p2 * n + q1].y;
+      if (p2 == q1) tr -= F[p1 * n + q2].x, ti -= F[p1 * n + q2].y;
+      if (p2 == q2) tr += F[p1 * n + q1].x, ti += F[p1 * n + q1].y;
+      cplx& dst = X[P * n2 + pair_index(q1, q2)];
+      dst.x += s * tr;
+      dst.y += s * ti;
+    };
+    if (x != p1) add(p1, x);
+    if (x != p1 && x != p2) add(p2, x);
+  }
+}
 }  // namespace
+
+void launch_pair_fold(int n, const cplx* F, cplx* X, double alpha, hipStream_t s) {
+  const i64 total = (i64)n * (n - 1) / 2 * n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_pair_fold, dim3(grid_for(total)), dim3(256), 0, s, n, F, X, alpha);
+  HIPCHK(hipGetLastError());
+}
 
 void launch_pack_pairs(i64 rows, int v, const cplx* src, cplx* dst, hipStream_t s) {
   const i64 total = rows * ((i64)v * (v - 1) / 2);
