@@ -411,7 +411,7 @@ void ladder_lambda_cot(Env& e, const Term& t, const Ten& cot_out) {
   g.B = c->Wp.c(); g.sBk = 1; g.sBn = V2;
   g.C = R; g.sCm = V2; g.sCn = 1;
   g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-  run_gemm(c, g);
+  with_plain_wp(c, [&]() { run_gemm(c, g); });
   launch_unpack_pairs_acc(o * o, (int)v, R, it->second.p, t.coef, c->stream);
   c->arena.reset(mk);
 }

@@ -189,7 +189,7 @@ int cclr_dbg_get(cclr_ctx* c, const char* name, cclr_c64* dst, long long* count)
     if (count) *count = (long long)(v * v * v * v);
     if (dst && c->Wp.p) {
       try {
-        launch_unpack_vvvv(c->v, c->Wp.c(), (cplx*)dst, c->stream);
+        with_plain_wp(c, [&]() { launch_unpack_vvvv(c->v, c->Wp.c(), (cplx*)dst, c->stream); });
         HIPCHK(hipStreamSynchronize(c->stream));
       } catch (const CclrError& e) {
         c->err = e.what();

@@ -13,6 +13,16 @@
 
 void launch_diag(int o, int v, const cplx* Foo, const cplx* Fvv, cplx* diag, hipStream_t s);
 
+// The doubles term P(ab) F^b_e r^ae_ij of the transforms equals
+// 1/2 sum_ef D^ab_ef r^ef_ij with the pair operator
+//   D^ab_ef = d_ae F^b_f - d_af F^b_e - d_be F^a_f + d_bf F^a_e,
+// so it is carried by the packed particle ladder when D is added to Wp[AB][EF];
+// read as Wp[EF][AB] the same array gives the left-transform term P(ab) l^ae_ij F^e_b.
+void fold_vv(cclr_ctx* c, double sign) {
+  if (c->v < 2 || !c->Wp.p) return;
+  launch_pair_fold((int)c->v, c->Fvv.c(), c->Wp.c(), sign, c->stream);
+}
+
 void build_intermediates(cclr_ctx* c) {
   const i64 o = c->o, v = c->v;
   for (int w = 0; w < 4; ++w) {  // split copies of the previous operators
@@ -176,6 +186,9 @@ void build_intermediates(cclr_ctx* c) {
   tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
   c->WvovvL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
   tcopy(c, ten(c->WvovvL, {o, v, v, v}), "iafe", Wvovv, "eifa", one, false);
+  // particle-ladder operator of the transforms: W^ab_ef plus the doubles term
+  // P(ab) F^b_e r^ae_ij written as a pair operator (fold_vv)
+  fold_vv(c, 1.0);
   // hole-ladder operator of the transforms on packed pairs: W^mn_ij plus the
   // doubles term -P(ij) F^m_j r^ab_im written as a pair operator,
   //   E^mn_ij = -(d_im F^n_j - d_in F^m_j - d_jm F^n_i + d_jn F^m_i),

@@ -191,6 +191,10 @@ void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cp
 // X[P][Q] += alpha (d(p1,q1) F[p2][q2] - d(p1,q2) F[p2][q1] - d(p2,q1) F[p1][q2] + d(p2,q2) F[p1][q1])
 // for pairs P = (p1 > p2), Q = (q1 > q2) of n indices; X is [n(n-1)/2][n(n-1)/2], F is n x n
 void launch_pair_fold(int n, const cplx* F, cplx* X, double alpha, hipStream_t s);
+struct cclr_ctx;
+// adds (sign = +1) or removes (sign = -1) the doubles' one-body term P(ab) F^b_e r^ae_ij
+// folded into the packed particle-ladder operator c->Wp
+void fold_vv(cclr_ctx* c, double sign);
 void launch_pack_pairs(i64 rows, int v, const cplx* src, cplx* dst, hipStream_t s);
 // dst[r][a][b] += alpha src[r][AB], dst[r][b][a] -= alpha src[r][AB]
 void launch_unpack_pairs_acc(i64 rows, int v, const cplx* src, cplx* dst, double alpha, hipStream_t s);
@@ -220,7 +224,8 @@ struct cclr_ctx {
   bool have_H = false, have_t = false, have_lam = false;
   // intermediates (unpacked, W[p][q][r][s] = W^pq_rs)
   DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo;
-  DevBuf Wp;         // packed W^ab_ef, [V2][V2], a>b, e>f (the only copy of W^ab_ef)
+  DevBuf Wp;         // packed particle-ladder operator, [V2][V2], a>b, e>f: W^ab_ef with the
+                     // doubles' F^b_e term folded in (see fold_vv; the only copy of W^ab_ef)
   DevBuf Wop;        // packed hole-ladder operator, [O2][O2], m>n (rows), i>j (columns): W^mn_ij with
                      // the doubles' F^m_j term folded in
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
@@ -284,6 +289,21 @@ inline cplx cx(double r, double i = 0.0) { return make_double2(r, i); }
 
 // ------------------------------------------------------------ schedule
 void build_intermediates(cclr_ctx* c);
+// runs f with the plain W^ab_ef in c->Wp (the one-body term taken out and put back afterwards)
+template <class F>
+void with_plain_wp(cclr_ctx* c, F&& f) {
+  fold_vv(c, -1.0);
+  try {
+    f();
+  } catch (...) {
+    try {
+      fold_vv(c, 1.0);
+    } catch (...) {
+    }
+    throw;
+  }
+  fold_vv(c, 1.0);
+}
 // sigma for nvec packed vectors in `in` -> `out` (packed); z per vector (may be null)
 void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z_dev);
 // The right sigma in two halves around its two large products, so that the

@@ -8,7 +8,8 @@
 // particle ladder 1/2 W^ab_ef r^ef_ij is evaluated directly on packed pairs:
 // sigma[IJ][AB] = sum_EF r[IJ][EF] W[AB][EF]  (right) and
 // sigma[IJ][AB] = sum_EF l[IJ][EF] W[EF][AB]  (left), with e>f so the 1/2
-// is absorbed.  So is the hole ladder 1/2 W^mn_ij r^ab_mn together with the
+// is absorbed; the doubles term P(ab) F^b_e r^ae_ij is folded into the same
+// packed operator when the intermediates are built.  So is the hole ladder 1/2 W^mn_ij r^ab_mn together with the
 // doubles term -P(ij) F^m_j r^ab_im (folded into one packed pair operator
 // when the intermediates are built): sigma[IJ][AB] += sum_MN W[MN][IJ] r[MN][AB]
 // (right; left: W[IJ][MN]).  Readings applied: the right-singles ring element is W^ma_ei;
@@ -211,7 +212,6 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
     contract(c, half, Voovv, "nmfe", a.R2, "kjmfe", Z, "knj");
     contract(c, mone, t2, "inab", Z, "knj", a.Xi, "kijab");
   }
-  contract(c, one, Fvv, "be", a.R2, "kijae", a.Xa, "kijab");
   w.ring = ring_args(c, in, a.Xai, true);
   w.ladder = ladder_args(c, in, out, true);
   return w;
@@ -257,7 +257,6 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   contract(c, mone, Goo, "knm", Wooov, "mina", a.S1, "kia");
   contract(c, one, a.R1, "kme", WL, "meia", a.S1, "kia");  // W^ie_am = WL[m][e][i][a]
   // doubles
-  contract(c, one, a.R2, "kijae", Fvv, "eb", a.Xa, "kijab");
   op_gemm(c, ring_args(c, in, a.Xai, false), 3);
   contract(c, one, Voovv, "ijae", Gvv, "keb", a.Xa, "kijab");
   contract(c, mone, a.R1, "kma", Wooov, "ijmb", a.Xa, "kijab");
