@@ -587,8 +587,10 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return -1;
   const double flops = 8.0 * g.M * (double)g.N * (g.kchunk > 0 ? g.kchunk : g.K) * g.batch;
   if (!c->autotune || flops < 5e10) {
-    launch_zgemm(g, c->stream);
-    return gemm_default_variant(g);
+    // untimed: 64-row tiles when the output has at most 64 rows (a 128-row tile would be mostly empty)
+    const int v = g.M <= 64 ? GEMM_64x64_G4 : gemm_default_variant(g);
+    launch_zgemm_variant(g, v, c->stream);
+    return v;
   }
   // a split-K product keeps its whole batch (it carries the parallelism of the launch)
   const int tmr = std::min(g.M, kTuneRows),
