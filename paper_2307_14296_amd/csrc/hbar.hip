@@ -186,6 +186,16 @@ void build_intermediates(cclr_ctx* c) {
   tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
   c->WvovvL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
   tcopy(c, ten(c->WvovvL, {o, v, v, v}), "iafe", Wvovv, "eifa", one, false);
+  // pair-packed operators of the right transform's o^2 v^3 products
+  if (o >= 2 && v >= 2) {
+    const i64 O2 = c->O2(), V2 = c->V2();
+    c->VoovvH.alloc(c, sizeof(cplx) * (size_t)(O2 * v * v));
+    launch_pack_first_pair(1, (int)o, v * v, c->Voovv.c(), c->VoovvH.c(), c->stream);
+    c->VoovvP.alloc(c, sizeof(cplx) * (size_t)(o * o * V2));
+    launch_pack_pairs(o * o, (int)v, c->Voovv.c(), c->VoovvP.c(), c->stream);
+    c->WvovvP.alloc(c, sizeof(cplx) * (size_t)(v * o * V2));
+    launch_pack_pairs(v * o, (int)v, c->Wvovv.c(), c->WvovvP.c(), c->stream);
+  }
   // particle-ladder operator of the transforms: W^ab_ef plus the doubles term
   // P(ab) F^b_e r^ae_ij written as a pair operator (fold_vv)
   fold_vv(c, 1.0);

@@ -191,6 +191,10 @@ void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cp
 // X[P][Q] += alpha (d(p1,q1) F[p2][q2] - d(p1,q2) F[p2][q1] - d(p2,q1) F[p1][q2] + d(p2,q2) F[p1][q1])
 // for pairs P = (p1 > p2), Q = (q1 > q2) of n indices; X is [n(n-1)/2][n(n-1)/2], F is n x n
 void launch_pair_fold(int n, const cplx* F, cplx* X, double alpha, hipStream_t s);
+// dst[b][P][x] = src[b][p1][p2][x] for P = (p1 > p2) (src [nb][n][n][rest] -> dst [nb][n(n-1)/2][rest])
+void launch_pack_first_pair(i64 nb, int n, i64 rest, const cplx* src, cplx* dst, hipStream_t s);
+// the inverse for antisymmetric data: dst[b][i][j][x] = +-src[b][pair(i,j)][x], 0 on i == j
+void launch_unpack_first_pair(i64 nb, int n, i64 rest, const cplx* src, cplx* dst, hipStream_t s);
 struct cclr_ctx;
 // adds (sign = +1) or removes (sign = -1) the doubles' one-body term P(ab) F^b_e r^ae_ij
 // folded into the packed particle-ladder operator c->Wp
@@ -226,6 +230,10 @@ struct cclr_ctx {
   DevBuf Foo, Fvv, Fov, Woooo, Wovvo, Wbar, Wooov, Wvovv, Wovoo, Wvvvo;
   DevBuf Wp;         // packed particle-ladder operator, [V2][V2], a>b, e>f: W^ab_ef with the
                      // doubles' F^b_e term folded in (see fold_vv; the only copy of W^ab_ef)
+  // operators of the right transform with one index pair packed, so that the
+  // products over that pair run on it once: VoovvH[MN][e][f] = V^mn_ef (m>n),
+  // VoovvP[m][n][EF] = V^mn_ef (e>f), WvovvP[a][m][EF] = W^am_ef (e>f)
+  DevBuf VoovvH, VoovvP, WvovvP;
   DevBuf Wop;        // packed hole-ladder operator, [O2][O2], m>n (rows), i>j (columns): W^mn_ij with
                      // the doubles' F^m_j term folded in
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm

@@ -107,7 +107,52 @@ __global__ __launch_bounds__(256) void k_pair_fold(int n, const cplx* __restrict
     if (x != p1 && x != p2) add(p2, x);
   }
 }
+
+// dst[b][P][x] = src[b][p1][p2][x] for P = (p1 > p2): the rows of a leading
+// antisymmetric index pair kept once (src [nb][n][n][rest], dst [nb][n2][rest])
+__global__ __launch_bounds__(256) void k_pack_first_pair(i64 nb, int n, i64 rest, const cplx* __restrict__ src,
+                                                         cplx* __restrict__ dst) {
+  const i64 n2 = (i64)n * (n - 1) / 2, total = nb * n2 * rest;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (i64)gridDim.x * blockDim.x) {
+    const i64 x = e % rest, P = e / rest % n2, b = e / (rest * n2);
+    int p1, p2;
+    unpair(P, p1, p2);
+    dst[e] = src[((b * n + p1) * n + p2) * rest + x];
+  }
+}
+
+// dst[b][i][j][x] = src[b][IJ][x] (i > j), -src[b][JI][x] (i < j), 0 (i == j):
+// a leading packed pair unpacked (src [nb][n2][rest], dst [nb][n][n][rest])
+__global__ __launch_bounds__(256) void k_unpack_first_pair(i64 nb, int n, i64 rest, const cplx* __restrict__ src,
+                                                           cplx* __restrict__ dst) {
+  const i64 n2 = (i64)n * (n - 1) / 2, total = nb * n * n * rest;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (i64)gridDim.x * blockDim.x) {
+    const i64 x = e % rest, ij = e / rest % ((i64)n * n), b = e / (rest * n * n);
+    const int i = (int)(ij / n), j = (int)(ij % n);
+    cplx y = make_double2(0.0, 0.0);
+    if (i > j) y = src[(b * n2 + pair_index(i, j)) * rest + x];
+    else if (i < j) {
+      const cplx t = src[(b * n2 + pair_index(j, i)) * rest + x];
+      y = make_double2(-t.x, -t.y);
+    }
+    dst[e] = y;
+  }
+}
 }  // namespace
+
+void launch_pack_first_pair(i64 nb, int n, i64 rest, const cplx* src, cplx* dst, hipStream_t s) {
+  const i64 total = nb * ((i64)n * (n - 1) / 2) * rest;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_pack_first_pair, dim3(grid_for(total)), dim3(256), 0, s, nb, n, rest, src, dst);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_unpack_first_pair(i64 nb, int n, i64 rest, const cplx* src, cplx* dst, hipStream_t s) {
+  const i64 total = nb * n * (i64)n * rest;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_unpack_first_pair, dim3(grid_for(total)), dim3(256), 0, s, nb, n, rest, src, dst);
+  HIPCHK(hipGetLastError());
+}
 
 void launch_pair_fold(int n, const cplx* F, cplx* X, double alpha, hipStream_t s) {
   const i64 total = (i64)n * (n - 1) / 2 * n;

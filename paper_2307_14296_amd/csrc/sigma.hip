@@ -191,7 +191,15 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   contract(c, mone, Fov, "me", a.R2, "kimea", a.S1, "kia");
   // W^ma_ei read from the ring operator WR[i][a][m][e]
   contract(c, one, WR, "iame", a.R1, "kme", a.S1, "kia");
-  contract(c, half, Wvovv, "amef", a.R2, "kimef", a.S1, "kia");
+  // r^ef_im with (i, m) unpacked and (e, f) packed: the v-pair sums below run over e > f once
+  const bool pairs = o >= 2 && v >= 2;
+  Ten R2v;
+  if (pairs) {
+    R2v = tmp(c, {nv, o, o, c->V2()});
+    launch_unpack_first_pair(nv, (int)o, c->V2(), in.d, R2v.p, c->stream);
+    // 1/2 W^am_ef r^ef_im = sum_(m, e>f) W^am_ef r^ef_im
+    contract(c, one, ten(c->WvovvP, {v, o, c->V2()}), "amQ", R2v, "kimQ", a.S1, "kia");
+  }
   contract(c, half, Wooov, "mnie", a.R2, "kmnea", a.S1, "kia");
   // doubles
   contract(c, mone, Wovoo, "mbij", a.R1, "kma", a.Xa, "kijab");
@@ -201,15 +209,20 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
     // Y_bf = W^bm_fe r^e_m - 1/2 V^nm_fe r^eb_mn, and likewise
     // -P(ij) [W^nm_je r^e_m t^ab_in + 1/2 V^nm_fe r^fe_im t^ba_jn] = -P(ij) t^ab_in Z_nj with
     // Z_nj = W^nm_je r^e_m + 1/2 V^nm_fe r^fe_jm  (antisymmetry of t relabels the second terms)
-    Ten Voovv = Vblk(c, "oovv");
     Ten Y = tmp(c, {nv, v, v});
     // antisymmetry relabellings W^bm_fe = -W^bm_ef, V^nm_fe = V^mn_ef keep the reductions unit-stride
     contract(c, mone, Wvovv, "bmef", a.R1, "kme", Y, "kbf", false);
-    contract(c, mhalf, Voovv, "mnef", a.R2, "kmneb", Y, "kbf");
+    if (pairs) {
+      // -1/2 V^mn_ef r^eb_mn = -sum_(m>n, e) V^mn_ef r^eb_mn on the (m>n) rows of r
+      Ten R2h = tmp(c, {nv, c->O2(), v, v});
+      launch_pack_first_pair(nv, (int)o, v * v, a.R2.p, R2h.p, c->stream);
+      contract(c, mone, ten(c->VoovvH, {c->O2(), v, v}), "Pef", R2h, "kPeb", Y, "kbf");
+    }
     contract(c, one, t2, "ijaf", Y, "kbf", a.Xa, "kijab");
     Ten Z = tmp(c, {nv, o, o});
     contract(c, one, Wooov, "nmje", a.R1, "kme", Z, "knj", false);
-    contract(c, half, Voovv, "nmfe", a.R2, "kjmfe", Z, "knj");
+    // 1/2 V^nm_fe r^fe_jm = sum_(m, f>e) V^nm_fe r^fe_jm
+    if (pairs) contract(c, one, ten(c->VoovvP, {o, o, c->V2()}), "nmQ", R2v, "kjmQ", Z, "knj");
     contract(c, mone, t2, "inab", Z, "knj", a.Xi, "kijab");
   }
   w.ring = ring_args(c, in, a.Xai, true);
