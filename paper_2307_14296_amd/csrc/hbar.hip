@@ -195,6 +195,8 @@ void build_intermediates(cclr_ctx* c) {
     launch_pack_pairs(o * o, (int)v, c->Voovv.c(), c->VoovvP.c(), c->stream);
     c->WvovvP.alloc(c, sizeof(cplx) * (size_t)(v * o * V2));
     launch_pack_pairs(v * o, (int)v, c->Wvovv.c(), c->WvovvP.c(), c->stream);
+    // -sum_me F^m_e r^ea_im = sum_(m, e>f) X^am_ef r^ef_im with X^am_ef = d_ea F^m_f - d_fa F^m_e
+    launch_fold_ov((int)o, (int)v, c->Fov.c(), c->WvovvP.c(), c->stream);
   }
   // particle-ladder operator of the transforms: W^ab_ef plus the doubles term
   // P(ab) F^b_e r^ae_ij written as a pair operator (fold_vv)

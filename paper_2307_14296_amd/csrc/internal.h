@@ -191,6 +191,8 @@ void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cp
 // X[P][Q] += alpha (d(p1,q1) F[p2][q2] - d(p1,q2) F[p2][q1] - d(p2,q1) F[p1][q2] + d(p2,q2) F[p1][q1])
 // for pairs P = (p1 > p2), Q = (q1 > q2) of n indices; X is [n(n-1)/2][n(n-1)/2], F is n x n
 void launch_pair_fold(int n, const cplx* F, cplx* X, double alpha, hipStream_t s);
+// W[a][m][pair(a,x)] += (a > x ? 1 : -1) F[m][x] for x != a (W [v][o][v(v-1)/2], F [o][v])
+void launch_fold_ov(int o, int v, const cplx* F, cplx* W, hipStream_t s);
 // dst[b][P][x] = src[b][p1][p2][x] for P = (p1 > p2) (src [nb][n][n][rest] -> dst [nb][n(n-1)/2][rest])
 void launch_pack_first_pair(i64 nb, int n, i64 rest, const cplx* src, cplx* dst, hipStream_t s);
 // the inverse for antisymmetric data: dst[b][i][j][x] = +-src[b][pair(i,j)][x], 0 on i == j
@@ -232,7 +234,8 @@ struct cclr_ctx {
                      // doubles' F^b_e term folded in (see fold_vv; the only copy of W^ab_ef)
   // operators of the right transform with one index pair packed, so that the
   // products over that pair run on it once: VoovvH[MN][e][f] = V^mn_ef (m>n),
-  // VoovvP[m][n][EF] = V^mn_ef (e>f), WvovvP[a][m][EF] = W^am_ef (e>f)
+  // VoovvP[m][n][EF] = V^mn_ef (e>f), WvovvP[a][m][EF] = W^am_ef (e>f) with the
+  // singles term -F^m_e r^ea_im folded in
   DevBuf VoovvH, VoovvP, WvovvP;
   DevBuf Wop;        // packed hole-ladder operator, [O2][O2], m>n (rows), i>j (columns): W^mn_ij with
                      // the doubles' F^m_j term folded in

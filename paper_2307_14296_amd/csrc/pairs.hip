@@ -138,7 +138,30 @@ __global__ __launch_bounds__(256) void k_unpack_first_pair(i64 nb, int n, i64 re
     dst[e] = y;
   }
 }
+
+// W[a][m][pair(a,x)] += (a > x ? 1 : -1) F[m][x] for x != a (W [v][o][V2], F [o][v]):
+// the singles term -sum_me F^m_e r^ea_im as a v-pair operator, added to the
+// pair-packed W^am_ef of the term 1/2 W^am_ef r^ef_im
+__global__ __launch_bounds__(256) void k_fold_ov(int o, int v, const cplx* __restrict__ F, cplx* __restrict__ W) {
+  const i64 V2 = (i64)v * (v - 1) / 2, total = (i64)v * o * v;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (i64)gridDim.x * blockDim.x) {
+    const int x = (int)(e % v), m = (int)(e / v % o), a = (int)(e / ((i64)v * o));
+    if (x == a) continue;
+    const cplx f = F[(i64)m * v + x];
+    const double sg = a > x ? 1.0 : -1.0;
+    cplx& dst = W[((i64)a * o + m) * V2 + (a > x ? pair_index(a, x) : pair_index(x, a))];
+    dst.x += sg * f.x;
+    dst.y += sg * f.y;
+  }
+}
 }  // namespace
+
+void launch_fold_ov(int o, int v, const cplx* F, cplx* W, hipStream_t s) {
+  const i64 total = (i64)v * o * v;
+  if (total <= 0 || v < 2) return;
+  hipLaunchKernelGGL(k_fold_ov, dim3(grid_for(total)), dim3(256), 0, s, o, v, F, W);
+  HIPCHK(hipGetLastError());
+}
 
 void launch_pack_first_pair(i64 nb, int n, i64 rest, const cplx* src, cplx* dst, hipStream_t s) {
   const i64 total = nb * ((i64)n * (n - 1) / 2) * rest;

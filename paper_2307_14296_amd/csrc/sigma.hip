@@ -187,8 +187,6 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   // singles
   contract(c, one, Fvv, "ae", a.R1, "kie", a.S1, "kia");
   contract(c, mone, Foo, "mi", a.R1, "kma", a.S1, "kia");
-  // r^ea_mi = -r^ea_im: unit-stride (m,e) reduction over the stored r[k][i][m][e][a]
-  contract(c, mone, Fov, "me", a.R2, "kimea", a.S1, "kia");
   // W^ma_ei read from the ring operator WR[i][a][m][e]
   contract(c, one, WR, "iame", a.R1, "kme", a.S1, "kia");
   // r^ef_im with (i, m) unpacked and (e, f) packed: the v-pair sums below run over e > f once
@@ -197,8 +195,10 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   if (pairs) {
     R2v = tmp(c, {nv, o, o, c->V2()});
     launch_unpack_first_pair(nv, (int)o, c->V2(), in.d, R2v.p, c->stream);
-    // 1/2 W^am_ef r^ef_im = sum_(m, e>f) W^am_ef r^ef_im
+    // 1/2 W^am_ef r^ef_im - F^m_e r^ea_im = sum_(m, e>f) (W + X)^am_ef r^ef_im (X folded into WvovvP)
     contract(c, one, ten(c->WvovvP, {v, o, c->V2()}), "amQ", R2v, "kimQ", a.S1, "kia");
+  } else {
+    contract(c, mone, Fov, "me", a.R2, "kimea", a.S1, "kia");
   }
   contract(c, half, Wooov, "mnie", a.R2, "kmnea", a.S1, "kia");
   // doubles
