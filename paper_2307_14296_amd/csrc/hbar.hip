@@ -197,6 +197,12 @@ void build_intermediates(cclr_ctx* c) {
     launch_pack_pairs(v * o, (int)v, c->Wvovv.c(), c->WvovvP.c(), c->stream);
     // -sum_me F^m_e r^ea_im = sum_(m, e>f) X^am_ef r^ef_im with X^am_ef = d_ea F^m_f - d_fa F^m_e
     launch_fold_ov((int)o, (int)v, c->Fov.c(), c->WvovvP.c(), c->stream);
+    c->WovooH.alloc(c, sizeof(cplx) * (size_t)(o * v * O2));
+    launch_pack_pairs(o * v, (int)o, c->Wovoo.c(), c->WovooH.c(), c->stream);
+    c->WooovH.alloc(c, sizeof(cplx) * (size_t)(O2 * o * v));
+    launch_pack_first_pair(1, (int)o, o * v, c->Wooov.c(), c->WooovH.c(), c->stream);
+    c->t2H.alloc(c, sizeof(cplx) * (size_t)(O2 * v * v));
+    launch_pack_first_pair(1, (int)o, v * v, c->t2.c(), c->t2H.c(), c->stream);
   }
   // particle-ladder operator of the transforms: W^ab_ef plus the doubles term
   // P(ab) F^b_e r^ae_ij written as a pair operator (fold_vv)

@@ -211,10 +211,11 @@ void launch_unpack_vvvv(int v, const cplx* Wp, cplx* dst, hipStream_t s);
 void launch_pack_vvvv(int v, const cplx* W, cplx* Wp, hipStream_t s);
 // out(packed) += X0 + P(ab)Xa + P(ij)Xi + P(ab)P(ij)Xai  (any X may be null),
 // singles out += S1; then out -= z_k * r_k  (z may be null).  X0, Xa, Xi are
-// [k][i][j][a][b]; Xai is [k][i][j][a][b], or [k][i][a][j][b] if xai_ring.
+// [k][i][j][a][b]; Xai is [k][i][j][a][b], or [k][i][a][j][b] if xai_ring; Xa
+// is [k][IJ][a][b] (pairs i > j only) if xa_half.
 void launch_pack_sigma(int nvec, int o, int v, const cplx* X0, const cplx* Xa, const cplx* Xi, const cplx* Xai,
                        const cplx* S1, cplx* outs, cplx* outd, const cplx* zk, const cplx* rs, const cplx* rd,
-                       hipStream_t st, bool xai_ring = false);
+                       hipStream_t st, bool xai_ring = false, bool xa_half = false);
 
 // ------------------------------------------------------------ context
 struct cclr_ctx {
@@ -237,6 +238,10 @@ struct cclr_ctx {
   // VoovvP[m][n][EF] = V^mn_ef (e>f), WvovvP[a][m][EF] = W^am_ef (e>f) with the
   // singles term -F^m_e r^ea_im folded in
   DevBuf VoovvH, VoovvP, WvovvP;
+  // the operands of the P(ab)-only doubles terms with the occupied pair packed
+  // (their output is needed for i > j only): WovooH[m][b][IJ] = W^mb_ij,
+  // WooovH[IJ][m][b] = W^ij_mb, t2H[IJ][a][f] = t^af_ij
+  DevBuf WovooH, WooovH, t2H;
   DevBuf Wop;        // packed hole-ladder operator, [O2][O2], m>n (rows), i>j (columns): W^mn_ij with
                      // the doubles' F^m_j term folded in
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm

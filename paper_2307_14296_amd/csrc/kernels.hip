@@ -145,14 +145,15 @@ __global__ __launch_bounds__(256) void k_pack_full(int nvec, int o, int v, const
 }
 
 // packed sigma assembly with the antisymmetrizers applied on the fly:
-// out += X0 + P(ab) Xa + P(ij) Xi + P(ab)P(ij) Xai - z r.  Doubles: one
+// out += X0 + P(ab) Xa + P(ij) Xi + P(ab)P(ij) Xai - z r (Xa, having no P(ij),
+// may hold the pairs i > j only: xa_half, layout [k][IJ][a][b]).  Doubles: one
 // workgroup per (vector, occupied pair i > j, tile pair); the images with
 // exchanged virtual indices are read with unit stride along a into LDS.
 __global__ __launch_bounds__(256) void k_pack_sigma_t(int o, int v, const cplx* __restrict__ X0,
                                                       const cplx* __restrict__ Xa, const cplx* __restrict__ Xi,
                                                       const cplx* __restrict__ Xai, cplx* __restrict__ outd,
                                                       const cplx* __restrict__ zk, const cplx* __restrict__ rd,
-                                                      int xai_ring) {
+                                                      int xai_ring, int xa_half) {
   __shared__ cplx s[PT][PT + 1];
   const i64 O2 = (i64)o * (o - 1) / 2, V2 = (i64)v * (v - 1) / 2;
   const int k = blockIdx.z, y = blockIdx.y, tid = threadIdx.x;
@@ -165,12 +166,16 @@ __global__ __launch_bounds__(256) void k_pack_sigma_t(int o, int v, const cplx* 
   auto ar = [&](int ii, int jj, int aa, int bb) -> i64 {
     return xai_ring ? base + (((i64)ii * v + aa) * o + jj) * v + bb : at(ii, jj, aa, bb);
   };
+  // Xa of the pair i > j only ([k][IJ][a][b]) or full
+  auto ah = [&](int aa, int bb) -> i64 {
+    return xa_half ? (((i64)k * O2 + y) * v + aa) * v + bb : at(i, j, aa, bb);
+  };
   // exchanged-virtual images on rows b, columns a: -Xa(i,j,b,a) - Xai(i,j,b,a) + Xai(j,i,b,a)
   for (int e = tid; e < PT * PT; e += 256) {
     const int r = e / PT, c = e % PT, b = b0 + r, a = a0 + c;
     double tr = 0.0, ti = 0.0;
     if (a < v && b < v) {
-      if (Xa) { const cplx u = Xa[at(i, j, b, a)]; tr -= u.x; ti -= u.y; }
+      if (Xa) { const cplx u = Xa[ah(b, a)]; tr -= u.x; ti -= u.y; }
       if (Xai) {
         const cplx u = Xai[ar(i, j, b, a)], w = Xai[ar(j, i, b, a)];
         tr += w.x - u.x; ti += w.y - u.y;
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(256) void k_pack_sigma_t(int o, int v, const cplx* 
     const cplx sx = s[c][r];
     t.x += sx.x; t.y += sx.y;
     if (X0) { const cplx u = X0[at(i, j, a, b)]; t.x += u.x; t.y += u.y; }
-    if (Xa) { const cplx u = Xa[at(i, j, a, b)]; t.x += u.x; t.y += u.y; }
+    if (Xa) { const cplx u = Xa[ah(a, b)]; t.x += u.x; t.y += u.y; }
     if (Xi) {
       const cplx u = Xi[at(i, j, a, b)], w = Xi[at(j, i, a, b)];
       t.x += u.x - w.x; t.y += u.y - w.y;
@@ -265,12 +270,12 @@ void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cp
 
 void launch_pack_sigma(int nvec, int o, int v, const cplx* X0, const cplx* Xa, const cplx* Xi, const cplx* Xai,
                        const cplx* S1, cplx* outs, cplx* outd, const cplx* zk, const cplx* rs, const cplx* rd,
-                       hipStream_t st, bool xai_ring) {
+                       hipStream_t st, bool xai_ring, bool xa_half) {
   if (nvec <= 0) return;
   const i64 ov = (i64)o * v;
   hipLaunchKernelGGL(k_pack_sigma_s, dim3(grid_for((i64)nvec * ov)), dim3(256), 0, st, nvec, ov, S1, outs, zk, rs);
   hipLaunchKernelGGL(k_pack_sigma_t, perm_grid(nvec, o, v, false), dim3(256), 0, st, o, v, X0, Xa, Xi, Xai, outd, zk,
-                     rd, xai_ring ? 1 : 0);
+                     rd, xai_ring ? 1 : 0, xa_half ? 1 : 0);
   HIPCHK(hipGetLastError());
 }
 

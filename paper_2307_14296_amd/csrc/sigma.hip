@@ -26,7 +26,8 @@ SigmaAcc prepare(cclr_ctx* c, const VecSet& in) {
   a.R2 = tmp(c, {k, o, o, v, v});
   launch_unpack((int)k, (int)o, (int)v, in.s, in.d, nullptr, a.R2.p, c->stream);
   // no group without a permutation operator remains outside the packed ladders (X0 stays empty)
-  a.Xa = tmp(c, {k, o, o, v, v});
+  // P(ab) group of the pairs i > j only ([k][IJ][a][b]): no P(ij) acts on it
+  a.Xa = tmp(c, {k, c->O2(), v, v});
   a.Xi = tmp(c, {k, o, o, v, v});
   // P(ab)P(ij) group in the ring layout [k][i][a][j][b], seen through a kijab view
   a.Xai = reorder(tmp(c, {k, o, v, o, v}), "kiajb", "kijab");
@@ -202,7 +203,8 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   }
   contract(c, half, Wooov, "mnie", a.R2, "kmnea", a.S1, "kia");
   // doubles
-  contract(c, mone, Wovoo, "mbij", a.R1, "kma", a.Xa, "kijab");
+  const i64 O2 = c->O2();
+  if (O2 > 0) contract(c, mone, ten(c->WovooH, {o, v, O2}), "mbP", a.R1, "kma", a.Xa, "kPab");
   contract(c, one, ten(c->WvvvoT, {o, v, v, v}), "jeab", a.R1, "kie", a.Xi, "kijab");
   {
     // P(ab) [W^bm_fe r^e_m t^af_ij - 1/2 V^nm_fe r^ea_mn t^fb_ij] = P(ab) t^af_ij Y_bf with
@@ -218,7 +220,7 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
       launch_pack_first_pair(nv, (int)o, v * v, a.R2.p, R2h.p, c->stream);
       contract(c, mone, ten(c->VoovvH, {c->O2(), v, v}), "Pef", R2h, "kPeb", Y, "kbf");
     }
-    contract(c, one, t2, "ijaf", Y, "kbf", a.Xa, "kijab");
+    if (O2 > 0) contract(c, one, ten(c->t2H, {O2, v, v}), "Paf", Y, "kbf", a.Xa, "kPab");
     Ten Z = tmp(c, {nv, o, o});
     contract(c, one, Wooov, "nmje", a.R1, "kme", Z, "knj", false);
     // 1/2 V^nm_fe r^fe_jm = sum_(m, f>e) V^nm_fe r^fe_jm
@@ -235,7 +237,7 @@ void sigma_finish(cclr_ctx* c, SigmaWork& w, const VecSet& in, const VecSet& out
   hole_ladder(c, in, out, true);
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, w.a.X0.p, w.a.Xa.p, w.a.Xi.p, w.a.Xai.p, w.a.S1.p, out.s, out.d, z, in.s,
-                    in.d, c->stream, true);
+                    in.d, c->stream, true, true);
   c->arena.reset(w.mk);
 }
 
@@ -271,8 +273,10 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   contract(c, one, a.R1, "kme", WL, "meia", a.S1, "kia");  // W^ie_am = WL[m][e][i][a]
   // doubles
   op_gemm(c, ring_args(c, in, a.Xai, false), 3);
-  contract(c, one, Voovv, "ijae", Gvv, "keb", a.Xa, "kijab");
-  contract(c, mone, a.R1, "kma", Wooov, "ijmb", a.Xa, "kijab");
+  if (c->O2() > 0) {
+    contract(c, one, ten(c->VoovvH, {c->O2(), v, v}), "Pae", Gvv, "keb", a.Xa, "kPab");
+    contract(c, mone, a.R1, "kma", ten(c->WooovH, {c->O2(), o, v}), "Pmb", a.Xa, "kPab");
+  }
   contract(c, mone, Voovv, "imab", Goo, "kjm", a.Xi, "kijab");
   contract(c, one, a.R1, "kie", Wvovv, "ejab", a.Xi, "kijab");
   contract(c, one, a.R1, "kia", Fov, "jb", a.Xai, "kijab");
@@ -283,6 +287,6 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   hole_ladder(c, in, out, false);
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, a.X0.p, a.Xa.p, a.Xi.p, a.Xai.p, a.S1.p, out.s, out.d, z, in.s, in.d,
-                    c->stream, true);
+                    c->stream, true, true);
   c->arena.reset(mk);
 }
