@@ -179,8 +179,13 @@ void build_intermediates(cclr_ctx* c) {
   tcopy(c, ten(c->WR, {o, v, o, v}), "jbme", Wovvo, "mbej", one, false);
   tcopy(c, ten(c->WL, {o, v, o, v}), "mejb", Wovvo, "jebm", one, false);
   // W^ab_ej as [j][e][a][b] for the right doubles term P(ij) W^ab_ej r^e_i (unit-stride ab)
-  c->WvvvoT.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
-  tcopy(c, ten(c->WvvvoT, {o, v, v, v}), "jeab", Wvvvo, "abej", one, false);
+  if (v >= 2) {
+    // W^ab_ej as [j][e][AB] (a > b) for the right doubles term P(ij) W^ab_ej r^e_i
+    Ten wt = tmp(c, {o, v, v, v});
+    tcopy(c, wt, "jeab", Wvvvo, "abej", one, false);
+    c->WvvvoTP.alloc(c, sizeof(cplx) * (size_t)(o * v * c->V2()));
+    launch_pack_pairs(o * v, (int)v, wt.p, c->WvvvoTP.c(), c->stream);
+  }
   // left-transform layouts with unit-stride reductions: W^ef_am as [a][m][e][f], W^ei_fa as [i][a][f][e]
   c->WvvvoL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
   tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
@@ -201,6 +206,8 @@ void build_intermediates(cclr_ctx* c) {
     launch_pack_pairs(o * v, (int)o, c->Wovoo.c(), c->WovooH.c(), c->stream);
     c->WooovH.alloc(c, sizeof(cplx) * (size_t)(O2 * o * v));
     launch_pack_first_pair(1, (int)o, o * v, c->Wooov.c(), c->WooovH.c(), c->stream);
+    c->t2P.alloc(c, sizeof(cplx) * (size_t)(o * o * V2));
+    launch_pack_pairs(o * o, (int)v, c->t2.c(), c->t2P.c(), c->stream);
     c->t2H.alloc(c, sizeof(cplx) * (size_t)(O2 * v * v));
     launch_pack_first_pair(1, (int)o, v * v, c->t2.c(), c->t2H.c(), c->stream);
   }

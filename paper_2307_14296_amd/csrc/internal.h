@@ -212,10 +212,11 @@ void launch_pack_vvvv(int v, const cplx* W, cplx* Wp, hipStream_t s);
 // out(packed) += X0 + P(ab)Xa + P(ij)Xi + P(ab)P(ij)Xai  (any X may be null),
 // singles out += S1; then out -= z_k * r_k  (z may be null).  X0, Xa, Xi are
 // [k][i][j][a][b]; Xai is [k][i][j][a][b], or [k][i][a][j][b] if xai_ring; Xa
-// is [k][IJ][a][b] (pairs i > j only) if xa_half.
+// is [k][IJ][a][b] (pairs i > j only) if xa_half; Xi is [k][i][j][AB] (pairs
+// a > b only) if xi_vpacked.
 void launch_pack_sigma(int nvec, int o, int v, const cplx* X0, const cplx* Xa, const cplx* Xi, const cplx* Xai,
                        const cplx* S1, cplx* outs, cplx* outd, const cplx* zk, const cplx* rs, const cplx* rd,
-                       hipStream_t st, bool xai_ring = false, bool xa_half = false);
+                       hipStream_t st, bool xai_ring = false, bool xa_half = false, bool xi_vpacked = false);
 
 // ------------------------------------------------------------ context
 struct cclr_ctx {
@@ -242,10 +243,11 @@ struct cclr_ctx {
   // (their output is needed for i > j only): WovooH[m][b][IJ] = W^mb_ij,
   // WooovH[IJ][m][b] = W^ij_mb, t2H[IJ][a][f] = t^af_ij
   DevBuf WovooH, WooovH, t2H;
+  DevBuf t2P;        // t2P[i][n][AB] = t^ab_in (a > b), for the P(ij)-only right doubles term
   DevBuf Wop;        // packed hole-ladder operator, [O2][O2], m>n (rows), i>j (columns): W^mn_ij with
                      // the doubles' F^m_j term folded in
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
-  DevBuf WvvvoT;     // WvvvoT[j][e][a][b] = W^ab_ej
+  DevBuf WvvvoTP;    // WvvvoTP[j][e][AB] = W^ab_ej (a > b), for the right doubles term P(ij) W^ab_ej r^e_i
   DevBuf WvvvoL, WvovvL;  // WvvvoL[a][m][e][f] = W^ef_am, WvovvL[i][a][f][e] = W^ei_fa (left transform)
   // split-BF16 copies of the ladder and ring operators, made on first use in
   // that precision: right ladder, left ladder, right ring, left ring

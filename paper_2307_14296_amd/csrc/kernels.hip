@@ -146,14 +146,15 @@ __global__ __launch_bounds__(256) void k_pack_full(int nvec, int o, int v, const
 
 // packed sigma assembly with the antisymmetrizers applied on the fly:
 // out += X0 + P(ab) Xa + P(ij) Xi + P(ab)P(ij) Xai - z r (Xa, having no P(ij),
-// may hold the pairs i > j only: xa_half, layout [k][IJ][a][b]).  Doubles: one
+// may hold the pairs i > j only: xa_half, layout [k][IJ][a][b]; Xi, having no
+// P(ab), the pairs a > b only: xi_vpacked, layout [k][i][j][AB]).  Doubles: one
 // workgroup per (vector, occupied pair i > j, tile pair); the images with
 // exchanged virtual indices are read with unit stride along a into LDS.
 __global__ __launch_bounds__(256) void k_pack_sigma_t(int o, int v, const cplx* __restrict__ X0,
                                                       const cplx* __restrict__ Xa, const cplx* __restrict__ Xi,
                                                       const cplx* __restrict__ Xai, cplx* __restrict__ outd,
                                                       const cplx* __restrict__ zk, const cplx* __restrict__ rd,
-                                                      int xai_ring, int xa_half) {
+                                                      int xai_ring, int xa_half, int xi_vpacked) {
   __shared__ cplx s[PT][PT + 1];
   const i64 O2 = (i64)o * (o - 1) / 2, V2 = (i64)v * (v - 1) / 2;
   const int k = blockIdx.z, y = blockIdx.y, tid = threadIdx.x;
@@ -195,7 +196,9 @@ __global__ __launch_bounds__(256) void k_pack_sigma_t(int o, int v, const cplx* 
     if (X0) { const cplx u = X0[at(i, j, a, b)]; t.x += u.x; t.y += u.y; }
     if (Xa) { const cplx u = Xa[ah(a, b)]; t.x += u.x; t.y += u.y; }
     if (Xi) {
-      const cplx u = Xi[at(i, j, a, b)], w = Xi[at(j, i, a, b)];
+      const i64 AB = pair_index(a, b);
+      const cplx u = xi_vpacked ? Xi[(((i64)k * o + i) * o + j) * V2 + AB] : Xi[at(i, j, a, b)];
+      const cplx w = xi_vpacked ? Xi[(((i64)k * o + j) * o + i) * V2 + AB] : Xi[at(j, i, a, b)];
       t.x += u.x - w.x; t.y += u.y - w.y;
     }
     if (Xai) {
@@ -270,12 +273,12 @@ void launch_pack_full(int nvec, int o, int v, const cplx* r1, const cplx* r2, cp
 
 void launch_pack_sigma(int nvec, int o, int v, const cplx* X0, const cplx* Xa, const cplx* Xi, const cplx* Xai,
                        const cplx* S1, cplx* outs, cplx* outd, const cplx* zk, const cplx* rs, const cplx* rd,
-                       hipStream_t st, bool xai_ring, bool xa_half) {
+                       hipStream_t st, bool xai_ring, bool xa_half, bool xi_vpacked) {
   if (nvec <= 0) return;
   const i64 ov = (i64)o * v;
   hipLaunchKernelGGL(k_pack_sigma_s, dim3(grid_for((i64)nvec * ov)), dim3(256), 0, st, nvec, ov, S1, outs, zk, rs);
   hipLaunchKernelGGL(k_pack_sigma_t, perm_grid(nvec, o, v, false), dim3(256), 0, st, o, v, X0, Xa, Xi, Xai, outd, zk,
-                     rd, xai_ring ? 1 : 0, xa_half ? 1 : 0);
+                     rd, xai_ring ? 1 : 0, xa_half ? 1 : 0, xi_vpacked ? 1 : 0);
   HIPCHK(hipGetLastError());
 }
 

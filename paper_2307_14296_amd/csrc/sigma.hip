@@ -19,7 +19,8 @@
 
 namespace {
 
-SigmaAcc prepare(cclr_ctx* c, const VecSet& in) {
+// xi_vpacked: the P(ij) group only for the pairs a > b ([k][i][j][AB]; no P(ab) acts on it)
+SigmaAcc prepare(cclr_ctx* c, const VecSet& in, bool xi_vpacked) {
   const i64 o = c->o, v = c->v, k = in.n;
   SigmaAcc a;
   a.R1 = ten(in.s, {k, o, v});
@@ -28,7 +29,7 @@ SigmaAcc prepare(cclr_ctx* c, const VecSet& in) {
   // no group without a permutation operator remains outside the packed ladders (X0 stays empty)
   // P(ab) group of the pairs i > j only ([k][IJ][a][b]): no P(ij) acts on it
   a.Xa = tmp(c, {k, c->O2(), v, v});
-  a.Xi = tmp(c, {k, o, o, v, v});
+  a.Xi = xi_vpacked ? tmp(c, {k, o, o, c->V2()}) : tmp(c, {k, o, o, v, v});
   // P(ab)P(ij) group in the ring layout [k][i][a][j][b], seen through a kijab view
   a.Xai = reorder(tmp(c, {k, o, v, o, v}), "kiajb", "kijab");
   a.S1 = tmp(c, {k, o, v});
@@ -178,7 +179,7 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   SigmaWork w;
   w.mk = c->arena.mark();
   const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
-  w.a = prepare(c, in);
+  w.a = prepare(c, in, o >= 2 && v >= 2);
   SigmaAcc& a = w.a;
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
@@ -190,10 +191,13 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   contract(c, mone, Foo, "mi", a.R1, "kma", a.S1, "kia");
   // W^ma_ei read from the ring operator WR[i][a][m][e]
   contract(c, one, WR, "iame", a.R1, "kme", a.S1, "kia");
-  // r^ef_im with (i, m) unpacked and (e, f) packed: the v-pair sums below run over e > f once
+  // r^ef_im with (i, m) unpacked and (e, f) packed, and r^ea_mn on the rows m > n: the pair
+  // sums below run over each antisymmetric pair once
   const bool pairs = o >= 2 && v >= 2;
-  Ten R2v;
+  Ten R2v, R2h;
   if (pairs) {
+    R2h = tmp(c, {nv, c->O2(), v, v});
+    launch_pack_first_pair(nv, (int)o, v * v, a.R2.p, R2h.p, c->stream);
     R2v = tmp(c, {nv, o, o, c->V2()});
     launch_unpack_first_pair(nv, (int)o, c->V2(), in.d, R2v.p, c->stream);
     // 1/2 W^am_ef r^ef_im - F^m_e r^ea_im = sum_(m, e>f) (W + X)^am_ef r^ef_im (X folded into WvovvP)
@@ -201,11 +205,12 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   } else {
     contract(c, mone, Fov, "me", a.R2, "kimea", a.S1, "kia");
   }
-  contract(c, half, Wooov, "mnie", a.R2, "kmnea", a.S1, "kia");
-  // doubles
+  // 1/2 W^mn_ie r^ea_mn = sum_(m>n, e) W^mn_ie r^ea_mn
+  if (pairs) contract(c, one, ten(c->WooovH, {c->O2(), o, v}), "Pie", R2h, "kPea", a.S1, "kia");
+  // doubles (the P(ij) group Xi holds the pairs a > b only: [k][i][j][AB])
   const i64 O2 = c->O2();
   if (O2 > 0) contract(c, mone, ten(c->WovooH, {o, v, O2}), "mbP", a.R1, "kma", a.Xa, "kPab");
-  contract(c, one, ten(c->WvvvoT, {o, v, v, v}), "jeab", a.R1, "kie", a.Xi, "kijab");
+  if (pairs) contract(c, one, ten(c->WvvvoTP, {o, v, c->V2()}), "jeQ", a.R1, "kie", a.Xi, "kijQ");
   {
     // P(ab) [W^bm_fe r^e_m t^af_ij - 1/2 V^nm_fe r^ea_mn t^fb_ij] = P(ab) t^af_ij Y_bf with
     // Y_bf = W^bm_fe r^e_m - 1/2 V^nm_fe r^eb_mn, and likewise
@@ -214,18 +219,14 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
     Ten Y = tmp(c, {nv, v, v});
     // antisymmetry relabellings W^bm_fe = -W^bm_ef, V^nm_fe = V^mn_ef keep the reductions unit-stride
     contract(c, mone, Wvovv, "bmef", a.R1, "kme", Y, "kbf", false);
-    if (pairs) {
-      // -1/2 V^mn_ef r^eb_mn = -sum_(m>n, e) V^mn_ef r^eb_mn on the (m>n) rows of r
-      Ten R2h = tmp(c, {nv, c->O2(), v, v});
-      launch_pack_first_pair(nv, (int)o, v * v, a.R2.p, R2h.p, c->stream);
-      contract(c, mone, ten(c->VoovvH, {c->O2(), v, v}), "Pef", R2h, "kPeb", Y, "kbf");
-    }
+    // -1/2 V^mn_ef r^eb_mn = -sum_(m>n, e) V^mn_ef r^eb_mn on the (m>n) rows of r
+    if (pairs) contract(c, mone, ten(c->VoovvH, {c->O2(), v, v}), "Pef", R2h, "kPeb", Y, "kbf");
     if (O2 > 0) contract(c, one, ten(c->t2H, {O2, v, v}), "Paf", Y, "kbf", a.Xa, "kPab");
     Ten Z = tmp(c, {nv, o, o});
     contract(c, one, Wooov, "nmje", a.R1, "kme", Z, "knj", false);
     // 1/2 V^nm_fe r^fe_jm = sum_(m, f>e) V^nm_fe r^fe_jm
     if (pairs) contract(c, one, ten(c->VoovvP, {o, o, c->V2()}), "nmQ", R2v, "kjmQ", Z, "knj");
-    contract(c, mone, t2, "inab", Z, "knj", a.Xi, "kijab");
+    if (pairs) contract(c, mone, ten(c->t2P, {o, o, c->V2()}), "inQ", Z, "knj", a.Xi, "kijQ");
   }
   w.ring = ring_args(c, in, a.Xai, true);
   w.ladder = ladder_args(c, in, out, true);
@@ -237,7 +238,7 @@ void sigma_finish(cclr_ctx* c, SigmaWork& w, const VecSet& in, const VecSet& out
   hole_ladder(c, in, out, true);
   launch_fill(out.s, nv * o * v, cx(0.0), c->stream);
   launch_pack_sigma((int)nv, (int)o, (int)v, w.a.X0.p, w.a.Xa.p, w.a.Xi.p, w.a.Xai.p, w.a.S1.p, out.s, out.d, z, in.s,
-                    in.d, c->stream, true, true);
+                    in.d, c->stream, true, true, o >= 2 && v >= 2);
   c->arena.reset(w.mk);
 }
 
@@ -252,7 +253,7 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   const i64 o = c->o, v = c->v, nv = in.n;
   Arena::Mark mk = c->arena.mark();
   const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
-  SigmaAcc a = prepare(c, in);
+  SigmaAcc a = prepare(c, in, false);
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
