@@ -178,13 +178,11 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
   const i64 o = c->o, v = c->v, nv = in.n;
   SigmaWork w;
   w.mk = c->arena.mark();
-  const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
+  const cplx one = cx(1.0), mone = cx(-1.0);
   w.a = prepare(c, in, o >= 2 && v >= 2);
   SigmaAcc& a = w.a;
-  Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
-  Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
   Ten WR = ten(c->WR, {o, v, o, v});
   // singles
   contract(c, one, Fvv, "ae", a.R1, "kie", a.S1, "kia");
@@ -257,7 +255,7 @@ void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z)
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
-  Ten Wovoo = ten(c->Wovoo, {o, v, o, o}), Wvvvo = ten(c->Wvvvo, {v, v, v, o});
+  Ten Wovoo = ten(c->Wovoo, {o, v, o, o});
   Ten Voovv = Vblk(c, "oovv");
   Ten WL = ten(c->WL, {o, v, o, v});
   // G^e_a = -1/2 l^mn_af t^ef_mn ; G^i_m = 1/2 l^in_ef t^ef_mn  (SI, eqs. G_ea, G_mi)
