@@ -91,6 +91,10 @@ int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
  * stream after every product. */
 int cclr_dbg_gemm_trace(cclr_ctx* ctx, int enable, char* buf, long long cap);
 
+/* Run (1) or do not run (0) the ring and ladder products of FP64 right
+ * transforms on a second stream, concurrently with the other products. */
+int cclr_dbg_set_overlap(cclr_ctx* ctx, int enable);
+
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
  * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
  * the variant in use: within 2% of the fastest, the grouped tile order, then

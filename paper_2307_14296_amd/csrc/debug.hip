@@ -275,6 +275,12 @@ int cclr_dbg_gemm_trace(cclr_ctx* c, int enable, char* buf, long long cap) {
   return CCLR_OK;
 }
 
+int cclr_dbg_set_overlap(cclr_ctx* c, int enable) {
+  if (!c) return CCLR_EINVAL;
+  c->overlap = enable != 0;
+  return CCLR_OK;
+}
+
 int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {
   if (!c) return CCLR_EINVAL;
   if (enable >= 0) c->autotune = enable != 0;

@@ -72,6 +72,7 @@ void* Arena::get(size_t bytes) {
 Arena::Mark Arena::mark() const { return {cur, chunks.empty() ? 0 : used[cur]}; }
 
 void Arena::reset(Mark m) {
+  if (hold > 0) return;
   for (size_t k = m.chunk + 1; k < chunks.size(); ++k) used[k] = 0;
   if (!chunks.empty()) used[m.chunk] = m.top;
   cur = m.chunk;
@@ -605,6 +606,9 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
     launch_zgemm_variant(g, it->second, c->stream);
     return it->second;
   }
+  // nothing else may run while the variants are timed: drain the side stream too
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->side) HIPCHK(hipStreamSynchronize(c->side));
   // the timed product: the leading rows and batch entries, on a scratch output covering their index range
   GemmArgs h = g;
   h.M = tmr;

@@ -63,6 +63,9 @@ struct Arena {
   std::vector<size_t> used;
   size_t cur = 0;
   size_t chunk_bytes = size_t(256) << 20;
+  // while hold > 0, reset() keeps everything: memory handed to work queued on
+  // another stream stays untouched until that stream has been joined
+  int hold = 0;
   ~Arena();
   void* get(size_t bytes);
   struct Mark { size_t chunk, top; };
@@ -275,6 +278,12 @@ struct cclr_ctx {
   bool autotune = true;
   // kernel variant of grouped multi-context launches, per set of product shapes
   std::map<std::string, int> group_choice;
+  // the ring and ladder products of an FP64 right transform run on a second
+  // stream of default priority (`side`, created on first use) while the other
+  // products run on `stream`; joined before the result is packed
+  bool overlap = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional per-product timing of run_gemm (shape, kernel form, ms), for diagnostics
   bool gemm_trace = false;
   std::vector<std::string> gemm_trace_log;

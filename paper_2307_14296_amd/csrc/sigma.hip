@@ -174,13 +174,11 @@ void timed(cclr_ctx* c, double flops, F&& launch) {
 double gemm_flops(const GemmArgs& g) { return 8.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch; }
 }  // namespace
 
-SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
+namespace {
+// every term of the right transform except the ring and the two ladders
+void right_terms(cclr_ctx* c, const VecSet& in, SigmaAcc& a) {
   const i64 o = c->o, v = c->v, nv = in.n;
-  SigmaWork w;
-  w.mk = c->arena.mark();
   const cplx one = cx(1.0), mone = cx(-1.0);
-  w.a = prepare(c, in, o >= 2 && v >= 2);
-  SigmaAcc& a = w.a;
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
   Ten WR = ten(c->WR, {o, v, o, v});
@@ -226,7 +224,29 @@ SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
     if (pairs) contract(c, one, ten(c->VoovvP, {o, o, c->V2()}), "nmQ", R2v, "kjmQ", Z, "knj");
     if (pairs) contract(c, mone, ten(c->t2P, {o, o, c->V2()}), "inQ", Z, "knj", a.Xi, "kijQ");
   }
-  w.ring = ring_args(c, in, a.Xai, true);
+}
+
+// exchanges the context's stream with its side stream for the lifetime of the
+// object; the arena keeps what the side-stream work takes until the join
+struct SideStream {
+  cclr_ctx* c;
+  explicit SideStream(cclr_ctx* cc) : c(cc) {
+    std::swap(c->stream, c->side);
+    ++c->arena.hold;
+  }
+  ~SideStream() {
+    --c->arena.hold;
+    std::swap(c->stream, c->side);
+  }
+};
+}  // namespace
+
+SigmaWork sigma_right_begin(cclr_ctx* c, const VecSet& in, const VecSet& out) {
+  SigmaWork w;
+  w.mk = c->arena.mark();
+  w.a = prepare(c, in, c->o >= 2 && c->v >= 2);
+  right_terms(c, in, w.a);
+  w.ring = ring_args(c, in, w.a.Xai, true);
   w.ladder = ladder_args(c, in, out, true);
   return w;
 }
@@ -241,9 +261,36 @@ void sigma_finish(cclr_ctx* c, SigmaWork& w, const VecSet& in, const VecSet& out
 }
 
 void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z) {
-  SigmaWork w = sigma_right_begin(c, in, out);
-  op_gemm(c, w.ring, 2);
-  timed(c, gemm_flops(w.ladder), [&]() { op_gemm(c, w.ladder, 0); });
+  if (!(c->overlap && c->sigma_prec == CCLR_FP64)) {
+    SigmaWork w = sigma_right_begin(c, in, out);
+    op_gemm(c, w.ring, 2);
+    timed(c, gemm_flops(w.ladder), [&]() { op_gemm(c, w.ladder, 0); });
+    sigma_finish(c, w, in, out, z);
+    return;
+  }
+  // the ring and ladder products on the side stream, the other terms on the
+  // context's stream meanwhile; their buffers are taken from the arena before
+  // the other terms take theirs, and none is released before the join
+  if (!c->side) {
+    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
+  SigmaWork w;
+  w.mk = c->arena.mark();
+  w.a = prepare(c, in, c->o >= 2 && c->v >= 2);
+  HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+  HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  {
+    SideStream on_side(c);
+    w.ring = ring_args(c, in, w.a.Xai, true);
+    op_gemm(c, w.ring, 2);
+    w.ladder = ladder_args(c, in, out, true);
+    timed(c, gemm_flops(w.ladder), [&]() { op_gemm(c, w.ladder, 0); });
+    HIPCHK(hipEventRecord(c->ev_join, c->stream));
+  }
+  right_terms(c, in, w.a);
+  HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   sigma_finish(c, w, in, out, z);
 }
 
