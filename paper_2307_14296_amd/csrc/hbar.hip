@@ -187,8 +187,13 @@ void build_intermediates(cclr_ctx* c) {
     launch_pack_pairs(o * v, (int)v, wt.p, c->WvvvoTP.c(), c->stream);
   }
   // left-transform layouts with unit-stride reductions: W^ef_am as [a][m][e][f], W^ei_fa as [i][a][f][e]
-  c->WvvvoL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
-  tcopy(c, ten(c->WvvvoL, {v, o, v, v}), "amef", Wvvvo, "efam", one, false);
+  if (v >= 2) {
+    // W^ef_am as [a][m][EF] (e > f) for the left singles term 1/2 l^im_ef W^ef_am
+    Ten wl = tmp(c, {v, o, v, v});
+    tcopy(c, wl, "amef", Wvvvo, "efam", one, false);
+    c->WvvvoLP.alloc(c, sizeof(cplx) * (size_t)(v * o * c->V2()));
+    launch_pack_pairs(v * o, (int)v, wl.p, c->WvvvoLP.c(), c->stream);
+  }
   c->WvovvL.alloc(c, sizeof(cplx) * (size_t)(o * v * v * v));
   tcopy(c, ten(c->WvovvL, {o, v, v, v}), "iafe", Wvovv, "eifa", one, false);
   // pair-packed operators of the right transform's o^2 v^3 products

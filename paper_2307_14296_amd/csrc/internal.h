@@ -251,7 +251,7 @@ struct cclr_ctx {
                      // the doubles' F^m_j term folded in
   DevBuf WR, WL;     // ring operators: WR[j][b][m][e] = W^mb_ej, WL[m][e][j][b] = W^je_bm
   DevBuf WvvvoTP;    // WvvvoTP[j][e][AB] = W^ab_ej (a > b), for the right doubles term P(ij) W^ab_ej r^e_i
-  DevBuf WvvvoL, WvovvL;  // WvvvoL[a][m][e][f] = W^ef_am, WvovvL[i][a][f][e] = W^ei_fa (left transform)
+  DevBuf WvvvoLP, WvovvL;  // WvvvoLP[a][m][EF] = W^ef_am (e > f), WvovvL[i][a][f][e] = W^ei_fa (left transform)
   // split-BF16 copies of the ladder and ring operators, made on first use in
   // that precision: right ladder, left ladder, right ring, left ring
   DevBuf wsplit[4];

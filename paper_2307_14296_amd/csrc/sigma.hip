@@ -297,23 +297,39 @@ void sigma_right(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z
 void sigma_left(cclr_ctx* c, const VecSet& in, const VecSet& out, const cplx* z) {
   const i64 o = c->o, v = c->v, nv = in.n;
   Arena::Mark mk = c->arena.mark();
-  const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5);
+  const cplx one = cx(1.0), mone = cx(-1.0);
   SigmaAcc a = prepare(c, in, false);
-  Ten t2 = ten(c->t2, {o, o, v, v});
+  // l^ef_im with (e, f) packed and l^ea_mn on the rows m > n, as in the right transform
+  const bool pairs = o >= 2 && v >= 2;
+  Ten R2v, R2h;
+  if (pairs) {
+    R2v = tmp(c, {nv, o, o, c->V2()});
+    launch_unpack_first_pair(nv, (int)o, c->V2(), in.d, R2v.p, c->stream);
+    R2h = tmp(c, {nv, c->O2(), v, v});
+    launch_pack_first_pair(nv, (int)o, v * v, a.R2.p, R2h.p, c->stream);
+  }
   Ten Foo = ten(c->Foo, {o, o}), Fvv = ten(c->Fvv, {v, v}), Fov = ten(c->Fov, {o, v});
   Ten Wooov = ten(c->Wooov, {o, o, o, v}), Wvovv = ten(c->Wvovv, {v, o, v, v});
-  Ten Wovoo = ten(c->Wovoo, {o, v, o, o});
   Ten Voovv = Vblk(c, "oovv");
   Ten WL = ten(c->WL, {o, v, o, v});
   // G^e_a = -1/2 l^mn_af t^ef_mn ; G^i_m = 1/2 l^in_ef t^ef_mn  (SI, eqs. G_ea, G_mi)
   Ten Gvv = tmp(c, {nv, v, v}), Goo = tmp(c, {nv, o, o});
-  contract(c, mhalf, a.R2, "kmnfa", t2, "mnfe", Gvv, "kea", false);  // l^mn_af t^ef_mn = l^mn_fa t^fe_mn
-  contract(c, half, a.R2, "kinef", t2, "mnef", Goo, "kim", false);
+  // over the pairs once: -sum_(m>n, f) l^fa_mn t^fe_mn and sum_(n, e>f) l^ef_in t^ef_mn
+  if (pairs) {
+    contract(c, mone, R2h, "kPfa", ten(c->t2H, {c->O2(), v, v}), "Pfe", Gvv, "kea", false);
+    contract(c, one, R2v, "kinQ", ten(c->t2P, {o, o, c->V2()}), "mnQ", Goo, "kim", false);
+  } else {
+    launch_fill(Gvv.p, Gvv.size(), cx(0.0), c->stream);
+    launch_fill(Goo.p, Goo.size(), cx(0.0), c->stream);
+  }
   // singles
   contract(c, one, a.R1, "kie", Fvv, "ea", a.S1, "kia");
   contract(c, mone, a.R1, "kma", Foo, "im", a.S1, "kia");
-  contract(c, half, a.R2, "kimef", ten(c->WvvvoL, {v, o, v, v}), "amef", a.S1, "kia");  // W^ef_am as [a][m][e][f]
-  contract(c, half, a.R2, "kmnea", Wovoo, "iemn", a.S1, "kia");  // l^mn_ae = -l^mn_ea
+  if (pairs) {
+    // 1/2 l^im_ef W^ef_am over e > f; 1/2 l^mn_ae W^ie_mn = 1/2 l^ea_mn W^ie_mn over m > n
+    contract(c, one, R2v, "kimQ", ten(c->WvvvoLP, {v, o, c->V2()}), "amQ", a.S1, "kia");
+    contract(c, one, R2h, "kPea", ten(c->WovooH, {o, v, c->O2()}), "ieP", a.S1, "kia");
+  }
   contract(c, mone, Gvv, "kfe", ten(c->WvovvL, {o, v, v, v}), "iafe", a.S1, "kia");  // W^ei_fa as [i][a][f][e]
   contract(c, mone, Goo, "knm", Wooov, "mina", a.S1, "kia");
   contract(c, one, a.R1, "kme", WL, "meia", a.S1, "kia");  // W^ie_am = WL[m][e][i][a]
