@@ -771,6 +771,137 @@ __global__ __launch_bounds__(256) void k_cgemm_f32(GemmArgs g) {
       }
 }
 
+// 128x128 form of the FP32 kernel (three products, FP32 planes in LDS),
+// with the structure of the FP64 128x128 tile: eight waves of 64x32, LDS
+// double-buffered (99 KB), the next K-tile fetched into registers during the
+// tile and the fragments of the next 4-deep K step read during the MFMAs of
+// the current one.  XCD-grouped tile order.
+template <bool AK, bool BNF>
+__global__ __launch_bounds__(512, 2) void k_cgemm_f32w(GemmArgs g, int tm, int tn, int gm) {
+  constexpr int BM = 128, BN = 128, BK = 16, NT = 512, WM = 64, WN = 32, FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+  __shared__ float sA[2][3][BK][BM + 1];
+  __shared__ float sB[2][3][BK][BN + 1];
+  int mi, ni, bz;
+  tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, 1, mi, ni, bz);
+  const int m0 = mi * BM, n0 = ni * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const cplx* __restrict__ A = g.A + boff(g, bz, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bz, g.sBb, g.sBb2);
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const float sa = g.conjA ? -1.f : 1.f;
+  const double sb = g.conjB ? -1.0 : 1.0;
+  const i64 sAk = AK ? 1 : g.sAk, sBn = BNF ? 1 : g.sBn;
+  const int mA = AK ? tid / BK : tid % BM, kA = AK ? tid % BK : tid / BM;
+  const int dmA = AK ? NT / BK : 0, dkA = AK ? 0 : NT / BM;
+  const int nB = BNF ? tid % BN : tid / BK, kB = BNF ? tid / BN : tid % BK;
+  const int dnB = BNF ? 0 : NT / BK, dkB = BNF ? NT / BN : 0;
+  const cplx* __restrict__ pA = A + (i64)(m0 + mA) * g.sAm + (i64)kA * sAk;
+  const cplx* __restrict__ pB = B + (i64)kB * g.sBk + (i64)(n0 + nB) * sBn;
+  const i64 stA = (i64)dmA * g.sAm + (i64)dkA * sAk, stB = (i64)dkB * g.sBk + (i64)dnB * sBn;
+  const int kend = g.K;
+  cplx ra[LA], rb[LB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int gm = m0 + mA + r * dmA, gk = k0 + kA + r * dkA;
+      ra[r] = (gm < g.M && gk < kend) ? pA[r * stA + (i64)k0 * sAk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int gn = n0 + nB + r * dnB, gk = k0 + kB + r * dkB;
+      rb[r] = (gn < g.N && gk < kend) ? pB[r * stB + (i64)k0 * g.sBk] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int mm = mA + r * dmA, kk = kA + r * dkA;
+      sA[buf][0][kk][mm] = (float)ra[r].x;
+      sA[buf][1][kk][mm] = sa * (float)ra[r].y;
+      sA[buf][2][kk][mm] = (float)(ra[r].x + (double)sa * ra[r].y);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int nn = nB + r * dnB, kk = kB + r * dkB;
+      const double re = rb[r].x, im = sb * rb[r].y;
+      sB[buf][0][kk][nn] = (float)re;
+      sB[buf][1][kk][nn] = (float)(im - re);
+      sB[buf][2][kk][nn] = (float)(re + im);
+    }
+  };
+  float fa[2][3][FM], fb[2][3][FN];
+  auto fread = [&](int buf, int ks, int s) {
+    const int kk = ks + (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) fa[s][p][i] = sA[buf][p][kk][wm + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) fb[s][p][j] = sB[buf][p][kk][wn + j * 16 + (lane & 15)];
+  };
+  f4 k1[FM][FN], k2[FM][FN], k3[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      k1[i][j] = f4{0, 0, 0, 0};
+      k2[i][j] = f4{0, 0, 0, 0};
+      k3[i][j] = f4{0, 0, 0, 0};
+    }
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  fread(0, 0, 0);
+  for (int k0 = 0; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK);
+#pragma unroll
+    for (int q = 0; q < BK / 4; ++q) {
+      const int s = q & 1;
+      if (q + 1 < BK / 4) fread(buf, 4 * (q + 1), s ^ 1);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          // k1 = (Ar + Ai) Br, k2 = Ar (Bi - Br), k3 = Ai (Br + Bi)
+          k1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s][2][i], fb[s][0][j], k1[i][j], 0, 0, 0);
+          k2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s][0][i], fb[s][1][j], k2[i][j], 0, 0, 0);
+          k3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s][1][i], fb[s][2][j], k3[i][j], 0, 0, 0);
+        }
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    if (more) fread(buf, 0, 0);
+  }
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + f32_out_row(lane, r);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double cr = (double)k1[i][j][r] - (double)k3[i][j][r];
+          const double ci = (double)k1[i][j][r] + (double)k2[i][j][r];
+          cplx y = make_double2(g.ar * cr - g.ai * ci, g.ar * ci + g.ai * cr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            const cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
 inline unsigned grid_for(i64 total) {
   i64 g = (total + 255) / 256;
   if (g > 65536) g = 65536;
@@ -904,6 +1035,19 @@ void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   REQUIRE(prec == CCLR_FP32, CCLR_EINVAL, "low-precision GEMM: only CCLR_FP32 is available");
   const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  if (g.kchunk == 0 && g.M >= 512 && g.N >= 512) {
+    // large products: 128x128 tiles in the XCD-grouped order
+    const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128, gm = std::min(tm, kGroupM);
+    const i64 total = (i64)tm * tn * g.batch;
+    REQUIRE(total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
+    dim3 grid((unsigned)total);
+    if (ak && bn) hipLaunchKernelGGL((k_cgemm_f32w<true, true>), grid, dim3(512), 0, s, g, tm, tn, gm);
+    else if (ak) hipLaunchKernelGGL((k_cgemm_f32w<true, false>), grid, dim3(512), 0, s, g, tm, tn, gm);
+    else if (bn) hipLaunchKernelGGL((k_cgemm_f32w<false, true>), grid, dim3(512), 0, s, g, tm, tn, gm);
+    else hipLaunchKernelGGL((k_cgemm_f32w<false, false>), grid, dim3(512), 0, s, g, tm, tn, gm);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   dim3 grid((g.M + 127) / 128, (g.N + 63) / 64, g.batch);
   if (ak && bn) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, true>), grid, dim3(256), 0, s, g);
   else if (ak) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, false>), grid, dim3(256), 0, s, g);

@@ -47,7 +47,8 @@ def cfg1():
     return pb, H, t1, t2, O.CCLR(H, t1, t2)
 
 
-GEMM_CASES = [(1, 1, 1, 0, 0), (17, 33, 5, 1, 0), (130, 3, 129, 0, 1), (200, 260, 300, 1, 1), (300, 257, 1000, 0, 0)]
+GEMM_CASES = [(1, 1, 1, 0, 0), (17, 33, 5, 1, 0), (130, 3, 129, 0, 1), (200, 260, 300, 1, 1), (300, 257, 1000, 0, 0),
+              (600, 530, 70, 0, 0), (1030, 600, 200, 1, 1), (520, 700, 33, 1, 0)]
 PRECS = {"fp32": (1, 1e-5, 1e-5), "bf16x3": (2, 5e-5, 1e-4)}
 
 
