@@ -464,7 +464,7 @@ def main():
                     help="comma list of reduced precisions to run after the FP64 run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent response solves would shard across GPUs, see the design notes)", file=sys.stderr)
         sys.exit(2)
 
