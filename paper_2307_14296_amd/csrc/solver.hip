@@ -51,28 +51,67 @@ __device__ cplx block_sum(cplx v) {
   return out;
 }
 
-// partial[(a*nj + j)*kChunks + chunk] = sum over chunk of conj(X[r][xj0+j]) * Y[r][yj],  r = act[a]
+// partial[(a*nj + j)*kChunks + chunk] = sum over chunk of conj(X[r][xj0+j]) * Y[r][yj],  r = act[a].
+// One block takes kGramJ consecutive j, so each element of Y is read once for up to kGramJ vectors of X.
+constexpr int kGramJ = 4;
 __global__ __launch_bounds__(kThreads) void k_gram(VS X, int xj0, int nj, VS Y, int yj, const int* act, i64 ov, i64 nd,
                                                    cplx* partial) {
-  const int a = blockIdx.z, j = blockIdx.y, chunk = blockIdx.x;
+  const int a = blockIdx.z, j0 = blockIdx.y * kGramJ, chunk = blockIdx.x;
+  const int cnt = min(kGramJ, nj - j0);
   const int r = act[a];
-  const cplx* xs = vs_s(X, r, xj0 + j, ov);
-  const cplx* xd = vs_d(X, r, xj0 + j, nd);
+  const cplx* xs[kGramJ];
+  const cplx* xd[kGramJ];
+  for (int q = 0; q < kGramJ; ++q) {
+    const int j = xj0 + j0 + min(q, cnt - 1);
+    xs[q] = vs_s(X, r, j, ov);
+    xd[q] = vs_d(X, r, j, nd);
+  }
   const cplx* ys = vs_s(Y, r, yj, ov);
   const cplx* yd = vs_d(Y, r, yj, nd);
   const i64 n = ov + nd;
   const i64 per = (n + kChunks - 1) / kChunks;
   const i64 lo = chunk * per, hi = min(n, lo + per);
-  cplx acc = make_double2(0.0, 0.0);
+  double accr[kGramJ], acci[kGramJ];
+  for (int q = 0; q < kGramJ; ++q) accr[q] = acci[q] = 0.0;
   for (i64 e = lo + threadIdx.x; e < hi; e += kThreads) {
-    const cplx x = e < ov ? xs[e] : xd[e - ov];
-    const cplx y = e < ov ? ys[e] : yd[e - ov];
-    const cplx p = cconjmul(x, y);
-    acc.x += p.x;
-    acc.y += p.y;
+    const bool single = e < ov;
+    const cplx y = single ? ys[e] : yd[e - ov];
+#pragma unroll
+    for (int q = 0; q < kGramJ; ++q) {
+      if (q < cnt) {
+        const cplx x = single ? xs[q][e] : xd[q][e - ov];
+        const cplx p = cconjmul(x, y);
+        accr[q] += p.x;
+        acci[q] += p.y;
+      }
+    }
   }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) partial[((i64)a * nj + j) * kChunks + chunk] = acc;
+  // wave sums by lane exchange, then the four waves through LDS
+  __shared__ double ws[kThreads / 64][2 * kGramJ];
+#pragma unroll
+  for (int q = 0; q < kGramJ; ++q) {
+    for (int off = 32; off > 0; off >>= 1) {
+      accr[q] += __shfl_xor(accr[q], off, 64);
+      acci[q] += __shfl_xor(acci[q], off, 64);
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    for (int q = 0; q < kGramJ; ++q) {
+      ws[wave][2 * q] = accr[q];
+      ws[wave][2 * q + 1] = acci[q];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    const int q = threadIdx.x;
+    cplx t = make_double2(0.0, 0.0);
+    for (int w = 0; w < kThreads / 64; ++w) {
+      t.x += ws[w][2 * q];
+      t.y += ws[w][2 * q + 1];
+    }
+    partial[((i64)a * nj + j0 + q) * kChunks + chunk] = t;
+  }
 }
 
 // out[r*ld + col0 + j] = sum of the chunk partials (conjugated if cj)
@@ -330,8 +369,8 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
   // out[r*ld + col0 + j] = <X[r][xj0+j], Y[r][yj]> for active r
   auto gram = [&](VS X, int xj0, int nj, VS Y, int yj, cplx* out, int ld, int col0, int cj) {
     if (nj <= 0 || na <= 0) return;
-    hipLaunchKernelGGL(k_gram, dim3(kChunks, nj, na), dim3(kThreads), 0, st, X, xj0, nj, Y, yj, act_d, ov, nd,
-                       partial);
+    hipLaunchKernelGGL(k_gram, dim3(kChunks, (nj + kGramJ - 1) / kGramJ, na), dim3(kThreads), 0, st, X, xj0, nj, Y,
+                       yj, act_d, ov, nd, partial);
     hipLaunchKernelGGL(k_reduce, dim3(na * nj), dim3(kThreads), 0, st, partial, nj, act_d, out, ld, col0, cj);
   };
   auto lincomb = [&](VS out, int oj, VS X, int xj0, int nj, const cplx* cf, int ldc, double sign, VS Y, int yj,
@@ -619,7 +658,8 @@ int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, st
   };
   auto gram = [&](VS Xs, int xj0, int nj, VS Ys, int yj, cplx* out, int ld, int col0, int cj) {
     if (nj <= 0 || na <= 0) return;
-    hipLaunchKernelGGL(k_gram, dim3(kChunks, nj, na), dim3(kThreads), 0, st, Xs, xj0, nj, Ys, yj, act_d, ov, nd, partial);
+    hipLaunchKernelGGL(k_gram, dim3(kChunks, (nj + kGramJ - 1) / kGramJ, na), dim3(kThreads), 0, st, Xs, xj0, nj,
+                       Ys, yj, act_d, ov, nd, partial);
     hipLaunchKernelGGL(k_reduce, dim3(na * nj), dim3(kThreads), 0, st, partial, nj, act_d, out, ld, col0, cj);
   };
   auto lincomb = [&](VS out, int oj, VS Xs, int xj0, int nj, const cplx* cf, int ldc, int acc) {
