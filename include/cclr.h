@@ -150,13 +150,15 @@ int cclr_solve_ccsd(cclr_ctx* ctx, double tol, int maxiter, int nsub, cclr_c64* 
 int cclr_set_amplitudes(cclr_ctx* ctx, const cclr_c64* t1, const cclr_c64* t2);
 
 /* s = (A - z_k) r_k for k < nvec, z_k = omega[k] + i*gamma[k]  (right
- * EOM-EE sigma vector, SI eqs. sigma_sin-ee and sigma_double-ee). */
+ * EOM-EE sigma vector, SI eqs. sigma_sin-ee and sigma_double-ee).
+ * nvec = 0 returns CCLR_OK and reads or writes nothing (any pointer may
+ * be null); nvec < 0 is CCLR_EINVAL. */
 int cclr_jacobian_right(cclr_ctx* ctx, int nvec, const double* omega, const double* gamma,
                         const cclr_c64* r1, const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2);
 
 /* s = l_k (A - z_k)  (left sigma vector, SI eqs. sigma_sin-ee-left and
  * sigma_double-ee-left; the transposed transform of the Lambda and left
- * response equations). */
+ * response equations).  nvec = 0 as for cclr_jacobian_right. */
 int cclr_jacobian_left(cclr_ctx* ctx, int nvec, const double* omega, const double* gamma,
                        const cclr_c64* l1, const cclr_c64* l2, cclr_c64* s1, cclr_c64* s2);
 

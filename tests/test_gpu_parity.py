@@ -72,8 +72,9 @@ def gpu():
     return True
 
 
-# sizes: o = 2 and v = 3 edge cases, sizes that leave ragged GEMM tiles, config 1
-SIZES = [(2, 3), (3, 5), (4, 7), (5, 9)]
+# sizes: the smallest problems (one occupied pair and/or one virtual pair), sizes that leave ragged
+# GEMM tiles, config 1
+SIZES = [(2, 2), (3, 2), (2, 3), (3, 5), (4, 7), (5, 9)]
 
 
 @pytest.mark.parametrize("o,v", SIZES, ids=[f"o{o}v{v}" for o, v in SIZES])
@@ -187,6 +188,24 @@ def test_response_asymmetric_config1(cfg1):
     e = np.linalg.norm(out[0] - ref) / np.linalg.norm(ref)
     print(f"asymmetric response: rel err {e:.2e}", flush=True)
     assert e < TOL
+
+
+def test_empty_batch_is_a_no_op(gpu):
+    """Zero vectors: both transforms return success and touch no output."""
+    cc = _lib()
+    pb, Vf, f, H, t1, t2 = small_problem(3, 5)
+    g = GPUProblem(H, t1, t2)
+    try:
+        r1 = torch.zeros((0, 3, 5), dtype=torch.complex128, device="cuda")
+        r2 = torch.zeros((0, 3, 3, 5, 5), dtype=torch.complex128, device="cuda")
+        for fn in (cc.cclr_jacobian_right, cc.cclr_jacobian_left):
+            fn(g.ctx, [], [], r1, r2, torch.empty_like(r1), torch.empty_like(r2))
+        # a transform after the empty call is unaffected
+        x = vec(pb, 0)
+        out = g.right([x], [0.1 + 0.01j])[0]
+        assert rel(out, O.CCLR(H, t1, t2).right(*x, 0.1 + 0.01j)) < TOL
+    finally:
+        g.close()
 
 
 def test_error_paths(gpu):
