@@ -487,7 +487,8 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
 // the 256 compute units split the reduction into chunks that write partial
 // products to a workspace, summed in a fixed order afterwards.
 // form: the kernel that ran (FP64 variant >= 0, -1 short-reduction VALU
-// kernel, -2 split-K with the default variant, -3 reduced precision)
+// kernel, -2 split-K with the default variant, -3 reduced precision, -4
+// short-output VALU kernel)
 static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form);
 void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
@@ -517,6 +518,23 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
 static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
   form = -1;
   if (g.K <= 32 && launch_zgemm_smallk(g, c->stream)) return;
+  {
+    // at most 16 output columns: FP64 VALU rows instead of mostly empty MFMA tiles
+    GemmArgs h;
+    int kc = 0, S = 0;
+    if (skinny_plan(g, h, kc, S)) {
+      form = -4;
+      if (S == 1) {
+        launch_zgemm_skinny(h, kc, 1, nullptr, c->stream);
+        return;
+      }
+      Arena::Mark mk = c->arena.mark();
+      cplx* W = (cplx*)c->arena.get(sizeof(cplx) * (size_t)h.batch * S * h.M * (size_t)h.N);
+      launch_zgemm_skinny(h, kc, S, W, c->stream);
+      c->arena.reset(mk);
+      return;
+    }
+  }
   // inside reduced-precision transforms the remaining products run on FP32 MFMA as well
   const bool lowp = c->sigma_prec != CCLR_FP64;
   const i64 tiles = (i64)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;

@@ -1,0 +1,168 @@
+// Complex products with a short output side (at most 16 columns) on FP64
+// VALU.  The 16x16x4 MFMA tiles of the GEMM kernels are 64 or 128 columns
+// wide, so a product with 1 or 12 columns executes several times its work
+// on padding; here one thread owns one row of C and keeps all of its columns
+// in registers, so every element of the long operand is read from HBM once
+// and used for every column.  The short operand is staged through LDS in
+// K-tiles and read back as a broadcast.  Rows run along the unit-stride
+// index of the long operand and of C (the product is transposed when that
+// index is n), so the loads and stores of a wave are contiguous.  Long
+// reductions are split into chunks whose partial sums go to a workspace
+// that a second kernel sums in a fixed order.  With 20 or more columns the
+// broadcast reads of the short operand from LDS cost more than the padding
+// of the MFMA tiles, so those products stay on MFMA.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace {
+constexpr int SN_THREADS = 256;
+constexpr int SN_KT = 16;      // K values per LDS tile (and A values in flight per thread)
+constexpr int SN_MAXN = 16;
+
+__device__ __forceinline__ i64 skn_off(const GemmArgs& g, i64 bz, i64 s1, i64 s2) {
+  if (g.nb2 <= 1) return bz * s1;
+  return (bz / g.nb2) * s1 + (bz % g.nb2) * s2;
+}
+
+// C[m][n] (+)= alpha * sum_k op(A)[m][k] op(B)[k][n] for n < N <= NS, with
+// sAm = sCm = 1.  blockIdx = (row block, K chunk q, batch).  With S > 1 chunk
+// q of kc reduction indices writes its raw sums to W[(b*S + q)][m][n].
+template <int NS>
+__global__ __launch_bounds__(SN_THREADS) void k_zgemm_skinny(GemmArgs g, int kc, int S, cplx* W) {
+  __shared__ cplx sB[SN_KT][NS];
+  const i64 bz = blockIdx.z;
+  const int q = blockIdx.y;
+  const int m = blockIdx.x * SN_THREADS + threadIdx.x;
+  const bool live = m < g.M;
+  const cplx* __restrict__ A = g.A + skn_off(g, bz, g.sAb, g.sAb2) + (live ? m : 0);
+  const cplx* __restrict__ B = g.B + skn_off(g, bz, g.sBb, g.sBb2);
+  const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+  const int k0 = q * kc, k1 = min(g.K, k0 + kc);
+  double accr[NS], acci[NS];
+#pragma unroll
+  for (int n = 0; n < NS; ++n) accr[n] = acci[n] = 0.0;
+  for (int kb = k0; kb < k1; kb += SN_KT) {
+    const int kt = min(SN_KT, k1 - kb);
+    // this thread's A values of the tile, issued before the barrier so they are in flight meanwhile
+    cplx a[SN_KT];
+#pragma unroll
+    for (int kk = 0; kk < SN_KT; ++kk) {
+      a[kk] = make_double2(0.0, 0.0);
+      if (live && kk < kt) a[kk] = A[(i64)(kb + kk) * g.sAk];
+    }
+    __syncthreads();  // the previous tile of sB has been consumed
+    for (int e = threadIdx.x; e < SN_KT * NS; e += SN_THREADS) {
+      const int kk = e / NS, n = e % NS;
+      cplx x = make_double2(0.0, 0.0);
+      if (kk < kt && n < g.N) {
+        x = B[(i64)(kb + kk) * g.sBk + (i64)n * g.sBn];
+        x.y *= sb;
+      }
+      sB[kk][n] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < SN_KT; ++kk) {
+      const double ar = a[kk].x, ai = sa * a[kk].y;
+#pragma unroll
+      for (int n = 0; n < NS; ++n) {
+        const cplx b = sB[kk][n];
+        accr[n] += ar * b.x - ai * b.y;
+        acci[n] += ar * b.y + ai * b.x;
+      }
+    }
+  }
+  if (!live) return;
+  if (S > 1) {
+    cplx* w = W + ((bz * S + q) * (i64)g.M + m) * g.N;
+#pragma unroll
+    for (int n = 0; n < NS; ++n)
+      if (n < g.N) w[n] = make_double2(accr[n], acci[n]);
+    return;
+  }
+  cplx* C = g.C + skn_off(g, bz, g.sCb, g.sCb2) + m;
+#pragma unroll
+  for (int n = 0; n < NS; ++n) {
+    if (n >= g.N) break;
+    cplx y = make_double2(g.ar * accr[n] - g.ai * acci[n], g.ar * acci[n] + g.ai * accr[n]);
+    cplx* dst = C + (i64)n * g.sCn;
+    if (g.beta) {
+      const cplx o = *dst;
+      y.x += o.x;
+      y.y += o.y;
+    }
+    *dst = y;
+  }
+}
+// C = alpha * (sum of the S chunk sums in W) (+ C): one element per thread, chunks in order
+__global__ __launch_bounds__(256) void k_skinny_reduce(GemmArgs g, int S, const cplx* __restrict__ W) {
+  const i64 mn = (i64)g.M * g.N, total = mn * g.batch, stride = (i64)gridDim.x * blockDim.x;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const i64 b = e / mn, r = e % mn;
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < S; ++q) {
+      const cplx w = W[(b * S + q) * mn + r];
+      sr += w.x;
+      si += w.y;
+    }
+    const i64 m = r / g.N, n = r % g.N;
+    cplx y = make_double2(g.ar * sr - g.ai * si, g.ar * si + g.ai * sr);
+    cplx* dst = g.C + skn_off(g, b, g.sCb, g.sCb2) + m * g.sCm + n * g.sCn;
+    if (g.beta) {
+      const cplx o = *dst;
+      y.x += o.x;
+      y.y += o.y;
+    }
+    *dst = y;
+  }
+}
+}  // namespace
+
+bool skinny_plan(const GemmArgs& g0, GemmArgs& g, int& kc, int& S) {
+  if (g0.kchunk > 0 || g0.M <= 0 || g0.N <= 0 || g0.K <= 0 || g0.batch <= 0) return false;
+  if (g0.N <= SN_MAXN && g0.M >= 64 && g0.sAm == 1 && g0.sCm == 1) {
+    g = g0;
+  } else if (g0.M <= SN_MAXN && g0.N >= 64 && g0.sBn == 1 && g0.sCn == 1) {
+    // C^T = B^T A^T: rows along n
+    g = g0;
+    g.M = g0.N; g.N = g0.M;
+    g.A = g0.B; g.sAb = g0.sBb; g.sAb2 = g0.sBb2; g.sAm = g0.sBn; g.sAk = g0.sBk; g.conjA = g0.conjB;
+    g.B = g0.A; g.sBb = g0.sAb; g.sBb2 = g0.sAb2; g.sBk = g0.sAk; g.sBn = g0.sAm; g.conjB = g0.conjA;
+    g.sCm = g0.sCn; g.sCn = g0.sCm;
+  } else {
+    return false;
+  }
+  const i64 rb = (g.M + SN_THREADS - 1) / SN_THREADS;
+  if (rb >= (1ll << 31) || g.batch >= 65536) return false;
+  // enough workgroups to keep every CU streaming: split the reduction when the rows alone give too few
+  i64 s = 1;
+  const i64 blocks = rb * g.batch;
+  if (blocks < 2048 && g.K >= 8 * SN_KT)
+    s = std::min<i64>((3072 + blocks - 1) / blocks, g.K / (4 * SN_KT));
+  // workspace of the partial sums at most 256 MB
+  s = std::min<i64>(s, std::max<i64>(1, (i64(1) << 28) / ((i64)sizeof(cplx) * g.batch * g.M * g.N)));
+  s = std::max<i64>(s, 1);
+  i64 c = (g.K + s - 1) / s;
+  c = (c + SN_KT - 1) / SN_KT * SN_KT;
+  s = (g.K + c - 1) / c;
+  if (s >= 65536) return false;
+  kc = (int)c;
+  S = (int)s;
+  return true;
+}
+
+void launch_zgemm_skinny(const GemmArgs& g, int kc, int S, cplx* W, hipStream_t s) {
+  REQUIRE(g.N >= 1 && g.N <= SN_MAXN && g.sAm == 1 && g.sCm == 1 && S >= 1 && (S == 1 || W != nullptr) &&
+              (i64)kc * S >= g.K,
+          CCLR_EINVAL, "skinny product: arguments outside the kernel's contract");
+  const dim3 grid((unsigned)((g.M + SN_THREADS - 1) / SN_THREADS), (unsigned)S, (unsigned)g.batch);
+  if (g.N <= 8) hipLaunchKernelGGL(k_zgemm_skinny<8>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
+  else hipLaunchKernelGGL(k_zgemm_skinny<16>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
+  HIPCHK(hipGetLastError());
+  if (S == 1) return;
+  const i64 total = (i64)g.batch * g.M * g.N;
+  const unsigned rgrid = (unsigned)std::min<i64>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_skinny_reduce, dim3(rgrid), dim3(256), 0, s, g, S, W);
+  HIPCHK(hipGetLastError());
+}

@@ -156,6 +156,11 @@ void launch_cgemm_bf16x3(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm,
 // products with K <= 32 on the vector ALU (returns false if the form does not apply)
 bool launch_zgemm_smallk(const GemmArgs& g, hipStream_t s);
 // C[b][m][n] = (beta ? C : 0) + alpha * sum_s W[b][s][m][n]
+// products with at most 16 output columns (after transposing, if the unit-stride output index is n):
+// skinny_plan fills g (possibly the transposed product), the chunk length kc and the chunk count S,
+// or returns false; S > 1 needs a workspace W of batch*S*M*N elements (the launch also sums it into C)
+bool skinny_plan(const GemmArgs& g0, GemmArgs& g, int& kc, int& S);
+void launch_zgemm_skinny(const GemmArgs& g, int kc, int S, cplx* W, hipStream_t s);
 void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i64 sCb, i64 sCm, i64 sCn, double ar,
                           double ai, int beta, hipStream_t s);
 // GEMM with automatic K splitting when the output has too few tiles to fill the GPU

@@ -140,7 +140,11 @@ def test_zgemm_grouped_persistent_launch(gpu, variant):
 # along K), short reductions, split-K and plain MFMA products
 DISPATCH_CASES = [(20, 300, 5000, 1), (300, 20, 700, 3), (3, 1000, 700, 2), (1, 240, 4000, 5), (40, 16, 100000, 1),
                   (4000, 12, 4000, 1), (33, 2000, 900, 1), (200, 200, 20, 7), (150, 140, 30000, 2),
-                  (500, 300, 260, 2)]
+                  (500, 300, 260, 2),
+                  # at most 16 output columns (short-output kernel, direct and transposed, split and whole
+                  # reductions, ragged row blocks and K chunks); 17 and more stay on MFMA
+                  (16, 300, 2000, 3), (300, 16, 2000, 2), (260, 9, 5000, 4), (5000, 3, 40, 3), (70, 1, 129, 2),
+                  (24, 700, 3000, 2), (130, 17, 129, 2)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", DISPATCH_CASES)
