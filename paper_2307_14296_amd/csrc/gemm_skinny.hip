@@ -1,6 +1,6 @@
 // Complex products with a short output side (at most 16 columns) on FP64
-// VALU.  The 16x16x4 MFMA tiles of the GEMM kernels are 64 or 128 columns
-// wide, so a product with 1 or 12 columns executes several times its work
+// VALU.  The MFMA tiles of the GEMM kernels are 64 or 128 columns wide, so
+// a product with 1 or 12 columns executes several times its work
 // on padding; here one thread owns one row of C and keeps all of its columns
 // in registers, so every element of the long operand is read from HBM once
 // and used for every column.  The short operand is staged through LDS in
@@ -8,9 +8,9 @@
 // index of the long operand and of C (the product is transposed when that
 // index is n), so the loads and stores of a wave are contiguous.  Long
 // reductions are split into chunks whose partial sums go to a workspace
-// that a second kernel sums in a fixed order.  With 20 or more columns the
-// broadcast reads of the short operand from LDS cost more than the padding
-// of the MFMA tiles, so those products stay on MFMA.
+// that a second kernel sums in a fixed order.  At 20 columns the broadcast
+// reads of the short operand from LDS already cost more than the padding of
+// the MFMA tiles (measured), so products wider than 16 stay on MFMA.
 #include <algorithm>
 
 #include "internal.h"
