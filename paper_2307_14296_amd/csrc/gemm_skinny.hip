@@ -157,7 +157,12 @@ void launch_zgemm_skinny(const GemmArgs& g, int kc, int S, cplx* W, hipStream_t 
               (i64)kc * S >= g.K,
           CCLR_EINVAL, "skinny product: arguments outside the kernel's contract");
   const dim3 grid((unsigned)((g.M + SN_THREADS - 1) / SN_THREADS), (unsigned)S, (unsigned)g.batch);
-  if (g.N <= 8) hipLaunchKernelGGL(k_zgemm_skinny<8>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
+  // the column count rounded up to an instantiated width (the padding columns cost LDS reads and FMAs)
+  if (g.N <= 1) hipLaunchKernelGGL(k_zgemm_skinny<1>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
+  else if (g.N <= 2) hipLaunchKernelGGL(k_zgemm_skinny<2>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
+  else if (g.N <= 4) hipLaunchKernelGGL(k_zgemm_skinny<4>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
+  else if (g.N <= 8) hipLaunchKernelGGL(k_zgemm_skinny<8>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
+  else if (g.N <= 12) hipLaunchKernelGGL(k_zgemm_skinny<12>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
   else hipLaunchKernelGGL(k_zgemm_skinny<16>, grid, dim3(SN_THREADS), 0, s, g, kc, S, W);
   HIPCHK(hipGetLastError());
   if (S == 1) return;

@@ -144,6 +144,7 @@ DISPATCH_CASES = [(20, 300, 5000, 1), (300, 20, 700, 3), (3, 1000, 700, 2), (1, 
                   # at most 16 output columns (short-output kernel, direct and transposed, split and whole
                   # reductions, ragged row blocks and K chunks); 17 and more stay on MFMA
                   (16, 300, 2000, 3), (300, 16, 2000, 2), (260, 9, 5000, 4), (5000, 3, 40, 3), (70, 1, 129, 2),
+                  (2, 500, 300, 2), (300, 6, 1000, 1),
                   (24, 700, 3000, 2), (130, 17, 129, 2)]
 
 
