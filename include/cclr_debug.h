@@ -38,9 +38,10 @@ int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N,
                              const cclr_c64* const* A, const cclr_c64* const* B, int btrans, cclr_c64* const* C);
 
 /* The same product (device pointers, the context's stream) through the
- * context's GEMM dispatch: the short-reduction vector-ALU kernel, split-K,
- * or the autotuned MFMA kernels, chosen by shape as for the contractions of
- * a transform. */
+ * context's GEMM dispatch: the short-reduction vector-ALU kernel, the
+ * short-output vector-ALU kernel (at most 16 columns), split-K, or the
+ * autotuned MFMA kernels, chosen by shape as for the contractions of a
+ * transform. */
 int cclr_dbg_run_gemm(cclr_ctx* ctx, int M, int N, int K, int batch, const cclr_c64* A, long long sAb, long long sAm,
                       long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
                       int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double alpha_re,
@@ -86,9 +87,9 @@ int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
 /* Per-product timing of the contraction engine's GEMMs: writes up to cap
  * bytes of the record so far, one line per product: "MxNxK bB sA(m,k)
  * sB(k,n) form F ms TFLOP/s" (F: FP64 variant >= 0, -1 short-reduction VALU
- * kernel, -2 split-K, -3 reduced precision); then, for enable >= 0, clears
- * the record and switches timing on (1) or off (0).  Timing synchronizes the
- * stream after every product. */
+ * kernel, -2 split-K, -3 reduced precision, -4 short-output VALU kernel);
+ * then, for enable >= 0, clears the record and switches timing on (1) or
+ * off (0).  Timing synchronizes the stream after every product. */
 int cclr_dbg_gemm_trace(cclr_ctx* ctx, int enable, char* buf, long long cap);
 
 /* Run (1) or do not run (0) the ring and ladder products of FP64 right
