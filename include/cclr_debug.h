@@ -96,6 +96,18 @@ int cclr_dbg_gemm_trace(cclr_ctx* ctx, int enable, char* buf, long long cap);
  * transforms on a second stream, concurrently with the other products. */
 int cclr_dbg_set_overlap(cclr_ctx* ctx, int enable);
 
+/* Size-dependent blocking, for tests of the paths that large problems take
+ * (0 restores the natural choice):
+ *   wp_block  > 0: the packed W^ef_ab build of later cclr_set_amplitudes calls
+ *              forms the term -P(ef) t^e_m V^mf_ab in column blocks of wp_block
+ *              AB pairs (naturally at most 2 GiB of temporary per block, so
+ *              only v >= 129 takes more than one block);
+ *   rhs_group > 0: lockstep solves and Hessian products take at most
+ *              rhs_group right-hand sides per group (naturally as many as fit
+ *              in free device memory under the context's cap).
+ * Negative values are CCLR_EINVAL. */
+int cclr_dbg_set_blocking(cclr_ctx* ctx, long long wp_block, int rhs_group);
+
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
  * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
  * the variant in use: within 2% of the fastest, the grouped tile order, then

@@ -281,6 +281,13 @@ int cclr_dbg_set_overlap(cclr_ctx* c, int enable) {
   return CCLR_OK;
 }
 
+int cclr_dbg_set_blocking(cclr_ctx* c, long long wp_block, int rhs_group) {
+  if (!c || wp_block < 0 || rhs_group < 0) return CCLR_EINVAL;
+  c->dbg_wp_block = wp_block;
+  c->dbg_rhs_group = rhs_group;
+  return CCLR_OK;
+}
+
 int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {
   if (!c) return CCLR_EINVAL;
   if (enable >= 0) c->autotune = enable != 0;

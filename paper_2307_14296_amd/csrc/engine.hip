@@ -102,7 +102,8 @@ int fit_vectors(cclr_ctx* c, double bytes_per_vec, int n) {
     budget = std::min(budget, left);
   }
   const double k = budget / std::max(bytes_per_vec, 1.0);
-  return (int)std::max(1.0, std::min((double)n, std::floor(k)));
+  const int fit = (int)std::max(1.0, std::min((double)n, std::floor(k)));
+  return c->dbg_rhs_group > 0 ? std::min(fit, c->dbg_rhs_group) : fit;
 }
 
 // ------------------------------------------------------------------ views

@@ -110,7 +110,8 @@ void build_intermediates(cclr_ctx* c) {
     // - P(ef) t^e_m V^mf_ab: Y[e][f][AB] = t^e_m V^mf_ab over column blocks of AB
     cplx* P = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(o * v * V2));  // P[m][f][AB] = V^mf_ab
     launch_pack_pairs(o * v, (int)v, c->Vovvv.c(), P, c->stream);
-    const i64 nc = std::max<i64>(1, std::min<i64>(V2, (i64)(size_t(1) << 27) / (v * v)));  // Y block <= 2 GiB
+    i64 nc = std::max<i64>(1, std::min<i64>(V2, (i64)(size_t(1) << 27) / (v * v)));  // Y block <= 2 GiB
+    if (c->dbg_wp_block > 0) nc = std::min<i64>(V2, c->dbg_wp_block);
     Ten Y = tmp(c, {v, v, nc});
     for (i64 c0 = 0; c0 < V2; c0 += nc) {
       const i64 n = std::min(nc, V2 - c0);

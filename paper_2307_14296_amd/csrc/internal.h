@@ -292,6 +292,11 @@ struct cclr_ctx {
   // optional per-product timing of run_gemm (shape, kernel form, ms), for diagnostics
   bool gemm_trace = false;
   std::vector<std::string> gemm_trace_log;
+  // test overrides of size-dependent blocking (0 = natural): the column block
+  // of the packed W^ef_ab build (AB pairs per block) and the number of
+  // right-hand sides a memory-bounded group may hold
+  i64 dbg_wp_block = 0;
+  int dbg_rhs_group = 0;
   // optional timing of the particle-particle ladder GEMM launches
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

@@ -18,7 +18,7 @@ import pytest
 import torch
 
 from gen import synth as s
-from helpers import config_problem, rel, vec
+from helpers import assert_alpha, assert_blocks, config_problem, vec
 from oracle import cclr_ref as O
 
 pytestmark = pytest.mark.gpu
@@ -56,9 +56,8 @@ def test_sigma_o10v80(cfg2):
         s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
         fn(ctx, [z.real for z in zs], [z.imag for z in zs], r1, r2, s1, s2)
         for k, (x, z) in enumerate(zip(xs, zs)):
-            e = rel((s1[k].cpu().numpy(), s2[k].cpu().numpy()), side(*x, z))
-            print(f"o10v80 {fn.__name__} z={z}: rel err {e:.2e}", flush=True)
-            assert e < 1e-10
+            assert_blocks((s1[k].cpu().numpy(), s2[k].cpu().numpy()), side(*x, z), 1e-10,
+                          f"o10v80 {fn.__name__} z={z}")
 
 
 def test_response_o10v80_vs_golden(cfg2):
@@ -72,9 +71,8 @@ def test_response_o10v80_vs_golden(cfg2):
         z = complex(zkey)
         g = np.array([[complex(a, b) for a, b in row] for row in vals])
         rc, out, info = cc.cclr_response_function(ctx, Xs, [z.real], [z.imag])
-        e = np.linalg.norm(out[0] - g) / np.linalg.norm(g)
-        print(f"o10v80 response z={z}: rel err {e:.2e}, iters {info.iters}", flush=True)
-        assert rc == 0 and e < 1e-10
+        assert rc == 0, info.as_dict()
+        assert_alpha(out[0], g, 1e-10, f"o10v80 response z={z} ({info.iters} iterations)")
 
 
 @pytest.fixture(scope="module")
