@@ -579,6 +579,77 @@ class CCLR:
                 out[p, q] = 0.5 * (h(p, q, z) + np.conj(h(p, q, -z.conjugate())))
         return out
 
+    def response_derivative(self, Xs, z, dXs=None, dH=None, method="dense"):
+        """Exact directional derivative of response(Xs, z) along changes dXs of
+        the perturbation matrices (list like Xs, or None) and dH of the
+        Hamiltonian (a Hamiltonian holding the change of f and of the canonical
+        integral blocks, or None), with the amplitudes t held fixed.
+
+        At fixed t every Hamiltonian-dependent piece of the response function
+        is linear in the Hamiltonian: the Hbar intermediates, the Jacobian
+        A (Table 1), eta^0 and the Hessian F; xi^X and eta^X are linear in X,
+        and eta^X and F are affine in lambda.  With the inverse rule
+        d(M^-1) = -M^-1 dM M^-1 the changes follow exactly (no difference
+        quotients):
+          d lambda:  d lambda A = -(eta^0(dH) + lambda A(dH))   (eq. Lambda),
+          d t^X(w):  (A - w) d t^X = -(xi(dX) + A(dH) t^X(w))   (eq. LR response equation_cpp),
+          d eta^X  = eta(dX; lambda) + [eta(X; d lambda) - eta(X; 0)],
+          d (F x)  = F(dH; lambda) x + [F(d lambda) - F(0)] x + F d x,
+        and d<<X;Y>> = 1/2 [dg(z) + conj dg(-z*)] for the g of response().
+        Returns the (nx, nx) array of d<<X_p; X_q>>_z."""
+        if self.lam is None:
+            self.solve_lambda(method)
+        z = complex(z)
+        o, v = self.o, self.v
+        nx = len(Xs)
+        add = lambda a, b: (a[0] + b[0], a[1] + b[1])  # noqa: E731
+        sub = lambda a, b: (a[0] - b[0], a[1] - b[1])  # noqa: E731
+        zero = (np.zeros((o, v), dtype=np.complex128), np.zeros((o, o, v, v), dtype=np.complex128))
+        t1, t2 = self.t1, self.t2
+        if dH is not None:
+            dcc = CCLR(dH, t1, t2)  # Hbar of the change (linear in H at fixed t)
+            dA = lambda x: sigma_right(dH, dcc.hb, t1, t2, *x)  # noqa: E731
+            rhs = add(eta0(dH, dcc.hb), sigma_left(dH, dcc.hb, t1, t2, *self.lam))
+            dlam = self.solve("left", rhs, 0.0, method)
+        else:
+            dA, dlam = None, zero
+        dX = dXs if dXs is not None else [np.zeros_like(X) for X in Xs]
+        freqs = {}
+        for w in (z, -z, z.conjugate(), -z.conjugate()):
+            freqs.setdefault(w, None)
+        xis = [self.xi(X) for X in Xs]
+        dxis = [self.xi(X) for X in dX]
+        etas = [self.eta(X) for X in Xs]
+        deta = [add(self.eta(dX[p]), sub(eta(self.H, Xs[p], t1, t2, *dlam), eta(self.H, Xs[p], t1, t2, *zero)))
+                for p in range(nx)]
+        tX = {w: [self.solve("right", x, w, method) for x in xis] for w in freqs}
+        dtX = {}
+        for w in freqs:
+            dtX[w] = []
+            for p in range(nx):
+                r = dxis[p] if dA is None else add(dxis[p], dA(tX[w][p]))
+                dtX[w].append(self.solve("right", r, w, method))
+        tFx = {w: [self.tF(t) for t in tX[w]] for w in freqs}
+
+        def dF(x, dx):
+            out = self.tF(dx)
+            out = add(out, sub(tF(self.H, self.hb, t1, t2, *dlam, *x), tF(self.H, self.hb, t1, t2, *zero, *x)))
+            if dH is not None:
+                out = add(out, tF(dH, dcc.hb, t1, t2, *self.lam, *x))
+            return out
+
+        dtFx = {w: [dF(tX[w][p], dtX[w][p]) for p in range(nx)] for w in freqs}
+
+        def dg(p, q, w):
+            return (dot(deta[p], tX[w][q]) + dot(etas[p], dtX[w][q]) + dot(deta[q], tX[-w][p])
+                    + dot(etas[q], dtX[-w][p]) + dot(dtFx[-w][p], tX[w][q]) + dot(tFx[-w][p], dtX[w][q]))
+
+        out = np.empty((nx, nx), dtype=np.complex128)
+        for p in range(nx):
+            for q in range(nx):
+                out[p, q] = 0.5 * (dg(p, q, z) + np.conj(dg(p, q, -z.conjugate())))
+        return out
+
     def response(self, Xs, z, method="dense"):
         """<<X_p; X_q>>_z for all pairs, z = w + i*gamma (complex).
 

@@ -333,3 +333,89 @@ def test_cholesky_integrals_vs_mulliken_hamiltonian():
     M1 = sp.hamiltonian(H.f, V)
     M2 = B.hamiltonian_mulliken(sp, h, eri)
     assert np.abs(M1 - M2).max() <= 1e-14 * np.abs(M1).max()
+
+
+# ----------------------------------------- exact derivative of the response function
+def _symmetric_change(o, v, rng):
+    """Random change of (f, <pq||rs>) that keeps their symmetries (f
+    Hermitian; <pq||rs> antisymmetric in each pair and equal to conj <rs||pq>),
+    as a Hamiltonian."""
+    n = o + v
+    cr = lambda *sh: rng.normal(size=sh) + 1j * rng.normal(size=sh)  # noqa: E731
+    D = cr(n, n, n, n)
+    D = D - D.transpose(1, 0, 2, 3)
+    D = D - D.transpose(0, 1, 3, 2)
+    D = 0.5 * (D + D.conj().transpose(2, 3, 0, 1))
+    F = cr(n, n)
+    F = F + F.conj().T
+    return O.Hamiltonian(o, v, F / np.linalg.norm(F), blocks_from_full(D / np.linalg.norm(D), o))
+
+
+@pytest.mark.parametrize("z", [0.3 + 0.02j, 0.0, -0.2 + 0.05j])
+def test_response_derivative_vs_difference_quotients(z):
+    """response_derivative along a change of the perturbations and of the
+    Hamiltonian (t fixed) against central differences of response() at steps
+    h and h/2, Richardson-extrapolated (error O(h^4))."""
+    pb, inst, H, t1, t2 = config_problem(3, 5, 4)
+    cc = O.CCLR(H, t1, t2)
+    Xs = [s.dipole(pb, 0).numpy(), s.magnetic_like(pb, 0).numpy()]
+    rng = np.random.default_rng(11)
+    dX = [rng.normal(size=X.shape) + 1j * rng.normal(size=X.shape) for X in Xs]
+    dH = _symmetric_change(3, 5, rng)
+    exact = cc.response_derivative(Xs, z, dX, dH)
+
+    def at(h):
+        Hh = O.Hamiltonian(3, 5, H.f + h * dH.f, {k: H.blocks[k] + h * dH.blocks[k] for k in H.blocks})
+        return O.CCLR(Hh, t1, t2).response([X + h * d for X, d in zip(Xs, dX)], z)
+
+    h = 2e-3
+    d1 = (at(h) - at(-h)) / (2 * h)
+    d2 = (at(h / 2) - at(-h / 2)) / h
+    fd = (4 * d2 - d1) / 3
+    err = np.abs(exact - fd).max() / np.abs(exact).max()
+    print(f"z={z}: exact derivative vs Richardson differences {err:.2e}")
+    assert err < 1e-8
+
+
+def test_response_derivative_in_x_is_the_bilinear_expansion():
+    """<<X;Y>> is real-bilinear in (X, Y), so its derivative along dX equals
+    <<dX_p; X_q>> + <<X_p; dX_q>>, read off one response() call with the
+    operators [X, dX] (exact, no step)."""
+    pb, inst, H, t1, t2 = config_problem(3, 5, 4)
+    cc = O.CCLR(H, t1, t2)
+    Xs = [s.dipole(pb, k).numpy() for k in range(2)]
+    rng = np.random.default_rng(5)
+    dX = [rng.normal(size=X.shape) + 1j * rng.normal(size=X.shape) for X in Xs]
+    for z in (0.25 + 0.01j, 0.0):
+        exact = cc.response_derivative(Xs, z, dX, None)
+        R = cc.response(Xs + dX, z)
+        bil = R[2:, :2] + R[:2, 2:]
+        assert np.abs(exact - bil).max() <= 1e-12 * np.abs(bil).max()
+
+
+def test_response_derivative_mutation_is_caught():
+    """Dropping the lambda change from the derivative (a plausible mistake)
+    is visible against the difference quotients."""
+    pb, inst, H, t1, t2 = config_problem(3, 5, 4)
+    cc = O.CCLR(H, t1, t2)
+    Xs = [s.dipole(pb, 0).numpy()]
+    dH = _symmetric_change(3, 5, np.random.default_rng(1))
+    z = 0.3 + 0.02j
+    cc.solve_lambda("dense")
+    exact = cc.response_derivative(Xs, z, None, dH)
+    orig = O.CCLR.solve
+    calls = []
+
+    def no_dlam(self, side, rhs, w, method="dense", **kw):
+        calls.append(side)
+        if side == "left" and len(calls) == 1 and self is cc:
+            return tuple(np.zeros_like(x) for x in rhs)
+        return orig(self, side, rhs, w, method, **kw)
+
+    O.CCLR.solve = no_dlam
+    try:
+        wrong = cc.response_derivative(Xs, z, None, dH)
+    finally:
+        O.CCLR.solve = orig
+    assert calls[0] == "left"   # the first solve is the lambda change
+    assert np.abs(wrong - exact).max() > 1e-6 * np.abs(exact).max()
