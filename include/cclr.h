@@ -156,6 +156,23 @@ int cclr_set_amplitudes(cclr_ctx* ctx, const cclr_c64* t1, const cclr_c64* t2);
 int cclr_jacobian_right(cclr_ctx* ctx, int nvec, const double* omega, const double* gamma,
                         const cclr_c64* r1, const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform and arguments as cclr_jacobian_right, with every temporary taken
+ * from a fixed 256 MiB work space that the library holds on each GPU it runs
+ * on until the process ends.  The call makes no hipMalloc or hipFree and
+ * starts no GEMM timing run (a product shape not yet timed in this context
+ * uses the untimed kernel choice).  FP64 transforms only (CCLR_EINVAL when a
+ * test hook forces another precision).  Sizes whose temporaries do not fit
+ * are rejected with CCLR_ENOMEM and nothing is written; about six full
+ * doubles tensors (16*o*o*v*v bytes each) per vector and three per call must
+ * fit, e.g. four vectors at o=10, v=80.  Every call on one GPU uses that GPU's one work
+ * space, which keeps the last call's contents: calls overlapping in time on
+ * one GPU would race, so the library serializes them (a second host thread
+ * waits).  The call returns after its stream has drained. */
+int cclr_jacobian_right_noalloc(cclr_ctx* ctx, int nvec, const double* omega, const double* gamma,
+                                const cclr_c64* r1, const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2);
+
 /* s = l_k (A - z_k)  (left sigma vector, SI eqs. sigma_sin-ee-left and
  * sigma_double-ee-left; the transposed transform of the Lambda and left
  * response equations).  nvec = 0 as for cclr_jacobian_right. */

@@ -108,6 +108,10 @@ int cclr_dbg_set_overlap(cclr_ctx* ctx, int enable);
  * Negative values are CCLR_EINVAL. */
 int cclr_dbg_set_blocking(cclr_ctx* ctx, long long wp_block, int rhs_group);
 
+/* Bytes of the fixed work space that the context's last
+ * cclr_jacobian_right_noalloc call took at most (0 before the first). */
+int cclr_dbg_fixed_ws_peak(const cclr_ctx* ctx, long long* bytes);
+
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
  * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
  * the variant in use: within 2% of the fastest, the grouped tile order, then

@@ -26,7 +26,7 @@ CCLR_RIGHT, CCLR_LEFT = 0, 1
 EXPORTED = (
     "cclr_default_options", "cclr_create", "cclr_destroy", "cclr_set_hamiltonian", "cclr_set_hamiltonian_cholesky",
     "cclr_set_amplitudes", "cclr_ccsd_residual", "cclr_solve_ccsd",
-    "cclr_jacobian_right", "cclr_jacobian_left", "cclr_jacobian_right_multi", "cclr_solve_damped", "cclr_eom_ee", "cclr_solve_lambda", "cclr_get_lambda",
+    "cclr_jacobian_right", "cclr_jacobian_right_noalloc", "cclr_jacobian_left", "cclr_jacobian_right_multi", "cclr_solve_damped", "cclr_eom_ee", "cclr_solve_lambda", "cclr_get_lambda",
     "cclr_response_function", "cclr_response_function_ci", "cclr_response_function_asym", "cclr_response_backward",
     "cclr_last_error",
 )
@@ -72,6 +72,7 @@ def lib():
     L.cclr_ccsd_residual.argtypes = [P, P, P, P, P, P]
     L.cclr_solve_ccsd.argtypes = [P, ctypes.c_double, I, I, P, P, P, ctypes.POINTER(cclr_solve_info)]
     L.cclr_jacobian_right.argtypes = [P, I, D, D, P, P, P, P]
+    L.cclr_jacobian_right_noalloc.argtypes = [P, I, D, D, P, P, P, P]
     L.cclr_jacobian_left.argtypes = [P, I, D, D, P, P, P, P]
     PP = ctypes.POINTER(P)
     L.cclr_jacobian_right_multi.argtypes = [I, PP, ctypes.POINTER(I), PP, PP, PP, PP, PP, PP]
@@ -187,6 +188,12 @@ def cclr_jacobian_right(ctx, omega, gamma, r1, r2, s1, s2):
     n = len(omega)
     return _check(ctx, lib().cclr_jacobian_right(ctx, n, _dbl(omega), _dbl(gamma), _ptr(r1, "r1"), _ptr(r2, "r2"),
                                                  _ptr(s1, "s1"), _ptr(s2, "s2")))
+
+
+def cclr_jacobian_right_noalloc(ctx, omega, gamma, r1, r2, s1, s2):
+    n = len(omega)
+    return _check(ctx, lib().cclr_jacobian_right_noalloc(ctx, n, _dbl(omega), _dbl(gamma), _ptr(r1, "r1"),
+                                                         _ptr(r2, "r2"), _ptr(s1, "s1"), _ptr(s2, "s2")))
 
 
 def cclr_jacobian_left(ctx, omega, gamma, l1, l2, s1, s2):

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 
 #include "internal.h"
 
@@ -17,6 +18,37 @@ VecSet packed_buf(cclr_ctx* c, int n) {
 }
 
 static thread_local std::string g_create_error;
+
+// The library's fixed work space, for cclr_jacobian_right_noalloc: a file-scope
+// device array that every GPU the library runs on holds until the process
+// ends.  In host code `scratch` names a host-side stand-in, not a device
+// address, so the kernels only ever see the address hipGetSymbolAddress gives
+// for the current device, looked up once per device when a context is created.
+constexpr size_t kFixedWsBytes = size_t(256) << 20;
+static __device__ __align__(256) char scratch[kFixedWsBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_ws_mutex;                 // guards g_ws_ptr
+void* g_ws_ptr[kMaxDevices] = {};      // this device's address of `scratch`
+std::mutex g_ws_busy[kMaxDevices];     // one no-alloc call per device at a time
+
+// the device's address of the work space (device current); called from cclr_create
+void* fixed_ws_address(int dev) {
+  REQUIRE(dev >= 0 && dev < kMaxDevices, CCLR_EHIP, "device index out of range for the fixed work space");
+  std::lock_guard<std::mutex> lk(g_ws_mutex);
+  if (!g_ws_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw CclrError(CCLR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_ws_ptr[dev] = p;
+  }
+  return g_ws_ptr[dev];
+}
+}  // namespace
 
 namespace {
 template <class F>
@@ -160,6 +192,12 @@ int cclr_create(int o, int v, const cclr_options* opt, cclr_ctx** out) {
       throw CclrError(CCLR_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
     c->arena.ctx = c;
+    try {
+      c->fixed_ws = fixed_ws_address(c->device);
+    } catch (...) {
+      delete c;
+      throw;
+    }
     *out = c;
     return CCLR_OK;
   });
@@ -304,6 +342,53 @@ int cclr_jacobian_right(cclr_ctx* c, int nvec, const double* omega, const double
                         const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2) {
   if (!c) return CCLR_EINVAL;
   return jacobian(c, CCLR_RIGHT, nvec, omega, gamma, r1, r2, s1, s2);
+}
+
+int cclr_jacobian_right_noalloc(cclr_ctx* c, int nvec, const double* omega, const double* gamma,
+                                const cclr_c64* r1, const cclr_c64* r2, cclr_c64* s1, cclr_c64* s2) {
+  if (!c) return CCLR_EINVAL;
+  return guarded(c, [&]() -> int {
+    require_t(c);
+    check_freqs(nvec, omega, gamma);
+    if (nvec == 0) return CCLR_OK;
+    REQUIRE(c->sigma_prec == CCLR_FP64, CCLR_EINVAL,
+            "cclr_jacobian_right_noalloc: FP64 transforms only (a reduced-precision operator copy is allocated)");
+    REQUIRE(c->fixed_ws, CCLR_ESTATE, "the fixed work space was not set up for this context");
+    // the packed input and output vectors, the full doubles layout and the
+    // ring layout are the least the transform takes; the arena's own bound
+    // check catches the rest before anything is written beyond the region
+    const double need = 16.0 * nvec * (2.0 * (c->ns() + c->nd()) + 2.0 * c->o * c->o * (double)c->v * c->v);
+    REQUIRE(need <= (double)kFixedWsBytes, CCLR_ENOMEM,
+            "cclr_jacobian_right_noalloc: " + std::to_string(nvec) + " vectors at o=" + std::to_string(c->o) +
+                ", v=" + std::to_string(c->v) + " need more than the fixed work space of " +
+                std::to_string(kFixedWsBytes) + " bytes; use cclr_jacobian_right");
+    std::lock_guard<std::mutex> busy(g_ws_busy[c->device]);
+    // route every temporary of this call into the work space, take no new
+    // timing runs, and keep the transform on the context's stream
+    struct Scope {
+      cclr_ctx* c;
+      bool overlap, prof;
+      Scope(cclr_ctx* c_) : c(c_), overlap(c_->overlap), prof(c_->prof) {
+        c->arena.ext = (char*)c->fixed_ws;
+        c->arena.ext_bytes = kFixedWsBytes;
+        c->arena.ext_used = c->arena.ext_peak = 0;
+        c->no_timing = true;
+        c->overlap = false;
+        c->prof = false;
+      }
+      ~Scope() {
+        // the work queued on the region must end before another call reuses it
+        (void)hipStreamSynchronize(c->stream);
+        c->fixed_ws_peak = c->arena.ext_peak;
+        c->arena.ext = nullptr;
+        c->arena.ext_bytes = c->arena.ext_used = 0;
+        c->no_timing = false;
+        c->overlap = overlap;
+        c->prof = prof;
+      }
+    } scope(c);
+    return jacobian(c, CCLR_RIGHT, nvec, omega, gamma, r1, r2, s1, s2);
+  });
 }
 
 namespace {

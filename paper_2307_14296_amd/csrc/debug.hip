@@ -288,6 +288,12 @@ int cclr_dbg_set_blocking(cclr_ctx* c, long long wp_block, int rhs_group) {
   return CCLR_OK;
 }
 
+int cclr_dbg_fixed_ws_peak(const cclr_ctx* c, long long* bytes) {
+  if (!c || !bytes) return CCLR_EINVAL;
+  *bytes = (long long)c->fixed_ws_peak;
+  return CCLR_OK;
+}
+
 int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {
   if (!c) return CCLR_EINVAL;
   if (enable >= 0) c->autotune = enable != 0;

@@ -47,6 +47,15 @@ Arena::~Arena() {
 
 void* Arena::get(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
+  if (ext) {
+    if (bytes > ext_bytes - ext_used)
+      throw CclrError(CCLR_ENOMEM, "work space of " + std::to_string(ext_bytes) + " bytes exhausted (" +
+                                       std::to_string(ext_used + bytes) + " bytes needed so far)");
+    void* p = ext + ext_used;
+    ext_used += bytes;
+    ext_peak = std::max(ext_peak, ext_used);
+    return p;
+  }
   while (cur < chunks.size()) {
     if (used[cur] + bytes <= chunks[cur]->bytes) {
       void* p = (char*)chunks[cur]->p + used[cur];
@@ -69,10 +78,18 @@ void* Arena::get(size_t bytes) {
   return b->p;
 }
 
-Arena::Mark Arena::mark() const { return {cur, chunks.empty() ? 0 : used[cur]}; }
+Arena::Mark Arena::mark() const {
+  if (ext) return {size_t(-1), ext_used};
+  return {cur, chunks.empty() ? 0 : used[cur]};
+}
 
 void Arena::reset(Mark m) {
   if (hold > 0) return;
+  if (ext) {
+    if (m.chunk == size_t(-1)) ext_used = m.top;
+    return;
+  }
+  if (m.chunk == size_t(-1)) return;  // a mark of the external region
   for (size_t k = m.chunk + 1; k < chunks.size(); ++k) used[k] = 0;
   if (!chunks.empty()) used[m.chunk] = m.top;
   cur = m.chunk;
@@ -624,6 +641,11 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (it != c->gemm_choice.end()) {
     launch_zgemm_variant(g, it->second, c->stream);
     return it->second;
+  }
+  if (c->no_timing) {  // a call that may not allocate: the untimed choice
+    const int v = g.M <= 64 ? GEMM_64x64_G4 : gemm_default_variant(g);
+    launch_zgemm_variant(g, v, c->stream);
+    return v;
   }
   // nothing else may run while the variants are timed: drain the side stream too
   HIPCHK(hipStreamSynchronize(c->stream));

@@ -66,6 +66,10 @@ struct Arena {
   // while hold > 0, reset() keeps everything: memory handed to work queued on
   // another stream stays untouched until that stream has been joined
   int hold = 0;
+  // external mode: while ext is set, get() carves from [ext, ext + ext_bytes)
+  // and never allocates; a request beyond the region throws CCLR_ENOMEM
+  char* ext = nullptr;
+  size_t ext_bytes = 0, ext_used = 0, ext_peak = 0;
   ~Arena();
   void* get(size_t bytes);
   struct Mark { size_t chunk, top; };
@@ -281,6 +285,12 @@ struct cclr_ctx {
   };
   std::vector<TuneRecord> gemm_tuning_log;
   bool autotune = true;
+  // no new timing runs (they create events and take scratch outputs); cached
+  // choices are still used
+  bool no_timing = false;
+  // this device's copy of the library's fixed work space (see capi.hip)
+  void* fixed_ws = nullptr;
+  size_t fixed_ws_peak = 0;  // bytes of it the last such call took at most
   // kernel variant of grouped multi-context launches, per set of product shapes
   std::map<std::string, int> group_choice;
   // the ring and ladder products of an FP64 right transform run on a second

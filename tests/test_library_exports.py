@@ -41,3 +41,4 @@ def test_binding_checks_arguments_without_gpu():
     assert cc.lib().cclr_create(1, 5, ctypes.byref(o), ctypes.byref(ctypes.c_void_p())) == cc.CCLR_EINVAL
     assert "o >= 2" in cc.cclr_last_error(None)
     assert cc.lib().cclr_jacobian_right(None, 1, None, None, None, None, None, None) == cc.CCLR_EINVAL
+    assert cc.lib().cclr_jacobian_right_noalloc(None, 1, None, None, None, None, None, None) == cc.CCLR_EINVAL
