@@ -141,6 +141,8 @@ def cclr_create(o, v, options=None, stream=None):
 
 
 def cclr_destroy(ctx):
+    if ctx is not None:
+        _loaded_h.pop(_ctx_key(ctx), None)
     return lib().cclr_destroy(ctx)
 
 
@@ -149,10 +151,24 @@ def cclr_last_error(ctx=None):
     return m.decode() if m else ""
 
 
+# The tensors last handed to cclr_set_hamiltonian, per context (weak
+# references and version counters), so that response_function can check that
+# the Hamiltonian it differentiates with respect to is the one loaded.
+_loaded_h = {}
+
+
+def _ctx_key(ctx):
+    return ctx.value if isinstance(ctx, ctypes.c_void_p) else int(ctx)
+
+
 def cclr_set_hamiltonian(ctx, f, oooo, ooov, oovv, ovov, ovvv, vvvv):
-    args = [_ptr(x, n) for x, n in zip((f, oooo, ooov, oovv, ovov, ovvv, vvvv),
-                                       ("f", "oooo", "ooov", "oovv", "ovov", "ovvv", "vvvv"))]
-    return _check(ctx, lib().cclr_set_hamiltonian(ctx, *args))
+    import weakref
+    ts = (f, oooo, ooov, oovv, ovov, ovvv, vvvv)
+    args = [_ptr(x, n) for x, n in zip(ts, ("f", "oooo", "ooov", "oovv", "ovov", "ovvv", "vvvv"))]
+    _loaded_h.pop(_ctx_key(ctx), None)
+    rc = _check(ctx, lib().cclr_set_hamiltonian(ctx, *args))
+    _loaded_h[_ctx_key(ctx)] = [(weakref.ref(t), t._version) for t in ts]
+    return rc
 
 
 def cclr_set_amplitudes(ctx, t1, t2):
@@ -161,6 +177,7 @@ def cclr_set_amplitudes(ctx, t1, t2):
 
 def cclr_set_hamiltonian_cholesky(ctx, f, L):
     """Integral blocks from Cholesky vectors L[nchol][n][n] (device tensor)."""
+    _loaded_h.pop(_ctx_key(ctx), None)
     return _check(ctx, lib().cclr_set_hamiltonian_cholesky(ctx, _ptr(f, "f"), int(L.shape[0]), _ptr(L, "L")))
 
 
@@ -296,32 +313,63 @@ def cclr_response_backward(ctx, X, omega, gamma, G, dX=None, df=None, dV=None):
     return rc, info
 
 
-def response_function(ctx, X, omega, gamma):
+def response_function(ctx, X, omega, gamma, hamiltonian=None):
     """Differentiable <<X_p;X_q>>(omega + i gamma): returns a (nfreq, nx, nx)
-    complex128 tensor on the GPU; gradients flow to the perturbation
-    matrices X through cclr_response_backward."""
-    return _ResponseFunction.apply(ctx, list(omega), list(gamma), *X)
+    complex128 tensor on the GPU.  Gradients flow to the perturbation
+    matrices X and, when ``hamiltonian`` is given, to the Fock matrix and the
+    six integral blocks (f, oooo, ooov, oovv, ovov, ovvv, vvvv): the very
+    tensors last passed to cclr_set_hamiltonian for this context, unchanged
+    since (checked).  The amplitudes are held fixed.  Both directions come
+    from cclr_response_backward; the gradient of f and of the integrals is the
+    one projected onto changes that keep their symmetries.  A forward or
+    backward call whose solves stop at maxiter warns (RuntimeWarning)."""
+    hs = ()
+    if hamiltonian is not None:
+        hs = tuple(hamiltonian)
+        if len(hs) != 7:
+            raise ValueError("hamiltonian: expected (f, oooo, ooov, oovv, ovov, ovvv, vvvv)")
+        rec = _loaded_h.get(_ctx_key(ctx))
+        if rec is None or any(r() is not t or t._version != ver for (r, ver), t in zip(rec, hs)):
+            raise ValueError("hamiltonian: these tensors are not the ones loaded in the context (or changed since); "
+                             "call cclr_set_hamiltonian and cclr_set_amplitudes with them first")
+    return _ResponseFunction.apply(ctx, list(omega), list(gamma), len(X), len(hs), *X, *hs)
 
 
 def _autograd():
+    import warnings
+
     import torch
 
     class ResponseFunction(torch.autograd.Function):
         @staticmethod
-        def forward(fctx, handle, omega, gamma, *X):
-            Xc = [x.detach().contiguous() for x in X]
+        def forward(fctx, handle, omega, gamma, nx, nh, *args):
+            Xc = [x.detach().contiguous() for x in args[:nx]]
             rc, out, info = cclr_response_function(handle, Xc, omega, gamma)
-            fctx.handle, fctx.omega, fctx.gamma = handle, omega, gamma
-            fctx.save_for_backward(*Xc)
-            return torch.as_tensor(out, device=X[0].device)
+            if rc == CCLR_ENOTCONV:
+                warnings.warn(f"response_function: solves not converged ({info.as_dict()})", RuntimeWarning)
+            fctx.handle, fctx.omega, fctx.gamma, fctx.nx, fctx.nh = handle, omega, gamma, nx, nh
+            fctx.save_for_backward(*Xc, *[h.detach() for h in args[nx:]])
+            return torch.as_tensor(out, device=args[0].device)
 
         @staticmethod
         def backward(fctx, gout):
-            Xc = fctx.saved_tensors
-            dX = [torch.empty_like(x) for x in Xc]
-            cclr_response_backward(fctx.handle, list(Xc), fctx.omega, fctx.gamma,
-                                   gout.detach().cpu().numpy(), dX=dX)
-            return (None, None, None, *dX)
+            saved = fctx.saved_tensors
+            nx, nh = fctx.nx, fctx.nh
+            Xc, hs = list(saved[:nx]), saved[nx:]
+            want_x = any(fctx.needs_input_grad[5:5 + nx])
+            want_h = nh > 0 and any(fctx.needs_input_grad[5 + nx:])
+            dX = [torch.empty_like(x) for x in Xc] if want_x else None
+            df = torch.empty_like(hs[0]) if want_h else None
+            dV = [torch.empty_like(h) for h in hs[1:]] if want_h else None
+            if want_x or want_h:
+                rc, info = cclr_response_backward(fctx.handle, Xc, fctx.omega, fctx.gamma,
+                                                  gout.detach().cpu().numpy(), dX=dX, df=df, dV=dV)
+                if rc == CCLR_ENOTCONV:
+                    warnings.warn(f"response_function backward: solves not converged ({info.as_dict()})",
+                                  RuntimeWarning)
+            gx = dX if want_x else [None] * nx
+            gh = ([df] + dV) if want_h else [None] * nh
+            return (None, None, None, None, None, *gx, *gh)
 
     return ResponseFunction
 

@@ -247,3 +247,114 @@ def test_backward_hamiltonian_config1(small):
         assert abs(an - fd) <= 1e-7 * abs(fd)
     finally:
         cc.cclr_destroy(ctx)
+
+
+# ------------------------------------------------------- oracle gradient
+def oracle_dL(ref, Xs, zs, G, dXs=None, df=None, dV=None):
+    """Exact directional derivative of L from the oracle's chain rule through
+    the solves (no difference quotients)."""
+    dH = None
+    if df is not None:
+        n = ref.o + ref.v
+        dH = O.Hamiltonian(ref.o, ref.v, df, {k: dV.get(k, np.zeros_like(ref.H.blocks[k])) for k in BLOCKS})
+    d = np.stack([ref.response_derivative(Xs, z, dXs=dXs, dH=dH) for z in zs])
+    return float(np.real(np.sum(np.conj(G) * d)))
+
+
+def test_backward_matches_oracle_gradient_config1():
+    """o=4, v=16: the adjoint against the oracle's exact derivative along
+    random directions of every perturbation matrix and of (f, <pq||rs>)."""
+    import paper_2307_14296_amd as cc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pb, inst, H, t1, t2 = config_problem(4, 16, 0)
+    ref = O.CCLR(H, t1, t2)
+    op = cc.cclr_default_options()
+    op.tol = 1e-12
+    ctx = cc.cclr_create(4, 16, op)
+    try:
+        keep = [dev(H.f)] + [dev(H.blocks[k]) for k in s.CANONICAL_BLOCKS] + [dev(t1), dev(t2)]
+        cc.cclr_set_hamiltonian(ctx, *keep[:7])
+        cc.cclr_set_amplitudes(ctx, *keep[7:])
+        Xs = [s.dipole(pb, 0).numpy(), s.magnetic_like(pb, 0).numpy()]
+        zs = [0.1 + 0.005j, -0.05 + 0.0j]
+        rng = np.random.default_rng(11)
+        G = rng.normal(size=(2, 2, 2)) + 1j * rng.normal(size=(2, 2, 2))
+        n = 20
+        gX = [torch.empty((n, n), dtype=torch.complex128, device="cuda") for _ in Xs]
+        gf = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+        gV = [torch.empty(H.blocks[k].shape, dtype=torch.complex128, device="cuda") for k in BLOCKS]
+        print("backward o=4 v=16 (dX, df, dV)", flush=True)
+        rc, info = cc.cclr_response_backward(ctx, [dev(x) for x in Xs], [z.real for z in zs], [z.imag for z in zs],
+                                             G, dX=gX, df=gf, dV=gV)
+        assert rc == 0, info.as_dict()
+        gX = [g.cpu().numpy() for g in gX]
+        gf, gV = gf.cpu().numpy(), {k: g.cpu().numpy() for k, g in zip(BLOCKS, gV)}
+        for r in range(2):
+            d = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+            dXs = [d if q == r else np.zeros((n, n), dtype=np.complex128) for q in range(2)]
+            ex = oracle_dL(ref, Xs, zs, G, dXs=dXs)
+            an = an_dir(gX[r], d)
+            print(f"dL along X_{r}: {an:.14e} vs oracle {ex:.14e}", flush=True)
+            assert abs(an - ex) <= 1e-10 * abs(ex)
+        df, dV = sym_direction(4, 16, rng)
+        ex_all = oracle_dL(ref, Xs, zs, G, df=df, dV=dV)
+        for name, a, b in [("f", df, {})] + [(k, np.zeros((n, n)), {k: dV[k]}) for k in BLOCKS]:
+            ex = oracle_dL(ref, Xs, zs, G, df=a, dV=b)
+            an = h_an(gf, gV, a, b)
+            print(f"dL along {name}: {an:.14e} vs oracle {ex:.14e}", flush=True)
+            assert abs(an - ex) <= 1e-10 * max(abs(ex), 1e-3 * abs(ex_all))
+        an = h_an(gf, gV, df, dV)
+        print(f"dL along all: {an:.14e} vs oracle {ex_all:.14e}", flush=True)
+        assert abs(an - ex_all) <= 1e-10 * abs(ex_all)
+    finally:
+        cc.cclr_destroy(ctx)
+
+
+def test_autograd_reaches_the_hamiltonian():
+    """torch.autograd through response_function with f and the six integral
+    blocks as inputs: gradients of Re and Im of one entry against the
+    oracle's exact derivative at o=3, v=6."""
+    import paper_2307_14296_amd as cc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pb, inst, H, t1, t2 = config_problem(3, 6, 4)
+    ref = O.CCLR(H, t1, t2)
+    op = cc.cclr_default_options()
+    op.tol = 1e-12
+    ctx = cc.cclr_create(3, 6, op)
+    try:
+        hs = [dev(H.f).requires_grad_(True)] + [dev(H.blocks[k]).requires_grad_(True) for k in BLOCKS]
+        cc.cclr_set_hamiltonian(ctx, *hs)
+        cc.cclr_set_amplitudes(ctx, dev(t1), dev(t2))
+        Xs = [s.dipole(pb, 0).numpy(), s.magnetic_like(pb, 0).numpy()]
+        X = [dev(x).requires_grad_(True) for x in Xs]
+        z = 0.0774 + 0.0j
+        out = cc.response_function(ctx, X, [z.real], [z.imag], hamiltonian=hs)
+        ref_out = ref.response(Xs, z)
+        assert np.abs(out.detach().cpu().numpy()[0] - ref_out).max() <= 1e-10 * np.abs(ref_out).max()
+        rng = np.random.default_rng(5)
+        n = 9
+        for part in ("re", "im"):
+            for t in X + hs:
+                t.grad = None
+            val = out[0, 0, 1].real if part == "re" else out[0, 0, 1].imag
+            val.backward(retain_graph=True)
+            G = np.zeros((1, 2, 2), dtype=np.complex128)
+            G[0, 0, 1] = 1.0 if part == "re" else 1j
+            df, dV = sym_direction(3, 6, rng)
+            ex = oracle_dL(ref, Xs, [z], G, df=df, dV=dV)
+            an = h_an(hs[0].grad.cpu().numpy(), {k: h.grad.cpu().numpy() for k, h in zip(BLOCKS, hs[1:])}, df, dV)
+            print(f"autograd {part} <<mu;m>> along (f, V): {an:.14e} vs oracle {ex:.14e}", flush=True)
+            assert abs(an - ex) <= 1e-10 * abs(ex)
+            d = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+            ex = oracle_dL(ref, Xs, [z], G, dXs=[np.zeros((n, n)), d])
+            an = an_dir(X[1].grad.cpu().numpy(), d)
+            print(f"autograd {part} <<mu;m>> along m: {an:.14e} vs oracle {ex:.14e}", flush=True)
+            assert abs(an - ex) <= 1e-10 * abs(ex)
+        # tensors that are not the loaded Hamiltonian are refused
+        other = [h.detach().clone() for h in hs]
+        with pytest.raises(ValueError):
+            cc.response_function(ctx, X, [z.real], [z.imag], hamiltonian=other)
+    finally:
+        cc.cclr_destroy(ctx)
