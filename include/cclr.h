@@ -65,8 +65,13 @@ enum {
 };
 
 /* arithmetic of the bulk contractions (solver, residuals and dot products
- * are always FP64) */
-enum { CCLR_FP64 = 0, CCLR_FP32 = 1, CCLR_BF16X3 = 2 };
+ * are always FP64): FP64; FP32 MFMA; split-BF16 MFMA with FP32 accumulation,
+ * both operands split hi + lo and three bf16 products per real product
+ * (BF16X3), or the trial-vector operand split and the Jacobian's operator
+ * rounded to bf16, two bf16 products per real product (BF16X2).  The reduced
+ * precisions run inside an FP64 iterative refinement, so the results meet
+ * the same tolerance. */
+enum { CCLR_FP64 = 0, CCLR_FP32 = 1, CCLR_BF16X3 = 2, CCLR_BF16X2 = 3 };
 
 enum { CCLR_RIGHT = 0, CCLR_LEFT = 1 };
 

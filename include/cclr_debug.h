@@ -48,8 +48,8 @@ int cclr_dbg_run_gemm(cclr_ctx* ctx, int M, int N, int K, int batch, const cclr_
                       double alpha_im, int beta);
 
 /* The same product (batch 1) in reduced arithmetic: prec = CCLR_FP32 (FP32
- * MFMA) or CCLR_BF16X3 (split-BF16 MFMA, three bf16 products per real
- * product, FP32 accumulation); operands and C stay complex128. */
+ * MFMA), CCLR_BF16X3 or CCLR_BF16X2 (split-BF16 MFMA, FP32 accumulation);
+ * operands and C stay complex128. */
 int cclr_dbg_zgemm_lowp(int prec, int M, int N, int K, const cclr_c64* A, long long sAm, long long sAk, int conjA,
                         const cclr_c64* B, long long sBk, long long sBn, int conjB, cclr_c64* C, long long sCm,
                         long long sCn, double alpha_re, double alpha_im, int beta);
@@ -76,8 +76,8 @@ int cclr_dbg_profile(cclr_ctx* ctx, int enable);
 int cclr_dbg_profile_read(cclr_ctx* ctx, int largest_only, long long* launches, double* ms, double* flops);
 
 /* Arithmetic of the ladder and ring products used by subsequent
- * cclr_jacobian_right/left calls on ctx (CCLR_FP64, CCLR_FP32, CCLR_BF16X3);
- * the solvers set it themselves. */
+ * cclr_jacobian_right/left calls on ctx (CCLR_FP64, CCLR_FP32, CCLR_BF16X3,
+ * CCLR_BF16X2); the solvers set it themselves. */
 int cclr_dbg_set_sigma_prec(cclr_ctx* ctx, int prec);
 
 /* Relative residual at which a reduced-precision inner solve hands over to

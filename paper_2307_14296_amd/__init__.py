@@ -20,7 +20,7 @@ CCLR_EINVAL = -1
 CCLR_ENOMEM = -2
 CCLR_EHIP = -3
 CCLR_ESTATE = -4
-CCLR_FP64, CCLR_FP32, CCLR_BF16X3 = 0, 1, 2
+CCLR_FP64, CCLR_FP32, CCLR_BF16X3, CCLR_BF16X2 = 0, 1, 2, 3
 CCLR_RIGHT, CCLR_LEFT = 0, 1
 
 EXPORTED = (

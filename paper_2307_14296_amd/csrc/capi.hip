@@ -177,9 +177,10 @@ int cclr_create(int o, int v, const cclr_options* opt, cclr_ctx** out) {
     c->v = v;
     if (opt) c->opt = *opt;
     else cclr_default_options(&c->opt);
-    if (c->opt.prec != CCLR_FP64 && c->opt.prec != CCLR_FP32 && c->opt.prec != CCLR_BF16X3) {
+    if (c->opt.prec != CCLR_FP64 && c->opt.prec != CCLR_FP32 && c->opt.prec != CCLR_BF16X3 &&
+        c->opt.prec != CCLR_BF16X2) {
       delete c;
-      throw CclrError(CCLR_EINVAL, "prec must be CCLR_FP64, CCLR_FP32 or CCLR_BF16X3");
+      throw CclrError(CCLR_EINVAL, "prec must be CCLR_FP64, CCLR_FP32, CCLR_BF16X3 or CCLR_BF16X2");
     }
     if (!(c->opt.tol > 0.0) || c->opt.maxiter < 1 || c->opt.max_subspace < 4 || c->opt.max_subspace > 120) {
       delete c;

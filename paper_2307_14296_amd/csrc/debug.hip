@@ -124,12 +124,13 @@ int cclr_dbg_zgemm_lowp(int prec, int M, int N, int K, const cclr_c64* A, long l
     g.B = (const cplx*)B; g.sBk = sBk; g.sBn = sBn; g.conjB = conjB;
     g.C = (cplx*)C; g.sCm = sCm; g.sCn = sCn;
     g.ar = ar; g.ai = ai; g.beta = beta;
-    if (prec == CCLR_BF16X3) {
-      HIPCHK(hipMalloc(&wa, split_bytes(M, K)));
-      HIPCHK(hipMalloc(&wb, split_bytes(N, K)));
-      const SplitMat sa = launch_split_bf16(M, K, g.A, sAm, sAk, conjA, wa, nullptr);
-      const SplitMat sb = launch_split_bf16(N, K, g.B, sBn, sBk, conjB, wb, nullptr);
-      launch_cgemm_bf16x3(sa, sb, g.C, sCm, sCn, ar, ai, beta, nullptr);
+    if (prec == CCLR_BF16X3 || prec == CCLR_BF16X2) {
+      const int form = bf16_form_of(prec);
+      HIPCHK(hipMalloc(&wa, split_bytes(M, K, form, 0)));
+      HIPCHK(hipMalloc(&wb, split_bytes(N, K, form, 1)));
+      const SplitMat sa = launch_split_bf16(M, K, g.A, sAm, sAk, conjA, wa, form, 0, nullptr);
+      const SplitMat sb = launch_split_bf16(N, K, g.B, sBn, sBk, conjB, wb, form, 1, nullptr);
+      launch_cgemm_bf16(sa, sb, g.C, sCm, sCn, ar, ai, beta, nullptr);
     } else {
       launch_zgemm_lowp(g, prec, nullptr);
     }
@@ -248,7 +249,7 @@ int cclr_dbg_profile_read(cclr_ctx* c, int largest_only, long long* launches, do
 }
 
 int cclr_dbg_set_sigma_prec(cclr_ctx* c, int prec) {
-  if (!c || (prec != CCLR_FP64 && prec != CCLR_FP32 && prec != CCLR_BF16X3)) return CCLR_EINVAL;
+  if (!c || (prec != CCLR_FP64 && prec != CCLR_FP32 && prec != CCLR_BF16X3 && prec != CCLR_BF16X2)) return CCLR_EINVAL;
   c->sigma_prec = prec;
   return CCLR_OK;
 }

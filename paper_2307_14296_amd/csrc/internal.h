@@ -143,20 +143,28 @@ int gemm_tile_cols(int variant);
 // the same product with FP32 (prec = CCLR_FP32) or split-BF16 (CCLR_BF16X3)
 // MFMA arithmetic and FP32 accumulation; operands and C stay complex128 in memory
 void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s);
-// Split-BF16 operand: a rows x K complex matrix as bf16 planes
-// [K/32][rows_pad][re_hi, re_lo, im_hi, im_lo][32], zero padded.
+// Split-BF16 products (gemm_bf16.hip): three (X3: both operands split
+// hi + lo) or two (X2: the B operand hi only) bf16 products per real product.
+enum { BF16_X3 = 0, BF16_X2 = 1 };
+bool bf16_form_valid(int form);
+int bf16_form_of(int prec);  // prec CCLR_BF16X3 or CCLR_BF16X2
+// A split operand of one form and side (0: A, the rows of C; 1: B, the
+// columns): a rows x K complex matrix as [K/32][rows_pad][4*nplanes]
+// 16-byte chunks of bf16 planes (codes in planes[]), swizzled, zero padded.
 struct SplitMat {
   const void* p = nullptr;
   int rows = 0, K = 0, rows_pad = 0, nkc = 0;
+  int form = 0, side = 0, nplanes = 0;
+  int planes[4] = {0, 0, 0, 0};
 };
-SplitMat split_shape(int rows, int K);
-size_t split_bytes(int rows, int K);
+SplitMat split_shape(int rows, int K, int form, int side);
+size_t split_bytes(int rows, int K, int form, int side);
 // dst <- split of op(src)[r][k] = src[r*sR + k*sK] (conjugated if conj)
-SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, hipStream_t s);
-// C[m][n] (+)= alpha * sum_k A[m][k] B[n][k], three bf16 products per real product, FP32 accumulation
-// variant 0: four waves of 64x64, variant 1: eight waves of 64x32 (more latency hiding)
-void launch_cgemm_bf16x3(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
-                         int beta, hipStream_t s, int variant = 0);
+SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, int form, int side,
+                           hipStream_t s);
+// C[m][n] (+)= alpha * sum_k A[m][k] B[n][k] on operands split for one form, FP32 accumulation
+void launch_cgemm_bf16(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
+                       int beta, hipStream_t s);
 // products with K <= 32 on the vector ALU (returns false if the form does not apply)
 bool launch_zgemm_smallk(const GemmArgs& g, hipStream_t s);
 // C[b][m][n] = (beta ? C : 0) + alpha * sum_s W[b][s][m][n]
@@ -262,7 +270,8 @@ struct cclr_ctx {
   DevBuf WvvvoTP;    // WvvvoTP[j][e][AB] = W^ab_ej (a > b), for the right doubles term P(ij) W^ab_ej r^e_i
   DevBuf WvvvoLP, WvovvL;  // WvvvoLP[a][m][EF] = W^ef_am (e > f), WvovvL[i][a][f][e] = W^ei_fa (left transform)
   // split-BF16 copies of the ladder and ring operators, made on first use in
-  // that precision: right ladder, left ladder, right ring, left ring
+  // that precision (in the form of the products): right ladder, left ladder,
+  // right ring, left ring
   DevBuf wsplit[4];
   SplitMat wsplit_m[4];
   DevBuf diag;       // Fock-like diagonal for preconditioning: singles then doubles (packed)

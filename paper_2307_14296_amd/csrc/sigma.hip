@@ -51,48 +51,21 @@ void op_gemm(cclr_ctx* c, const GemmArgs& g, int which) {
     launch_zgemm_lowp(g, CCLR_FP32, c->stream);
     return;
   }
-  REQUIRE(c->sigma_prec == CCLR_BF16X3 && g.batch == 1 && g.kchunk == 0, CCLR_EINVAL, "unsupported product form");
+  REQUIRE((c->sigma_prec == CCLR_BF16X3 || c->sigma_prec == CCLR_BF16X2) && g.batch == 1 && g.kchunk == 0,
+          CCLR_EINVAL, "unsupported product form");
+  const int form = bf16_form_of(c->sigma_prec);
   SplitMat& W = c->wsplit_m[which];
-  if (!W.p) {
-    c->wsplit[which].alloc(c, split_bytes(g.N, g.K));
-    W = launch_split_bf16(g.N, g.K, g.B, g.sBn, g.sBk, g.conjB, c->wsplit[which].p, c->stream);
+  if (!W.p || W.form != form) {
+    c->wsplit_m[which] = SplitMat{};
+    c->wsplit[which].release();
+    c->wsplit[which].alloc(c, split_bytes(g.N, g.K, form, 1));
+    W = launch_split_bf16(g.N, g.K, g.B, g.sBn, g.sBk, g.conjB, c->wsplit[which].p, form, 1, c->stream);
   }
   REQUIRE(W.rows == g.N && W.K == g.K, CCLR_EINVAL, "split operator has another shape");
   Arena::Mark mk = c->arena.mark();
-  void* ws = c->arena.get(split_bytes(g.M, g.K));
-  const SplitMat A = launch_split_bf16(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, ws, c->stream);
-  // kernel variant (wave layout) timed once per shape
-  const auto key = std::make_tuple(octave_bucket(g.M), shape_bucket(g.N), shape_bucket(g.K), 1, 200 + which);
-  auto it = c->gemm_choice.find(key);
-  int var = 0;
-  if (it != c->gemm_choice.end()) {
-    var = it->second;
-  } else if (c->autotune && !g.beta) {  // timing runs overwrite C
-    std::vector<double> ms;
-    double best = 1e300;
-    for (int v = 0; v < 2; ++v) {
-      hipEvent_t e0, e1;
-      HIPCHK(hipEventCreate(&e0));
-      HIPCHK(hipEventCreate(&e1));
-      HIPCHK(hipEventRecord(e0, c->stream));
-      launch_cgemm_bf16x3(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream, v);
-      HIPCHK(hipEventRecord(e1, c->stream));
-      HIPCHK(hipEventSynchronize(e1));
-      float t = 0.f;
-      HIPCHK(hipEventElapsedTime(&t, e0, e1));
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      ms.push_back(t);
-      if (t < best) best = t, var = v;
-    }
-    c->gemm_choice[key] = var;
-    std::vector<std::pair<int, double>> rec;
-    for (int v = 0; v < (int)ms.size(); ++v) rec.push_back({v, ms[v]});
-    c->gemm_tuning_log.push_back({"bf16x3 " + std::to_string(g.M) + "x" + std::to_string(g.N) + "x" +
-                                      std::to_string(g.K) + " op" + std::to_string(which),
-                                  rec, var});
-  }
-  launch_cgemm_bf16x3(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream, var);
+  void* ws = c->arena.get(split_bytes(g.M, g.K, form, 0));
+  const SplitMat A = launch_split_bf16(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, ws, form, 0, c->stream);
+  launch_cgemm_bf16(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
   c->arena.reset(mk);
 }
 

@@ -410,7 +410,7 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
     xinorm[r] = rcnorm[r] = std::sqrt(hv[r].x);
     if (xinorm[r] == 0.0) done[r] = 1, accumulated[r] = 1;  // x = 0
   }
-  const int max_outer = 8;
+  const int max_outer = 12;
   launch_fill(xout.s, (i64)nr * ov, cx(0.0), st);
   launch_fill(xout.d, (i64)nr * nd, cx(0.0), st);
   {
@@ -590,7 +590,12 @@ int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rh
   const double tol = c->opt.tol;
   const int lowp = c->opt.prec;
   // inner accuracy: what the reduced-precision products can deliver
-  const double inner = lowp == CCLR_FP64 ? 0.0 : c->inner_tol > 0.0 ? c->inner_tol : (lowp == CCLR_FP32 ? 1e-6 : 1e-4);
+  // (split-BF16 with the operator rounded to bf16: about 2^-9 of the operator)
+  const double inner = lowp == CCLR_FP64      ? 0.0
+                       : c->inner_tol > 0.0   ? c->inner_tol
+                       : lowp == CCLR_FP32    ? 1e-6
+                       : lowp == CCLR_BF16X3  ? 1e-4
+                                              : 1e-3;
   if (lowp == CCLR_FP64) c->sigma_prec = CCLR_FP64;
   const i64 ov = c->ns(), nd = c->nd(), oovv = (i64)c->o * c->o * c->v * c->v;
   const int ms = std::max(4, std::min(c->opt.max_subspace, 120));
