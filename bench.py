@@ -60,39 +60,169 @@ def make_inputs(o, v, seed, device, v_std=None):
     return pb, f, V, t1, t2, X
 
 
-def cpu_baseline(seconds_target=15.0):
-    """Oracle right Jacobian transform timed on the host (bounded sample)."""
+def host_threads():
+    """Cores this process may run on, and the BLAS library and its thread count."""
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        ncpu = os.cpu_count() or 1
+    blas, nthr = "unknown", ncpu
+    try:
+        from threadpoolctl import threadpool_info
+        info = [x for x in threadpool_info() if x.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
+            nthr = int(info[0].get("num_threads", ncpu))
+    except Exception:  # pragma: no cover
+        pass
+    return ncpu, blas, nthr
+
+
+def oracle_problem(o, v, seed, dev):
+    """The benchmark generators' instance (generated on the GPU, copied to the
+    host) as an oracle Hamiltonian and amplitudes."""
+    import torch
+    from gen import synth as s
+    from oracle import cclr_ref as O
+    pb, f, V, t1, t2, X = make_inputs(o, v, seed, dev)
+    host = lambda x: x.cpu().numpy()  # noqa: E731
+    H = O.Hamiltonian(o, v, host(f), {k: host(V[k]) for k in s.CANONICAL_BLOCKS})
+    r = [host(x) for x in s.excitation_vector(pb, 0, dev)]
+    Xs = [host(x) for x in X]
+    out = (H, host(t1), host(t2), r, Xs)
+    del f, V, t1, t2, X
+    torch.cuda.empty_cache()
+    return out
+
+
+def time_oracle_sigma(H, t1, t2, r, reps, threads=None):
+    """Median wall time of the oracle's right transform (after one warm-up
+    call), and the Hbar build time, optionally with the BLAS limited."""
+    import contextlib
+    import statistics
+    from oracle import cclr_ref as O
+    lim = contextlib.nullcontext()
+    if threads is not None:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=threads)
+    with lim:
+        t0 = time.perf_counter()
+        ref = O.CCLR(H, t1, t2)
+        t_hbar = time.perf_counter() - t0
+        ref.right(*r, 0.0774 + 0.005j)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ref.right(*r, 0.0774 + 0.005j)
+            ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), t_hbar
+
+
+def cpu_baseline(dev, o=16, v=120, reps=3):
+    """The oracle's right Jacobian transform timed on the host at o=16,
+    v=120 (the largest size whose set-up and transforms take well under a
+    minute of host time; the o=20, v=200 oracle transform, measured on its
+    own with --mode cpu, takes minutes to set up), every core."""
+    ncpu, blas, nthr = host_threads()
+    H, t1, t2, r, _ = oracle_problem(o, v, 2, dev)
+    dt, t_hbar = time_oracle_sigma(H, t1, t2, r, reps)
+    return {
+        "value": 1.0 / dt,
+        "unit": "Jacobian transforms/s",
+        "cores": nthr,
+        "kind": "oracle",
+        "sample": (f"oracle right Jacobian transform (numpy, FP64 complex, {blas}) measured at o={o}, v={v} (not at "
+                   f"o=20, v=200; no scaling): median of {reps} after a warm-up, {dt:.2f} s each, "
+                   f"{sigma_flops(o, v)['total'] / dt / 1e9:.1f} GFLOP/s algorithmic; Hbar build {t_hbar:.1f} s; "
+                   f"{nthr} BLAS threads on {ncpu} cores"),
+    }
+
+
+def cpu_table(dev):
+    """Oracle timings on the host: one right transform at (4,16), (10,80),
+    (16,120) and (20,200) with every core and (below (20,200)) one thread,
+    and the whole response tensor of the first two configurations."""
     import numpy as np
     from gen import synth as s
     from oracle import cclr_ref as O
-    o, v = 10, 80
-    pb = s.Problem(o, v, 1)
-    inst = s.instance(pb)
-    H = O.Hamiltonian(o, v, inst["f"].numpy(), {k: x.numpy() for k, x in inst["V"].items()})
-    cc = O.CCLR(H, inst["t1"].numpy(), inst["t2"].numpy())
-    r = [x.numpy() for x in s.excitation_vector(pb, 0)]
-    cc.right(*r, 0.1)  # warm-up
-    n, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds_target or n < 2:
-        cc.right(*r, 0.1)
-        n += 1
-    dt = (time.perf_counter() - t0) / n
+    ncpu, blas, nthr = host_threads()
+    rows = []
+    for (o, v, seed) in ((4, 16, 0), (10, 80, 1), (16, 120, 2), (20, 200, 3)):
+        tg = time.perf_counter()
+        H, t1, t2, r, Xs = oracle_problem(o, v, seed, dev)
+        row = {"o": o, "v": v, "input_s": round(time.perf_counter() - tg, 1),
+               "sigma_gflop": sigma_flops(o, v)["total"] / 1e9}
+        reps = 10 if o <= 10 else 3
+        dt, th = time_oracle_sigma(H, t1, t2, r, reps)
+        row.update({"all_cores_s": dt, "hbar_all_cores_s": round(th, 2), "reps": reps})
+        log(f"cpu oracle o={o} v={v}: {dt:.3f} s per transform ({nthr} threads), Hbar {th:.1f} s")
+        if o < 20:
+            dt1, th1 = time_oracle_sigma(H, t1, t2, r, reps, threads=1)
+            row.update({"one_thread_s": dt1, "hbar_one_thread_s": round(th1, 2)})
+            log(f"cpu oracle o={o} v={v}: {dt1:.3f} s per transform (1 thread)")
+        if o <= 10:
+            z = 0.1 + 0.005j if o == 4 else 0.08 + 0.004j
+            t0 = time.perf_counter()
+            ref = O.CCLR(H, t1, t2)
+            alpha = -ref.response(Xs, z, method="dense" if o == 4 else "gmres")
+            row["alpha_all_cores_s"] = round(time.perf_counter() - t0, 2)
+            row["alpha_z"] = [z.real, z.imag]
+            log(f"cpu oracle o={o} v={v}: alpha in {row['alpha_all_cores_s']} s")
+        rows.append(row)
+        del H, t1, t2, r, Xs
+    return {"cores": ncpu, "blas": blas, "blas_threads": nthr, "rows": rows}
+
+
+def sigma_table(cc, dev, o, v, seed, reps=10):
+    """Right transforms at o, v for 1, 3 and 12 vectors in every arithmetic:
+    median of reps timed calls after a warm-up call (the paper's sigma
+    benchmark runs each transform 10 times)."""
+    import statistics
+    import torch
+    from gen import synth as s
+    L = cc.lib()
+    pb, f, V, t1, t2, X = make_inputs(o, v, seed, dev)
+    ctx = cc.cclr_create(o, v, cc.cclr_default_options())
+    rows = []
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([int(x.get("num_threads", 1)) for x in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
-    f_small = sigma_flops(o, v)["total"]
-    f_big = sigma_flops(20, 200)["total"]
-    return {
-        "value": (1.0 / dt) * (f_small / f_big),
-        "unit": "Jacobian transforms/s",
-        "cores": cores,
-        "kind": "oracle",
-        "sample": (f"oracle right Jacobian transform (numpy einsum, FP64 complex) at o=10, v=80: {n} calls, "
-                   f"{dt:.3f} s each; rate scaled to o=20, v=200 by the algorithmic-flop ratio "
-                   f"{f_small:.3e}/{f_big:.3e}"),
-    }
+        cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+        del V
+        torch.cuda.empty_cache()
+        cc.cclr_set_amplitudes(ctx, t1, t2)
+        nmax = 12
+        r1 = torch.zeros((nmax, o, v), dtype=torch.complex128, device=dev)
+        r2 = torch.zeros((nmax, o, o, v, v), dtype=torch.complex128, device=dev)
+        for k in range(nmax):
+            r1[k], r2[k] = s.excitation_vector(pb, k, dev)
+        fl = sigma_flops(o, v)["total"]
+        for prec, code in (("fp64", cc.CCLR_FP64), ("fp32", cc.CCLR_FP32), ("bf16x3", cc.CCLR_BF16X3),
+                           ("bf16x2", cc.CCLR_BF16X2)):
+            L.cclr_dbg_set_sigma_prec(ctx, code)
+            for n in (1, 3, 12):
+                a, b = r1[:n].contiguous(), r2[:n].contiguous()
+                s1, s2 = torch.empty_like(a), torch.empty_like(b)
+                om, ga = [0.0774] * n, [0.005] * n
+                cc.cclr_jacobian_right(ctx, om, ga, a, b, s1, s2)
+                ts = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    cc.cclr_jacobian_right(ctx, om, ga, a, b, s1, s2)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                t = statistics.median(ts)
+                rows.append({"prec": prec, "nvec": n, "ms": round(1e3 * t, 3),
+                             "transforms_per_s": round(n / t, 2),
+                             "tflops_algorithmic": round(n * fl / t / 1e12, 2)})
+                log(f"sigma table {prec} nvec={n}: {1e3 * t:.2f} ms")
+                del a, b, s1, s2
+        L.cclr_dbg_set_sigma_prec(ctx, cc.CCLR_FP64)
+    finally:
+        cc.cclr_destroy(ctx)
+        del f, t1, t2, X
+        torch.cuda.empty_cache()
+    return {"workload": f"right Jacobian transforms o={o} v={v} complex128, median of {reps} after a warm-up "
+                        "(wall time of the call, including the pack and unpack of the vectors)", "rows": rows}
 
 
 def spectrum_bench(cc, dev, o=16, v=120, seed=2, nfreq=16):
@@ -427,6 +557,21 @@ def gemm_kernel_name(variant):
     return "k_zgemm_p1" if variant >= 9 else "k_zgemm_p"
 
 
+def alpha_err(a, ref):
+    """Errors of a response tensor against a reference: Frobenius-norm
+    relative, the largest relative error of the entries at least 1e-3 of the
+    largest, and the largest error of the other entries relative to the
+    largest entry."""
+    import numpy as np
+    a, ref = np.asarray(a), np.asarray(ref)
+    mx = float(np.abs(ref).max())
+    big = np.abs(ref) >= 1e-3 * mx
+    d = np.abs(a - ref)
+    return {"frobenius": float(np.linalg.norm(a - ref) / np.linalg.norm(ref)),
+            "entries": float((d[big] / np.abs(ref[big])).max()),
+            "small_entries": float(d[~big].max() / mx) if (~big).any() else 0.0}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -441,9 +586,10 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--omega", type=float, default=0.0774)
     ap.add_argument("--gamma", type=float, default=0.005)
-    ap.add_argument("--mode", choices=["response", "sigma", "sweep"], default="response",
+    ap.add_argument("--mode", choices=["response", "sigma", "sweep", "cpu"], default="response",
                     help="response: the whole job (default); sigma: transforms of --nvec vectors; sweep: one "
-                         "transform at each of the paper's sigma-benchmark shapes")
+                         "transform at each of the paper's sigma-benchmark shapes; cpu: the oracle's timings on "
+                         "the host (transforms at four sizes, every core and one thread, and two response tensors)")
     ap.add_argument("--nvec", type=int, default=12, help="vectors per transform call in --mode sigma")
     ap.add_argument("--max-subspace", type=int, default=24)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -460,8 +606,13 @@ def main():
                     help="skip the backward of <<mu; m>> at o=24, v=240 (about 240 GB of device memory)")
     ap.add_argument("--no-ground", dest="ground", action="store_false",
                     help="skip the CCSD ground-state (CROP) and Cholesky-integral timings")
-    ap.add_argument("--mixed-precs", default="fp32,bf16x3",
+    ap.add_argument("--mixed-precs", default="fp32,bf16x3,bf16x2",
                     help="comma list of reduced precisions to run after the FP64 run")
+    ap.add_argument("--mixed-steps", type=int, default=5, help="timed steps of each reduced-precision run")
+    ap.add_argument("--tight-tol", type=float, default=1e-11,
+                    help="tolerance of the untimed FP64 reference solve that the alpha errors are measured against")
+    ap.add_argument("--no-sigma-table", dest="sigma_table", action="store_false",
+                    help="skip the table of transform timings per precision and vector count")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
@@ -474,7 +625,7 @@ def main():
 
     L = cc.lib()
     L.cclr_dbg_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    L.cclr_dbg_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+    L.cclr_dbg_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.cclr_dbg_set_sigma_prec.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.cclr_dbg_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_longlong]
@@ -482,8 +633,12 @@ def main():
     dev = torch.device("cuda:0")
     z = complex(args.omega, args.gamma)
 
-    def run(prec):
-        """Time args.steps steps with the given arithmetic; returns a dict."""
+    PRECS = {"fp64": cc.CCLR_FP64, "fp32": cc.CCLR_FP32, "bf16x3": cc.CCLR_BF16X3, "bf16x2": cc.CCLR_BF16X2}
+
+    def run(prec, steps, warmup, tight_tol=None):
+        """Time `steps` steps with the given arithmetic; returns a dict.  With
+        tight_tol, one more untimed response solve to that tolerance follows
+        (FP64 reference of the alpha errors, conditioning estimate)."""
         t_gen = time.perf_counter()
         pb, f, V, t1, t2, X = make_inputs(o, v, args.seed, dev)
         torch.cuda.synchronize()
@@ -492,11 +647,12 @@ def main():
         opt = cc.cclr_default_options()
         opt.max_subspace = args.max_subspace
         opt.tol = args.tol
-        opt.prec = {"fp64": cc.CCLR_FP64, "fp32": cc.CCLR_FP32, "bf16x3": cc.CCLR_BF16X3}[prec]
+        opt.prec = PRECS[prec]
         ctx = cc.cclr_create(o, v, opt)
         cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
-        del V
-        torch.cuda.empty_cache()
+        if tight_tol is None:
+            del V
+            torch.cuda.empty_cache()
         log(f"[{prec}] Hamiltonian copied into the context")
         res = {"input_generation_s": round(t_gen, 2)}
         if args.mode == "sigma":
@@ -526,7 +682,7 @@ def main():
                 res["rc"] = rc
                 return info.nsigma
 
-        for k in range(args.warmup):
+        for k in range(warmup):
             tw = time.perf_counter()
             step()
             torch.cuda.synchronize()
@@ -535,23 +691,43 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ntr = 0
-        for k in range(args.steps):
+        for k in range(steps):
             ntr += step()
             torch.cuda.synchronize()
             log(f"[{prec}] timed step {k} done ({time.perf_counter() - t0:.2f} s so far)")
         dt = time.perf_counter() - t0
         nl, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
-        L.cclr_dbg_profile_read(ctx, 1, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
+        L.cclr_dbg_profile_read(ctx, 1, opt.prec, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
         L.cclr_dbg_profile(ctx, 0)
         buf = ctypes.create_string_buffer(1 << 16)
         L.cclr_dbg_tuning(ctx, -1, buf, len(buf))
         res["gemm_tuning"] = [ln for ln in buf.value.decode().splitlines() if ln]
         cc.cclr_destroy(ctx)
+        if tight_tol is not None and args.mode == "response":
+            # untimed FP64 reference solved to the tight tolerance
+            opt.tol = tight_tol
+            opt.prec = cc.CCLR_FP64
+            ctx = cc.cclr_create(o, v, opt)
+            try:
+                cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+                cc.cclr_set_amplitudes(ctx, t1, t2)
+                tt = time.perf_counter()
+                rc, out, info = cc.cclr_response_function(ctx, X, [z.real], [z.imag])
+                torch.cuda.synchronize()
+                res["tight"] = {"tol": tight_tol, "alpha": -out[0], "rc": rc, "solver": info.as_dict(),
+                                "seconds": round(time.perf_counter() - tt, 2)}
+                log(f"[{prec}] reference solve to {tight_tol:g}: {info.as_dict()}")
+            finally:
+                cc.cclr_destroy(ctx)
+            del V
         del f, t1, t2, X
         torch.cuda.empty_cache()
         res.update({"transforms": ntr, "dt": dt, "nl": nl.value, "ms": ms.value, "fl": fl.value})
         return res
 
+    if args.mode == "cpu":
+        print(json.dumps({"cpu_oracle_table": cpu_table(dev)}), flush=True)
+        return
     if args.mode == "sweep":
         rows = sweep_bench(cc, dev)
         tot_ms = sum(r["ms"] for r in rows)
@@ -572,11 +748,11 @@ def main():
         log(f"copy probe: {nel * 16 / (1 << 30):.3f} GiB read + written")
         del a, b
         torch.cuda.empty_cache()
-    main_res = run("fp64")
+    main_res = run("fp64", args.steps, args.warmup, tight_tol=args.tight_tol if args.mode == "response" else None)
     mixed = {}
     if args.mixed:
         for p in [x for x in args.mixed_precs.split(",") if x]:
-            mixed[p] = run(p)
+            mixed[p] = run(p, args.mixed_steps, 1)
     ntr, dt = main_res["transforms"], main_res["dt"]
     nl = ctypes.c_longlong(main_res["nl"])
     ms = ctypes.c_double(main_res["ms"])
@@ -623,25 +799,45 @@ def main():
         "roofline": roofline,
     }
     line["config"].update(extra)
+    ref_alpha = None
     if "alpha" in main_res:
         a = main_res["alpha"]
         line["config"]["alpha_fp64"] = [[[x.real, x.imag] for x in row] for row in a]
+        if "tight" in main_res:
+            tight = main_res["tight"]
+            ref_alpha = tight["alpha"]
+            line["config"]["alpha_reference"] = {
+                "tol": tight["tol"], "rc": tight["rc"], "solve_seconds": tight["seconds"],
+                "resnorm": tight["solver"]["resnorm"], "iters": tight["solver"]["iters"],
+                "alpha": [[[x.real, x.imag] for x in row] for row in ref_alpha],
+                "timed_fp64_alpha_vs_reference": alpha_err(a, ref_alpha)}
+            line["config"]["conditioning"] = {
+                "kappa_estimate": tight["solver"]["kappa"], "ritz_min": tight["solver"]["ritz_min"],
+                "what": "Ritz values theta of (A - z) on the final Davidson subspaces of the reference solve "
+                        "(the eigenvalues of the projected matrix): kappa = max|theta|/min|theta| (largest over "
+                        "right-hand sides), ritz_min = min|theta|"}
     names = {"fp32": "FP32 MFMA ladder/ring products, FP64 refinement",
-             "bf16x3": "split-BF16 MFMA ladder/ring products (3 bf16 products per real product, FP32 "
-                       "accumulation), FP64 refinement"}
+             "bf16x3": "split-BF16 MFMA ladder/ring products (both operands split hi+lo, 3 bf16 products per "
+                       "real product, FP32 accumulation), FP64 refinement",
+             "bf16x2": "split-BF16 MFMA ladder/ring products (trial vectors split hi+lo, operator rounded to "
+                       "bf16, 2 bf16 products per real product, FP32 accumulation), FP64 refinement"}
     if mixed:
         line["mixed_precision"] = {}
+    fp64_step = main_res["dt"] / args.steps
     for p, mres in mixed.items():
-        mx = {"prec": names[p], "value": mres["transforms"] / mres["dt"],
-              "ms_per_step": 1e3 * mres["dt"] / args.steps, "transforms": mres["transforms"],
-              "job_speedup_vs_fp64": main_res["dt"] / mres["dt"]}
+        step_s = mres["dt"] / args.mixed_steps
+        mx = {"prec": names[p], "value": mres["transforms"] / mres["dt"], "steps": args.mixed_steps,
+              "ms_per_step": 1e3 * step_s, "transforms": mres["transforms"],
+              "job_speedup_vs_fp64": fp64_step / step_s}
         if "alpha" in mres:
-            import numpy as np
-            mx["alpha_rel_err_vs_fp64"] = float(np.linalg.norm(mres["alpha"] - main_res["alpha"]) /
-                                                np.linalg.norm(main_res["alpha"]))
+            mx["alpha_err_vs_fp64_timed"] = alpha_err(mres["alpha"], main_res["alpha"])
+            if ref_alpha is not None:
+                mx["alpha_err_vs_fp64_reference"] = alpha_err(mres["alpha"], ref_alpha)
             mx["solver"] = mres.get("solver")
         if mres["ms"] > 0:
-            mx["ladder_tflops_fp64_equivalent"] = round(mres["fl"] / (mres["ms"] * 1e-3) / 1e12, 3)
+            # launches of the reduced-precision ladder product only (the FP64 residual transforms excluded);
+            # a split-BF16 launch includes splitting the trial vectors
+            mx["ladder_tflops_algorithmic"] = round(mres["fl"] / (mres["ms"] * 1e-3) / 1e12, 3)
             mx["ladder_avg_launch_ms"] = round(mres["ms"] / max(1, mres["nl"]), 4)
         line["mixed_precision"][p] = mx
     def section(name, fn):
@@ -661,9 +857,11 @@ def main():
         section("ground_state", lambda: ground_bench(cc, dev, o, v, args.seed))
     if args.diff and args.mode == "response":
         section("differentiation", lambda: diff_bench(cc, dev))
+    if args.sigma_table and args.mode == "response":
+        section("sigma_table", lambda: sigma_table(cc, dev, o, v, args.seed))
     if not args.no_cpu:
         log("timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(dev)
     print(json.dumps(line), flush=True)
 
 

@@ -90,6 +90,12 @@ typedef struct {
   double resnorm;   /* max relative residual norm ||R||/||rhs|| at exit       */
   double time_ms;   /* wall time of the call                                  */
   long nsigma;      /* number of single-vector Jacobian transforms applied    */
+  double kappa;     /* conditioning estimate of the damped solves: the largest
+                       over right-hand sides of max|theta|/min|theta|, theta
+                       the Ritz values of (A - z) on the final subspace (the
+                       eigenvalues of the projected matrix G'); 0 if none    */
+  double ritz_min;  /* the smallest such |theta|: an estimate of the distance
+                       from z to the spectrum of A (0 if none)               */
 } cclr_solve_info;
 
 /* Fill *opt with the defaults listed above. */

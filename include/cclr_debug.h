@@ -71,9 +71,12 @@ int cclr_dbg_profile(cclr_ctx* ctx, int enable);
 
 /* Launch count, summed duration (ms, from HIP events on the context's
  * stream) and summed algorithmic flops (8 per complex multiply-add) of the
- * ladder GEMM launches recorded since profiling was enabled; with
- * largest_only, only the launches of the largest product (most flops). */
-int cclr_dbg_profile_read(cclr_ctx* ctx, int largest_only, long long* launches, double* ms, double* flops);
+ * ladder GEMM launches recorded since profiling was enabled, those in
+ * arithmetic prec only (CCLR_FP64 ...; -1: all); with largest_only, only the
+ * launches of the largest such product (most flops).  A split-BF16 launch
+ * includes the split of the trial vectors. */
+int cclr_dbg_profile_read(cclr_ctx* ctx, int largest_only, int prec, long long* launches, double* ms,
+                          double* flops);
 
 /* Arithmetic of the ladder and ring products used by subsequent
  * cclr_jacobian_right/left calls on ctx (CCLR_FP64, CCLR_FP32, CCLR_BF16X3,

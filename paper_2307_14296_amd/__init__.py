@@ -39,7 +39,8 @@ class cclr_options(ctypes.Structure):
 
 class cclr_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("resnorm", ctypes.c_double),
-                ("time_ms", ctypes.c_double), ("nsigma", ctypes.c_long)]
+                ("time_ms", ctypes.c_double), ("nsigma", ctypes.c_long), ("kappa", ctypes.c_double),
+                ("ritz_min", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -706,6 +706,9 @@ static int response_impl(cclr_ctx* c, int model, int nx, const cclr_c64* const* 
       info->converged = sinfo.converged && (linfo.iters == 0 || linfo.converged);
       info->resnorm = std::max(sinfo.resnorm, linfo.resnorm);
       info->nsigma = nsig;
+      info->kappa = info->ritz_min = 0.0;
+      merge_conditioning(*info, sinfo);
+      merge_conditioning(*info, linfo);
       info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV) return CCLR_ENOTCONV;
@@ -834,6 +837,8 @@ int cclr_response_function_asym(cclr_ctx* c, int nx, const cclr_c64* const* X, i
       info->converged = rinfo.converged && minfo.converged && (linfo.iters == 0 || linfo.converged);
       info->resnorm = std::max(std::max(rinfo.resnorm, minfo.resnorm), linfo.resnorm);
       info->nsigma = nsig;
+      info->kappa = info->ritz_min = 0.0;
+      for (const cclr_solve_info* x : {&rinfo, &minfo, &linfo}) merge_conditioning(*info, *x);
       info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV || ls == CCLR_ENOTCONV) return CCLR_ENOTCONV;
@@ -975,6 +980,8 @@ int cclr_response_backward(cclr_ctx* c, int nx, const cclr_c64* const* X, int nf
                         (!df || hinfo.converged);
       info->resnorm = std::max(std::max(std::max(sinfo.resnorm, ainfo.resnorm), linfo.resnorm), hinfo.resnorm);
       info->nsigma = nsig;
+      info->kappa = info->ritz_min = 0.0;
+      for (const cclr_solve_info* x : {&sinfo, &ainfo, &linfo, &hinfo}) merge_conditioning(*info, *x);
       info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (rc == CCLR_ENOTCONV || rs == CCLR_ENOTCONV || ra == CCLR_ENOTCONV || (df && !hinfo.converged))

@@ -218,6 +218,7 @@ static void clear_prof(cclr_ctx* c) {
   }
   c->prof_events.clear();
   c->prof_flops.clear();
+  c->prof_prec.clear();
 }
 
 int cclr_dbg_profile(cclr_ctx* c, int enable) {
@@ -228,13 +229,15 @@ int cclr_dbg_profile(cclr_ctx* c, int enable) {
   return CCLR_OK;
 }
 
-int cclr_dbg_profile_read(cclr_ctx* c, int largest_only, long long* launches, double* ms, double* flops) {
+int cclr_dbg_profile_read(cclr_ctx* c, int largest_only, int prec, long long* launches, double* ms, double* flops) {
   if (!c) return CCLR_EINVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return CCLR_EHIP;
   double t = 0.0, f = 0.0, fmax = 0.0;
   long long n = 0;
-  for (double x : c->prof_flops) fmax = std::max(fmax, x);
+  for (size_t k = 0; k < c->prof_events.size(); ++k)
+    if (prec < 0 || c->prof_prec[k] == prec) fmax = std::max(fmax, c->prof_flops[k]);
   for (size_t k = 0; k < c->prof_events.size(); ++k) {
+    if (prec >= 0 && c->prof_prec[k] != prec) continue;
     if (largest_only && c->prof_flops[k] < fmax) continue;
     float x = 0.f;
     if (hipEventElapsedTime(&x, c->prof_events[k].first, c->prof_events[k].second) != hipSuccess) return CCLR_EHIP;

@@ -360,6 +360,7 @@ int ccsd_crop(cclr_ctx* c, double tol, int maxit, int nsub, const VecSet& t, std
     info->converged = conv ? 1 : 0;
     info->resnorm = rn;
     info->nsigma = nres;
+    info->kappa = info->ritz_min = 0.0;
     info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return conv ? CCLR_OK : CCLR_ENOTCONV;

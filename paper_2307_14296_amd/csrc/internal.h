@@ -320,6 +320,7 @@ struct cclr_ctx {
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   std::vector<double> prof_flops;
+  std::vector<int> prof_prec;  // arithmetic of each recorded launch
 
   i64 O2() const { return (i64)o * (o - 1) / 2; }
   i64 V2() const { return (i64)v * (v - 1) / 2; }
@@ -387,6 +388,8 @@ void launch_conj_inplace(i64 n, cplx* x, hipStream_t s);
 // (A - z_k) x_k = -rhs_k (right) or x_k (A - z_k) = -rhs_k (left) in the context's precision
 int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, const VecSet& xout,
                  cclr_solve_info* info);
+// folds the conditioning estimates of src into dst (largest kappa, smallest nonzero Ritz value)
+void merge_conditioning(cclr_solve_info& dst, const cclr_solve_info& src);
 // nvec packed vectors from the arena
 VecSet packed_buf(cclr_ctx* c, int n);
 // how many of n vectors with the given working memory each fit in free device memory (>= 1)

@@ -142,6 +142,7 @@ void timed(cclr_ctx* c, double flops, F&& launch) {
   HIPCHK(hipEventRecord(e1, c->stream));
   c->prof_events.push_back({e0, e1});
   c->prof_flops.push_back(flops);
+  c->prof_prec.push_back(c->sigma_prec);
 }
 
 double gemm_flops(const GemmArgs& g) { return 8.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch; }

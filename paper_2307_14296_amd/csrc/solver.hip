@@ -16,6 +16,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "eigen_small.h"
 
 namespace {
 constexpr int kThreads = 256;
@@ -559,6 +560,29 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
     lincomb(XO, 0, B, 0, msub[r], beta, ms, 1.0, XO, 0, 0, refine ? 1 : 0);
   }
   c->sigma_prec = CCLR_FP64;
+  // conditioning estimate: Ritz values of (A - z) on each final subspace
+  double kappa = 0.0, ritz_min = 0.0;
+  {
+    std::vector<cplx> Gh((size_t)nr * ms * ms);
+    HIPCHK(hipMemcpyAsync(Gh.data(), G, sizeof(cplx) * Gh.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int r = 0; r < nr; ++r) {
+      const int m = msub[r];
+      if (m < 1) continue;
+      std::vector<eigsmall::zc> A((size_t)m * m), w, V;
+      for (int i = 0; i < m; ++i)
+        for (int jj = 0; jj < m; ++jj) {
+          const cplx g = Gh[((size_t)r * ms + i) * ms + jj];
+          A[(size_t)i * m + jj] = eigsmall::zc(g.x, g.y);
+        }
+      if (!eigsmall::eig(m, A, w, V)) continue;
+      double lo = 1e300, hi = 0.0;
+      for (const auto& x : w) lo = std::min(lo, std::abs(x)), hi = std::max(hi, std::abs(x));
+      if (!(lo > 0.0) || !std::isfinite(hi)) continue;
+      kappa = std::max(kappa, hi / lo);
+      ritz_min = ritz_min > 0.0 ? std::min(ritz_min, lo) : lo;
+    }
+  }
   HIPCHK(hipStreamSynchronize(st));
   c->arena.reset(mk);
   int conv = 1;
@@ -573,8 +597,15 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
     info->converged = conv;
     info->nsigma = nsigma;
     info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->kappa = kappa;
+    info->ritz_min = ritz_min;
   }
   return conv ? CCLR_OK : CCLR_ENOTCONV;
+}
+
+void merge_conditioning(cclr_solve_info& dst, const cclr_solve_info& src) {
+  dst.kappa = std::max(dst.kappa, src.kappa);
+  if (src.ritz_min > 0.0) dst.ritz_min = dst.ritz_min > 0.0 ? std::min(dst.ritz_min, src.ritz_min) : src.ritz_min;
 }
 
 // ------------------------------------------------------- precision driver
@@ -616,6 +647,7 @@ int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rh
     all.converged = all.converged && part.converged;
     all.resnorm = std::max(all.resnorm, part.resnorm);
     all.nsigma += part.nsigma;
+    merge_conditioning(all, part);
   }
   all.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = all;
@@ -631,7 +663,6 @@ int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rh
 // Ritz pairs (theta_k, x_k = B y_k), residuals r_k = S y_k - theta_k x_k,
 // corrections (theta_k - D)^-1 r_k orthogonalized twice against the
 // subspace.  When the subspace is full it restarts from the Ritz vectors.
-#include "eigen_small.h"
 
 int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, std::vector<cplx>& omega,
                  const VecSet& xout, cclr_solve_info* info) {
@@ -825,6 +856,7 @@ int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, st
     info->resnorm = mx;
     info->nsigma = nsigma;
     info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->kappa = info->ritz_min = 0.0;
   }
   return conv ? CCLR_OK : CCLR_ENOTCONV;
 }

@@ -159,6 +159,14 @@ def test_response_config1(cfg1):
     rc, out, info = g.cc.cclr_response_function(g.ctx, [dev(X) for X in Xs], [z.real], [z.imag])
     assert rc == 0, info.as_dict()
     assert_alpha(out[0], ref, TOL, "config 1 response function")
+    # conditioning estimate: Ritz values of (A - z) (and of A for lambda) on the
+    # final subspaces; each |theta| is at most ||A - z'||_2 over the solves' z'
+    A = cc.matrix("right")
+    bound = max(np.linalg.norm(A - w * np.eye(A.shape[0]), 2) for w in (z, -z, z.conjugate(), 0.0))
+    dist = min(np.abs(np.linalg.eigvals(A) - w).min() for w in (z, -z, z.conjugate(), -z.conjugate()))
+    print(f"kappa estimate {info.kappa:.3e}, min Ritz {info.ritz_min:.3e}; ||A - z|| <= {bound:.3e}, "
+          f"dist(z, spec A) {dist:.3e}", flush=True)
+    assert info.kappa >= 1.0 and 0.0 < info.ritz_min <= bound and info.kappa * info.ritz_min <= bound * (1 + 1e-12)
 
 
 @pytest.mark.parametrize("zs", [[0.1 + 0.005j], [0.0, 0.3 + 0.01j]])
