@@ -118,23 +118,22 @@ def time_oracle_sigma(H, t1, t2, r, reps, threads=None):
     return statistics.median(ts), t_hbar
 
 
-def cpu_baseline(dev, o=16, v=120, reps=3):
-    """The oracle's right Jacobian transform timed on the host at o=16,
-    v=120 (the largest size whose set-up and transforms take well under a
-    minute of host time; the o=20, v=200 oracle transform, measured on its
-    own with --mode cpu, takes minutes to set up), every core."""
+def cpu_baseline(dev, o, v, seed, reps=2):
+    """The oracle's right Jacobian transform of the benchmark instance timed on
+    the host, every core: a bounded sample of the workload (a warm-up and
+    `reps` timed transforms after the oracle's Hbar build)."""
     ncpu, blas, nthr = host_threads()
-    H, t1, t2, r, _ = oracle_problem(o, v, 2, dev)
+    H, t1, t2, r, _ = oracle_problem(o, v, seed, dev)
     dt, t_hbar = time_oracle_sigma(H, t1, t2, r, reps)
     return {
         "value": 1.0 / dt,
         "unit": "Jacobian transforms/s",
         "cores": nthr,
         "kind": "oracle",
-        "sample": (f"oracle right Jacobian transform (numpy, FP64 complex, {blas}) measured at o={o}, v={v} (not at "
-                   f"o=20, v=200; no scaling): median of {reps} after a warm-up, {dt:.2f} s each, "
-                   f"{sigma_flops(o, v)['total'] / dt / 1e9:.1f} GFLOP/s algorithmic; Hbar build {t_hbar:.1f} s; "
-                   f"{nthr} BLAS threads on {ncpu} cores"),
+        "sample": (f"oracle right Jacobian transform (numpy, FP64 complex, {blas}) of one vector at o={o}, v={v}: "
+                   f"median of {reps} after a warm-up, {dt:.2f} s each, "
+                   f"{sigma_flops(o, v)['total'] / dt / 1e9:.1f} GFLOP/s algorithmic (the oracle's Hbar build, "
+                   f"{t_hbar:.1f} s, not counted); {nthr} BLAS threads on {ncpu} cores"),
     }
 
 
@@ -609,6 +608,8 @@ def main():
     ap.add_argument("--mixed-precs", default="fp32,bf16x3,bf16x2",
                     help="comma list of reduced precisions to run after the FP64 run")
     ap.add_argument("--mixed-steps", type=int, default=5, help="timed steps of each reduced-precision run")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x3", "bf16x2"], default="fp64",
+                    help="arithmetic of the main (reported) run; anything but fp64 is for profiling only")
     ap.add_argument("--tight-tol", type=float, default=1e-11,
                     help="tolerance of the untimed FP64 reference solve that the alpha errors are measured against")
     ap.add_argument("--no-sigma-table", dest="sigma_table", action="store_false",
@@ -748,7 +749,8 @@ def main():
         log(f"copy probe: {nel * 16 / (1 << 30):.3f} GiB read + written")
         del a, b
         torch.cuda.empty_cache()
-    main_res = run("fp64", args.steps, args.warmup, tight_tol=args.tight_tol if args.mode == "response" else None)
+    main_res = run(args.prec, args.steps, args.warmup,
+                   tight_tol=args.tight_tol if args.mode == "response" and args.prec == "fp64" else None)
     mixed = {}
     if args.mixed:
         for p in [x for x in args.mixed_precs.split(",") if x]:
@@ -861,7 +863,7 @@ def main():
         section("sigma_table", lambda: sigma_table(cc, dev, o, v, args.seed))
     if not args.no_cpu:
         log("timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline(dev)
+        line["cpu_baseline"] = cpu_baseline(dev, o, v, args.seed)
     print(json.dumps(line), flush=True)
 
 
