@@ -111,6 +111,12 @@ int cclr_dbg_set_overlap(cclr_ctx* ctx, int enable);
  * Negative values are CCLR_EINVAL. */
 int cclr_dbg_set_blocking(cclr_ctx* ctx, long long wp_block, int rhs_group);
 
+/* Hessian products (t^X F) of nvec response vectors with the context's
+ * amplitudes and lambda (cclr_solve_lambda first; CCLR_ESTATE otherwise):
+ * x1 [nvec][o][v], x2 [nvec][o][o][v][v] in (only unique doubles read), s1,
+ * s2 the same layouts out (full antisymmetric doubles); device pointers. */
+int cclr_dbg_hessian(cclr_ctx* ctx, int nvec, const cclr_c64* x1, const cclr_c64* x2, cclr_c64* s1, cclr_c64* s2);
+
 /* Bytes of the fixed work space that the context's last
  * cclr_jacobian_right_noalloc call took at most (0 before the first). */
 int cclr_dbg_fixed_ws_peak(const cclr_ctx* ctx, long long* bytes);

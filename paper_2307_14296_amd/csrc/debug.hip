@@ -292,6 +292,25 @@ int cclr_dbg_set_blocking(cclr_ctx* c, long long wp_block, int rhs_group) {
   return CCLR_OK;
 }
 
+int cclr_dbg_hessian(cclr_ctx* c, int nvec, const cclr_c64* x1, const cclr_c64* x2, cclr_c64* s1, cclr_c64* s2) {
+  if (!c || nvec < 1 || !x1 || !x2 || !s1 || !s2) return CCLR_EINVAL;
+  if (!c->have_t || !c->have_lam) return CCLR_ESTATE;
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    Arena::Mark mk = c->arena.mark();
+    VecSet in = packed_buf(c, nvec), out = packed_buf(c, nvec);
+    launch_pack_full(nvec, c->o, c->v, (const cplx*)x1, (const cplx*)x2, in.s, in.d, c->stream);
+    hessian_product(c, in, out);
+    launch_unpack(nvec, c->o, c->v, out.s, out.d, (cplx*)s1, (cplx*)s2, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->arena.reset(mk);
+  } catch (const CclrError& e) {
+    c->err = e.what();
+    return e.code;
+  }
+  return CCLR_OK;
+}
+
 int cclr_dbg_fixed_ws_peak(const cclr_ctx* c, long long* bytes) {
   if (!c || !bytes) return CCLR_EINVAL;
   *bytes = (long long)c->fixed_ws_peak;

@@ -137,7 +137,7 @@ void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
 static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
   const i64 o = c->o, v = c->v, nv = xin.n;
   Arena::Mark mk = c->arena.mark();
-  const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5), qtr = cx(0.25), mqtr = cx(-0.25);
+  const cplx one = cx(1.0), mone = cx(-1.0), half = cx(0.5), mhalf = cx(-0.5), qtr = cx(0.25);
   Ten t2 = ten(c->t2, {o, o, v, v});
   Ten Fov = ten(c->Fov, {o, v});
   Ten Woooo = ten(c->Woooo, {o, o, o, o}), Wovvo = ten(c->Wovvo, {o, v, v, o});
@@ -146,6 +146,14 @@ static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
   Ten l1 = ten(c->lam_s, {o, v});
   Ten l2 = tmp(c, {o, o, v, v});
   launch_unpack(1, (int)o, (int)v, c->lam_s.c(), c->lam_d.c(), nullptr, l2.p, c->stream);
+  // operands of the products over unique pairs: lambda^IJ_ea for i > j ([IJ][e][a]),
+  // W^ek_AB for a > b ([e][k][AB]) and the packed doubles of the vectors ([Z][IJ][AB])
+  const i64 O2 = c->O2(), V2 = c->V2();
+  Ten lamH = tmp(c, {O2, v, v});
+  launch_pack_first_pair(1, (int)o, v * v, l2.p, lamH.p, c->stream);
+  Ten WvP = tmp(c, {v, o, V2});
+  launch_pack_pairs(v * o, (int)v, c->Wvovv.c(), WvP.p, c->stream);
+  Ten xp2 = ten(xin.d, {nv, O2, V2});
   // lambda-only pieces
   Ten LW = tmp(c, {o, o, v, v});
   {
@@ -246,12 +254,13 @@ static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
     Ten Z5 = tmp(c, {nv, o, v, o, v});  // [Z][k][e][j][a] = lambda^ik_eb x^ab_ij
     contract(c, one, l2, "ikeb", x2, "Zijab", Z5, "Zkeja", false);
     contract(c, mone, Z5, "Zkeja", Wvovv, "ejac", s, "Zkc");               // 21
-    Ten Z6 = tmp(c, {nv, o, v, o, v});  // [Z][m][c][i][b] = lambda^mj_ac x^ab_ij
-    contract(c, one, l2, "mjac", x2, "Zijab", Z6, "Zmcib", false);
-    contract(c, one, Z6, "Zmcib", Wooov, "ikmb", s, "Zkc");                // 22
-    Ten Z7 = tmp(c, {nv, o, o, v, o});  // [Z][i][j][e][k] = W^ek_ab x^ab_ij
-    contract(c, one, Wvovv, "ekab", x2, "Zijab", Z7, "Zijek", false);
-    contract(c, mqtr, l2, "ijec", Z7, "Zijek", s, "Zkc");                  // 23
+    // lambda^mj_ac x^ab_ij = lambda^jm_ca x^ba_ji is the same array, read as [Z][m][c][i][b]
+    contract(c, one, Z5, "Zmcib", Wooov, "ikmb", s, "Zkc");                // 22
+    // -1/4 lambda^ij_ec W^ek_ab x^ab_ij over the unique pairs i > j, a > b (every factor
+    // antisymmetric in them): Z7[Z][IJ][e][k] = sum_(a>b) W^ek_ab x^ab_ij
+    Ten Z7 = tmp(c, {nv, O2, v, o});
+    contract(c, one, WvP, "ekQ", xp2, "ZIQ", Z7, "ZIek", false);
+    contract(c, mone, lamH, "Iec", Z7, "ZIek", s, "Zkc");                  // 23
     Ten Z8 = tmp(c, {nv, o, o, o, o});  // [Z][m][k][i][j] = lambda^mk_ab x^ab_ij
     contract(c, one, l2, "mkab", x2, "Zijab", Z8, "Zmkij", false);
     contract(c, qtr, Z8, "Zmkij", Wooov, "ijmc", s, "Zkc");                // 24
@@ -273,18 +282,9 @@ static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
   contract(c, one, l2, "klce", Qec, "Zed", Xa, "Zklcd");                   // 6
   contract(c, mone, l2, "kmcd", Qkm, "Zlm", Xi, "Zklcd");                  // 7
   {
-    Ten Z = tmp(c, {nv, o, o, v, v});  // [Z][k][m][d][a] = W^ki_md x^a_i
-    contract(c, one, Wooov, "kimd", x1, "Zia", Z, "Zkmda", false);
-    contract(c, one, l2, "mlca", Z, "Zkmda", Xai, "Zklcd");                // 8
     Ten Zp = tmp(c, {nv, o, o, o, o});  // [Z][k][l][m][i] = W^kl_ma x^a_i
     contract(c, one, Wooov, "klma", x1, "Zia", Zp, "Zklmi", false);
     contract(c, one, l2, "micd", Zp, "Zklmi", X0, "Zklcd");                // 9
-    Ten Zpp = tmp(c, {nv, v, o, v, o});  // [Z][e][l][c][i] = W^el_ca x^a_i
-    contract(c, one, Wvovv, "elca", x1, "Zia", Zpp, "Zelci", false);
-    contract(c, mone, l2, "kied", Zpp, "Zelci", Xai, "Zklcd");             // 10
-    Ten L = tmp(c, {nv, o, o, v, o});  // [Z][k][l][e][i] = lambda^kl_ea x^a_i
-    contract(c, one, l2, "klea", x1, "Zia", L, "Zklei", false);
-    contract(c, mone, L, "Zklei", Wvovv, "eicd", X0, "Zklcd");             // 11
   }
   contract(c, mhalf, l2, "klca", Y3ca, "Zda", Xa, "Zklcd");                // 12
   contract(c, mhalf, l2, "kicd", Y2ki, "Zli", Xi, "Zklcd");                // 13
@@ -295,13 +295,26 @@ static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
     Ten N = tmp(c, {nv, o, o, o, o});  // [Z][k][l][i][j] = lambda^kl_ab x^ab_ij
     contract(c, one, l2, "klab", x2, "Zijab", N, "Zklij", false);
     contract(c, qtr, N, "Zklij", Vv, "ijcd", X0, "Zklcd");                 // 15
-    Ten Z = tmp(c, {nv, o, v, o, v});  // [Z][l][d][j][b] = V^li_da x^ab_ij
-    contract(c, one, Vv, "lida", x2, "Zijab", Z, "Zldjb", false);
-    contract(c, one, l2, "kjcb", Z, "Zldjb", Xai, "Zklcd");                // 16
+    // terms 8, 10 and 16 under P(kl)P(cd) as one product lambda^ky_cw T[l][d][y][w]
+    // (8 read with k and l exchanged, 10 with c and d exchanged, each a sign):
+    //   T[l][d][y][w] = V^li_da x^aw_iy (16) + W^li_yd x^w_i (8) - W^wl_da x^a_y (10)
+    Ten T = tmp(c, {nv, o, v, o, v});
+    contract(c, one, Vv, "lida", x2, "Zijab", T, "Zldjb", false);          // 16: V^li_da x^ab_ij
+    contract(c, one, Wooov, "liyd", x1, "Ziw", T, "Zldyw");                // 8
+    contract(c, mone, Wvovv, "wlda", x1, "Zya", T, "Zldyw");               // 10
+    contract(c, one, l2, "kycw", T, "Zldyw", Xai, "Zklcd");                // 8 + 10 + 16
   }
   contract(c, mhalf, Z4kj, "Zkj", Vv, "jlcd", Xi, "Zklcd");                // 17
   contract(c, mhalf, Z3cb, "Zcb", Vv, "klbd", Xa, "Zklcd");                // 18
   finish(c, G, nv, out);
+  // term 11, -lambda^kl_ea x^a_i W^ei_cd, has no permutation operator: only its
+  // unique pairs k > l, c > d enter the result, so it is added to the packed
+  // doubles directly: out[KL][CD] -= sum_(e,i) Lp[KL][e][i] W^ei_CD
+  {
+    Ten Lp = tmp(c, {nv, O2, v, o});  // [Z][KL][e][i] = lambda^kl_ea x^a_i  (k > l)
+    contract(c, one, lamH, "Kea", x1, "Zia", Lp, "ZKei", false);
+    contract(c, mone, Lp, "ZKei", WvP, "eiC", ten(out.d, {nv, O2, V2}), "ZKC");  // 11
+  }
   c->arena.reset(mk);
 }
 
