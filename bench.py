@@ -704,7 +704,7 @@ def main():
         L.cclr_dbg_tuning(ctx, -1, buf, len(buf))
         res["gemm_tuning"] = [ln for ln in buf.value.decode().splitlines() if ln]
         cc.cclr_destroy(ctx)
-        if tight_tol is not None and args.mode == "response":
+        if tight_tol and args.mode == "response":
             # untimed FP64 reference solved to the tight tolerance
             opt.tol = tight_tol
             opt.prec = cc.CCLR_FP64

@@ -127,6 +127,18 @@ static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out);
 // t^X F for several vectors, in groups whose temporaries fit in device memory
 void hessian_product(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
   const i64 ov = c->ns(), nd = c->nd(), oovv = (i64)c->o * c->o * c->v * c->v;
+  // In the reduced-precision modes the bulk products of t^X F run on FP32 MFMA
+  // (not split-BF16: the product enters the response function directly, with
+  // no refinement after it, so it keeps about 1e-7 relative accuracy); the
+  // FP64 mode stays FP64.
+  struct Prec {
+    cclr_ctx* c;
+    int keep;
+    Prec(cclr_ctx* c_) : c(c_), keep(c_->sigma_prec) {
+      if (c->opt.prec != CCLR_FP64) c->sigma_prec = CCLR_FP32;
+    }
+    ~Prec() { c->sigma_prec = keep; }
+  } prec(c);
   const int chunk = fit_vectors(c, 10.0 * (double)oovv * sizeof(cplx) + 2.0 * (ov + nd) * sizeof(cplx), xin.n);
   for (int k0 = 0; k0 < xin.n; k0 += chunk) {
     const int n = std::min(chunk, xin.n - k0);
