@@ -47,9 +47,12 @@ int cclr_dbg_run_gemm(cclr_ctx* ctx, int M, int N, int K, int batch, const cclr_
                       int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double alpha_re,
                       double alpha_im, int beta);
 
-/* The same product (batch 1) in reduced arithmetic: prec = CCLR_FP32 (FP32
- * MFMA), CCLR_BF16X3 or CCLR_BF16X2 (split-BF16 MFMA, FP32 accumulation);
- * operands and C stay complex128. */
+/* The same product (batch 1) in reduced arithmetic on pre-split operands, the
+ * form of the transforms' ladder and ring products: prec = CCLR_FP32 (FP32
+ * MFMA, three real products per complex block), CCLR_BF16X3 or CCLR_BF16X2
+ * (split-BF16 MFMA, FP32 accumulation); prec = 16: the engine's FP32 kernel
+ * of the other products (complex128 operands converted in the kernel).
+ * Operands and C stay complex128. */
 int cclr_dbg_zgemm_lowp(int prec, int M, int N, int K, const cclr_c64* A, long long sAm, long long sAk, int conjA,
                         const cclr_c64* B, long long sBk, long long sBn, int conjB, cclr_c64* C, long long sCm,
                         long long sCn, double alpha_re, double alpha_im, int beta);

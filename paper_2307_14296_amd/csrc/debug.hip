@@ -124,15 +124,16 @@ int cclr_dbg_zgemm_lowp(int prec, int M, int N, int K, const cclr_c64* A, long l
     g.B = (const cplx*)B; g.sBk = sBk; g.sBn = sBn; g.conjB = conjB;
     g.C = (cplx*)C; g.sCm = sCm; g.sCn = sCn;
     g.ar = ar; g.ai = ai; g.beta = beta;
-    if (prec == CCLR_BF16X3 || prec == CCLR_BF16X2) {
-      const int form = bf16_form_of(prec);
+    if (prec == CCLR_FP32 || prec == CCLR_BF16X3 || prec == CCLR_BF16X2) {
+      const int form = split_form_of(prec);
       HIPCHK(hipMalloc(&wa, split_bytes(M, K, form, 0)));
       HIPCHK(hipMalloc(&wb, split_bytes(N, K, form, 1)));
-      const SplitMat sa = launch_split_bf16(M, K, g.A, sAm, sAk, conjA, wa, form, 0, nullptr);
-      const SplitMat sb = launch_split_bf16(N, K, g.B, sBn, sBk, conjB, wb, form, 1, nullptr);
-      launch_cgemm_bf16(sa, sb, g.C, sCm, sCn, ar, ai, beta, nullptr);
+      const SplitMat sa = launch_split(M, K, g.A, sAm, sAk, conjA, wa, form, 0, nullptr);
+      const SplitMat sb = launch_split(N, K, g.B, sBn, sBk, conjB, wb, form, 1, nullptr);
+      launch_split_gemm(sa, sb, g.C, sCm, sCn, ar, ai, beta, nullptr);
     } else {
-      launch_zgemm_lowp(g, prec, nullptr);
+      REQUIRE(prec == 16, CCLR_EINVAL, "unknown arithmetic");
+      launch_zgemm_lowp(g, CCLR_FP32, nullptr);
     }
     HIPCHK(hipDeviceSynchronize());
   } catch (const CclrError& e) {

@@ -1,5 +1,7 @@
-// Split-BF16 complex GEMM for the low-precision inner solves.
+// Complex GEMMs on pre-split operands for the reduced-precision inner
+// solves: split-BF16 (below) and FP32 Gauss planes (after it).
 //
+// Split-BF16.
 // Every real component x of a complex128 operand is split into bf16 numbers,
 // hi = bf16(x) and lo = bf16(x - hi), so x = hi + lo to about 2^-17
 // relative.  A real product of two split operands is formed from three bf16
@@ -247,6 +249,150 @@ __global__ __launch_bounds__(512) void k_cgemm_bf16s(const u4v* __restrict__ As,
 }
 #undef MF
 
+// ---------------------------------------------------------------- FP32 form
+// Three real products per complex block (Gauss): k1 = (Ar + Ai) Br,
+// k2 = Ar (Bi - Br), k3 = Ai (Br + Bi), Re = k1 - k3, Im = k1 + k2, on
+// v_mfma_f32_16x16x4f32 with FP32 accumulation.  Split layout: [K/16][rows_pad]
+// [12] 16-byte chunks; logical chunk c = 4p + g of a row holds the four FP32
+// values k = 16 kb + 4g ... + 3 of plane p (A: Ar + Ai, Ar, Ai; B: Br,
+// Bi - Br, Br + Bi), stored at position (c + (r / 4) mod 4) mod 12, which
+// puts one chunk of 16 consecutive rows in 16 different bank groups.  A lane
+// reads its four k values with one 16-byte read and feeds them to the four
+// MFMAs of the k-step (lane group g takes k = 4g + s in MFMA s: the k order
+// within the step is the same on both operands, so the sum is unchanged).
+__host__ __device__ constexpr int f32pos(int r, int c) { return (c + ((r >> 2) & 3)) % 12; }
+
+__global__ __launch_bounds__(256) void k_split_f32(int rows, int K, const cplx* __restrict__ src, i64 sR, i64 sK,
+                                                   int conj, int side, u4v* __restrict__ dst, int rows_pad, int nkb,
+                                                   int rows_fast) {
+  const i64 units = (i64)rows_pad * nkb * 4;
+  const double si = conj ? -1.0 : 1.0;
+  for (i64 u = blockIdx.x * (i64)blockDim.x + threadIdx.x; u < units; u += (i64)gridDim.x * blockDim.x) {
+    i64 r, kb;
+    int g;
+    if (rows_fast) {
+      r = u % rows_pad;
+      const i64 q = u / rows_pad;
+      g = (int)(q & 3);
+      kb = q >> 2;
+    } else {
+      g = (int)(u & 3);
+      const i64 q = u >> 2;
+      r = q % rows_pad;
+      kb = q / rows_pad;
+    }
+    float pl[3][4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const i64 k = kb * 16 + g * 4 + e;
+      cplx x = (r < rows && k < K) ? src[r * sR + k * sK] : make_double2(0.0, 0.0);
+      const double re = x.x, im = si * x.y;
+      if (side == 0) {
+        pl[0][e] = (float)(re + im);
+        pl[1][e] = (float)re;
+        pl[2][e] = (float)im;
+      } else {
+        pl[0][e] = (float)re;
+        pl[1][e] = (float)(im - re);
+        pl[2][e] = (float)(re + im);
+      }
+    }
+    u4v* o = dst + (kb * rows_pad + r) * 12;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      o[f32pos((int)r, 4 * p + g)] =
+          u4v{__float_as_uint(pl[p][0]), __float_as_uint(pl[p][1]), __float_as_uint(pl[p][2]), __float_as_uint(pl[p][3])};
+  }
+}
+
+// C[m][n] (+)= alpha * sum_k A[m][k] B[n][k] on FP32 split operands: the
+// pipeline of k_cgemm_bf16s (128 x 128 tiles of eight 64 x 32 waves, direct
+// loads one 16-deep k step ahead into the other of two LDS stages).
+__global__ __launch_bounds__(512) void k_cgemm_f32s(const u4v* __restrict__ As, const u4v* __restrict__ Bs, int Mpad,
+                                                    int Npad, int nkb, int M, int N, cplx* __restrict__ C, i64 sCm,
+                                                    i64 sCn, double ar, double ai, int beta, int Mt, int T) {
+  constexpr int RS = 12, NT = 512, WM = TM / 2, WN = TM / 4, FM = WM / 16, FN = WN / 16;
+  constexpr int CH = TM * RS;  // chunks per tile and k step
+  static_assert(CH % NT == 0, "tiles must be whole rounds of direct loads");
+  __shared__ u4v sA0[CH], sA1[CH];
+  __shared__ u4v sB0[CH], sB1[CH];
+  const int per = gridDim.x >> 3;
+  const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (t >= T) return;
+  const int m0 = (t % Mt) * TM, n0 = (t / Mt) * TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const int rr = lane & 15, g = lane >> 4;
+  auto fetch = [&](int kb, u4v* la, u4v* lb) {
+    dma_tile<NT, CH>(As + ((i64)kb * Mpad + m0) * RS, la, tid);
+    dma_tile<NT, CH>(Bs + ((i64)kb * Npad + n0) * RS, lb, tid);
+  };
+  // the rotation depends on the row only through rr (wm, wn and 16 i are multiples of 16)
+  int off[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) off[p] = rr * RS + f32pos(rr, 4 * p + g);
+  f4 acc[3][FM][FN];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[a][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto step = [&](int kb, const u4v* ca, const u4v* cb, u4v* na, u4v* nb) {
+    fetch(kb + 1 < nkb ? kb + 1 : kb, na, nb);
+    __builtin_amdgcn_sched_barrier(0);  // the loads are requested first, not scheduled between the MFMAs
+    f4 b[FN][3];
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) b[j][p] = __builtin_bit_cast(f4, cb[(wn + 16 * j) * RS + off[p]]);
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      f4 a[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) a[p] = __builtin_bit_cast(f4, ca[(wm + 16 * i) * RS + off[p]]);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p][s], b[j][p][s], acc[p][i][j], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  fetch(0, sA0, sB0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int kb = 0; kb < nkb; kb += 2) {
+    step(kb, sA0, sB0, sA1, sB1);
+    if (kb + 1 < nkb) step(kb + 1, sA1, sB1, sA0, sB0);
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * g + r;
+        const int n = n0 + wn + 16 * j + rr;
+        if (m < M && n < N) {
+          const double k1 = acc[0][i][j][r], k2 = acc[1][i][j][r], k3 = acc[2][i][j][r];
+          const double xr = k1 - k3, xi = k1 + k2;
+          cplx y = make_double2(ar * xr - ai * xi, ar * xi + ai * xr);
+          cplx* dst = C + (i64)m * sCm + (i64)n * sCn;
+          if (beta) {
+            const cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
 template <int P>
 void launch_split_p(const SplitMat& s, const cplx* src, i64 sR, i64 sK, int conj, hipStream_t st) {
   const i64 units = (i64)s.rows_pad * s.nkc * 4;
@@ -258,42 +404,58 @@ void launch_split_p(const SplitMat& s, const cplx* src, i64 sR, i64 sK, int conj
 }
 }  // namespace
 
-bool bf16_form_valid(int form) { return form == BF16_X3 || form == BF16_X2; }
+bool split_form_valid(int form) { return form == BF16_X3 || form == BF16_X2 || form == F32_G3; }
 
-int bf16_form_of(int prec) { return prec == CCLR_BF16X2 ? BF16_X2 : BF16_X3; }
+int split_form_of(int prec) { return prec == CCLR_FP32 ? F32_G3 : prec == CCLR_BF16X2 ? BF16_X2 : BF16_X3; }
 
 SplitMat split_shape(int rows, int K, int form, int side) {
-  REQUIRE(bf16_form_valid(form), CCLR_EINVAL, "split: unknown split-BF16 form");
-  const FormDesc& d = kForms[form];
+  REQUIRE(split_form_valid(form), CCLR_EINVAL, "split: unknown form");
   SplitMat s;
   s.rows = rows;
   s.K = K;
   s.rows_pad = (rows + TM - 1) / TM * TM;
-  s.nkc = (K + 31) / 32;
   s.form = form;
   s.side = side;
+  if (form == F32_G3) {
+    s.nkc = (K + 15) / 16;
+    s.nplanes = 3;
+    s.chunks = 12;
+    return s;
+  }
+  const FormDesc& d = kForms[form];
+  s.nkc = (K + 31) / 32;
   s.nplanes = side == 0 ? d.pa : d.pb;
+  s.chunks = 4 * s.nplanes;
   for (int p = 0; p < 4; ++p) s.planes[p] = p < s.nplanes ? (side == 0 ? d.planes_a[p] : d.planes_b[p]) : 0;
   return s;
 }
 
 size_t split_bytes(int rows, int K, int form, int side) {
   const SplitMat s = split_shape(rows, K, form, side);
-  return (size_t)s.rows_pad * (size_t)s.nkc * (size_t)(4 * s.nplanes) * 16;
+  return (size_t)s.rows_pad * (size_t)s.nkc * (size_t)s.chunks * 16;
 }
 
-SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, int form, int side,
-                           hipStream_t st) {
+SplitMat launch_split(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, int form, int side,
+                      hipStream_t st) {
   REQUIRE(rows > 0 && K > 0, CCLR_EINVAL, "split: empty operand");
   SplitMat s = split_shape(rows, K, form, side);
   s.p = dst;
-  if (s.nplanes == 4) launch_split_p<4>(s, src, sR, sK, conj, st);
-  else launch_split_p<2>(s, src, sR, sK, conj, st);
+  if (form == F32_G3) {
+    const i64 units = (i64)s.rows_pad * s.nkc * 4;
+    i64 grid = (units + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_split_f32, dim3((unsigned)grid), dim3(256), 0, st, rows, K, src, sR, sK, conj, side,
+                       (u4v*)dst, s.rows_pad, s.nkc, sR == 1 ? 1 : 0);
+  } else if (s.nplanes == 4) {
+    launch_split_p<4>(s, src, sR, sK, conj, st);
+  } else {
+    launch_split_p<2>(s, src, sR, sK, conj, st);
+  }
   HIPCHK(hipGetLastError());
   return s;
 }
 
-void launch_cgemm_bf16(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
+void launch_split_gemm(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
                        int beta, hipStream_t st) {
   REQUIRE(A.p && B.p, CCLR_EINVAL, "split GEMM: operand not split");
   REQUIRE(A.form == B.form && A.side == 0 && B.side == 1, CCLR_EINVAL, "split GEMM: operands of different forms");
@@ -302,7 +464,10 @@ void launch_cgemm_bf16(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i
   const i64 T = (i64)Mt * Nt;
   REQUIRE(T < (i64)1 << 30, CCLR_EINVAL, "split GEMM: too many tiles");
   const i64 grid = (T + 7) / 8 * 8;
-  if (A.form == BF16_X2)
+  if (A.form == F32_G3)
+    hipLaunchKernelGGL(k_cgemm_f32s, dim3((unsigned)grid), dim3(512), 0, st, (const u4v*)A.p, (const u4v*)B.p,
+                       A.rows_pad, B.rows_pad, A.nkc, A.rows, B.rows, C, sCm, sCn, ar, ai, beta, Mt, (int)T);
+  else if (A.form == BF16_X2)
     hipLaunchKernelGGL((k_cgemm_bf16s<BF16_X2>), dim3((unsigned)grid), dim3(512), 0, st, (const u4v*)A.p,
                        (const u4v*)B.p, A.rows_pad, B.rows_pad, A.nkc, A.rows, B.rows, C, sCm, sCn, ar, ai, beta, Mt,
                        (int)T);

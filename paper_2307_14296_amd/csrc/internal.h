@@ -143,27 +143,30 @@ int gemm_tile_cols(int variant);
 // the same product with FP32 (prec = CCLR_FP32) or split-BF16 (CCLR_BF16X3)
 // MFMA arithmetic and FP32 accumulation; operands and C stay complex128 in memory
 void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s);
-// Split-BF16 products (gemm_bf16.hip): three (X3: both operands split
-// hi + lo) or two (X2: the B operand hi only) bf16 products per real product.
-enum { BF16_X3 = 0, BF16_X2 = 1 };
-bool bf16_form_valid(int form);
-int bf16_form_of(int prec);  // prec CCLR_BF16X3 or CCLR_BF16X2
+// Products on pre-split operands (gemm_split.hip): split-BF16 with three (X3:
+// both operands split hi + lo) or two (X2: the B operand hi only) bf16
+// products per real product, and FP32 Gauss planes (three real products per
+// complex block).
+enum { BF16_X3 = 0, BF16_X2 = 1, F32_G3 = 2 };
+bool split_form_valid(int form);
+int split_form_of(int prec);  // prec CCLR_FP32, CCLR_BF16X3 or CCLR_BF16X2
 // A split operand of one form and side (0: A, the rows of C; 1: B, the
-// columns): a rows x K complex matrix as [K/32][rows_pad][4*nplanes]
-// 16-byte chunks of bf16 planes (codes in planes[]), swizzled, zero padded.
+// columns): a rows x K complex matrix as [K/kstep][rows_pad][chunks] 16-byte
+// chunks of planes (bf16: kstep 32, codes in planes[]; FP32: kstep 16, three
+// planes), position-permuted within a row, zero padded.
 struct SplitMat {
   const void* p = nullptr;
   int rows = 0, K = 0, rows_pad = 0, nkc = 0;
-  int form = 0, side = 0, nplanes = 0;
+  int form = 0, side = 0, nplanes = 0, chunks = 0;
   int planes[4] = {0, 0, 0, 0};
 };
 SplitMat split_shape(int rows, int K, int form, int side);
 size_t split_bytes(int rows, int K, int form, int side);
 // dst <- split of op(src)[r][k] = src[r*sR + k*sK] (conjugated if conj)
-SplitMat launch_split_bf16(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, int form, int side,
-                           hipStream_t s);
+SplitMat launch_split(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj, void* dst, int form, int side,
+                      hipStream_t s);
 // C[m][n] (+)= alpha * sum_k A[m][k] B[n][k] on operands split for one form, FP32 accumulation
-void launch_cgemm_bf16(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
+void launch_split_gemm(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
                        int beta, hipStream_t s);
 // products with K <= 32 on the vector ALU (returns false if the form does not apply)
 bool launch_zgemm_smallk(const GemmArgs& g, hipStream_t s);

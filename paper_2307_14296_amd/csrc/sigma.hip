@@ -39,33 +39,28 @@ SigmaAcc prepare(cclr_ctx* c, const VecSet& in, bool xi_vpacked) {
 
 // Product with one of the Jacobian's large operators (B side of g: 0 right
 // ladder, 1 left ladder, 2 right ring, 3 left ring) in the arithmetic of the
-// transforms being applied.  Split-BF16 keeps a split copy of the operator,
-// made on first use; the trial-vector side is split per product.
+// transforms being applied.  FP32 and split-BF16 keep a split copy of the
+// operator, made on first use; the trial-vector side is split per product.
 void op_gemm(cclr_ctx* c, const GemmArgs& g, int which) {
   if (c->sigma_prec == CCLR_FP64) {
     if (which < 2) tuned_gemm(c, g);
     else run_gemm(c, g);
     return;
   }
-  if (c->sigma_prec == CCLR_FP32) {
-    launch_zgemm_lowp(g, CCLR_FP32, c->stream);
-    return;
-  }
-  REQUIRE((c->sigma_prec == CCLR_BF16X3 || c->sigma_prec == CCLR_BF16X2) && g.batch == 1 && g.kchunk == 0,
-          CCLR_EINVAL, "unsupported product form");
-  const int form = bf16_form_of(c->sigma_prec);
+  REQUIRE(g.batch == 1 && g.kchunk == 0, CCLR_EINVAL, "unsupported product form");
+  const int form = split_form_of(c->sigma_prec);
   SplitMat& W = c->wsplit_m[which];
   if (!W.p || W.form != form) {
     c->wsplit_m[which] = SplitMat{};
     c->wsplit[which].release();
     c->wsplit[which].alloc(c, split_bytes(g.N, g.K, form, 1));
-    W = launch_split_bf16(g.N, g.K, g.B, g.sBn, g.sBk, g.conjB, c->wsplit[which].p, form, 1, c->stream);
+    W = launch_split(g.N, g.K, g.B, g.sBn, g.sBk, g.conjB, c->wsplit[which].p, form, 1, c->stream);
   }
   REQUIRE(W.rows == g.N && W.K == g.K, CCLR_EINVAL, "split operator has another shape");
   Arena::Mark mk = c->arena.mark();
   void* ws = c->arena.get(split_bytes(g.M, g.K, form, 0));
-  const SplitMat A = launch_split_bf16(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, ws, form, 0, c->stream);
-  launch_cgemm_bf16(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
+  const SplitMat A = launch_split(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, ws, form, 0, c->stream);
+  launch_split_gemm(A, W, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
   c->arena.reset(mk);
 }
 

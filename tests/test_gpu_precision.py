@@ -52,9 +52,11 @@ def cfg1():
 GEMM_CASES = [(1, 1, 1, 0, 0), (17, 33, 5, 1, 0), (130, 3, 129, 0, 1), (200, 260, 300, 1, 1), (300, 257, 1000, 0, 0),
               (600, 530, 70, 0, 0), (1030, 600, 200, 1, 1), (520, 700, 33, 1, 0)]
 PRECS = {"fp32": (1, 1e-5, 1e-5), "bf16x3": (2, 5e-5, 1e-4), "bf16x2": (3, 3e-3, 3e-3)}
+# the engine's FP32 kernel of the remaining products (complex128 operands converted in the kernel)
+GEMM_PRECS = {**PRECS, "fp32_engine": (16, 1e-5, None)}
 
 
-@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("prec", list(GEMM_PRECS))
 @pytest.mark.parametrize("M,N,K,ta,tb", GEMM_CASES)
 def test_lowp_gemm(cfg1, prec, M, N, K, ta, tb):
     import paper_2307_14296_amd as cc
@@ -62,7 +64,7 @@ def test_lowp_gemm(cfg1, prec, M, N, K, ta, tb):
     P, LL = ctypes.c_void_p, ctypes.c_longlong
     L.cclr_dbg_zgemm_lowp.argtypes = [ctypes.c_int] * 4 + [P, LL, LL, ctypes.c_int, P, LL, LL, ctypes.c_int,
                                                           P, LL, LL, ctypes.c_double, ctypes.c_double, ctypes.c_int]
-    code, gemm_bar, _ = PRECS[prec]
+    code, gemm_bar, _ = GEMM_PRECS[prec]
     rng = np.random.default_rng(M + 7 * N + 13 * K)
     A = rng.normal(size=(M, K)) + 1j * rng.normal(size=(M, K))
     B = rng.normal(size=(K, N)) + 1j * rng.normal(size=(K, N))
