@@ -125,7 +125,9 @@ int cclr_dbg_hessian(cclr_ctx* ctx, int nvec, const cclr_c64* x1, const cclr_c64
 int cclr_dbg_fixed_ws_peak(const cclr_ctx* ctx, long long* bytes);
 
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
- * GEMM shape class: "MxNxK bB layoutL: variant=ms ... -> chosen" (chosen is
+ * GEMM shape class: "MxNxK bB layoutL timed mxNxK bb: variant=ms ... -> chosen"
+ * (the product's shape, then the part of it that was timed: at most 8192 rows
+ * and 16 batch entries, so the times are those of the timed part; chosen is
  * the variant in use: within 2% of the fastest, the grouped tile order, then
  * larger tiles, are preferred).
  * enable >= 0 switches tuning on (1) or off (0) for later products. */

@@ -704,8 +704,11 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   c->gemm_choice[key] = best;
   std::vector<std::pair<int, double>> rec;
   for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) rec.push_back({v, ms[v]});
+  // the product's shape, then the part that was timed (at most kTuneRows rows and kTuneBatch batch entries)
   c->gemm_tuning_log.push_back({std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + " b" +
-                                    std::to_string(g.batch) + " layout" + std::to_string(std::get<4>(key)),
+                                    std::to_string(g.batch) + " layout" + std::to_string(std::get<4>(key)) +
+                                    " timed " + std::to_string(tmr) + "x" + std::to_string(g.N) + "x" +
+                                    std::to_string(g.K) + " b" + std::to_string(tbt),
                                 rec, best});
   launch_zgemm_variant(g, best, c->stream);
   return best;
