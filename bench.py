@@ -551,6 +551,8 @@ def gemm_kernel_name(variant):
     """HIP kernel behind an FP64 GEMM variant number of the autotuner."""
     if variant is None:
         return "FP64 GEMM"
+    if variant >= 15:
+        return "k_zgemm_dma"
     if variant >= 13:
         return "k_zgemm_w1"
     return "k_zgemm_p1" if variant >= 9 else "k_zgemm_p"

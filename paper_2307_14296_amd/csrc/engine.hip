@@ -605,7 +605,8 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
 constexpr int kTuneRows = 8192, kTuneBatch = 16;
 bool gemm_variant_grouped(int variant) {
   return (variant > GEMM_64x64_G4 && variant <= 2 * GEMM_64x64_G4) || variant == GEMM_64x64_G4_SB_GROUPED ||
-         variant == GEMM_128x64_G4_SB_GROUPED || variant == GEMM_128x128_G4_GROUPED;
+         variant == GEMM_128x64_G4_SB_GROUPED || variant == GEMM_128x128_G4_GROUPED ||
+         variant == GEMM_128x128_DMA_GROUPED;
 }
 int octave_bucket(int x) {
   int p = 1;

@@ -606,6 +606,205 @@ __global__ __launch_bounds__(512, 2) void k_zgemm_group_w1(const GemmArgs* __res
   }
 }
 
+// --------------------------------------------------------------------------
+// 128x128 four-product tile whose operand tiles go from HBM to LDS by direct
+// loads (global_load_lds_dwordx4: each lane names one 16-byte complex element,
+// the wave's 64 elements land as one contiguous KiB of LDS), so no register
+// staging, no LDS stores and no wait for the global loads sit in the K loop.
+// Each 16-deep K tile of an operand is 32 KiB in one of two layouts:
+//  * unit-stride k (the operand rows hold consecutive k): [row][16 slots],
+//    element k of a row in slot k ^ (row mod 16), so the 16 lanes that read
+//    one k of 16 consecutive rows hit 16 different bank groups and the 16
+//    lanes that load a row read its 256 contiguous bytes;
+//  * unit-stride rows: [k][128 rows], rows contiguous in both places.
+// Two stages in separate LDS arrays (128 KiB, one workgroup per CU, eight
+// waves of 64x32): each K tile first requests the next tile's loads into the
+// idle stage, then runs its MFMAs; the wait for the loads and the barrier sit
+// before its last K step.
+// Rows beyond the operand are clamped to its last row (their outputs are not
+// stored); a K remainder below 16 goes through registers with zero fill.
+// Conjugation flips the sign of the imaginary part of each operand fragment
+// (a separate instantiation, so products without it carry no flips).
+// --------------------------------------------------------------------------
+template <bool KC>
+__device__ __forceinline__ int dma_row(int c, int lane) {
+  return KC ? 4 * c + (lane >> 4) : (c & 1) * 64 + lane;
+}
+template <bool KC>
+__device__ __forceinline__ int dma_k(int c, int lane) {
+  return KC ? (lane & 15) ^ ((4 * c + (lane >> 4)) & 15) : c >> 1;
+}
+__device__ __forceinline__ void dma16(const cplx* src, cplx* lds) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+constexpr int kDmaTile = 128 * 16;  // complex elements per operand tile and stage
+
+template <bool AK, bool BNF, bool CJ>
+__device__ __forceinline__ void zgemm_tile_dma(const GemmArgs& g, const int m0, const int n0, const i64 bz,
+                                               cplx* sA0, cplx* sA1, cplx* sB0, cplx* sB1) {
+  constexpr int BK = 16, WM = 64, WN = 32, FM = WM / 16, FN = WN / 16;
+  constexpr bool KCA = AK, KCB = !BNF;  // which operands have unit-stride k
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int kbeg = 0, kend = g.K;
+  i64 bb = bz;
+  if (g.kchunk > 0) {
+    const int ns = (g.K + g.kchunk - 1) / g.kchunk;
+    kbeg = (int)(bz % ns) * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+    bb = bz / ns;
+  }
+  const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
+  const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const unsigned sgnA = g.conjA ? 0x80000000u : 0u, sgnB = g.conjB ? 0x80000000u : 0u;
+  const int nfull = (kend - kbeg) / BK, tail = kend - kbeg - nfull * BK;
+  // this lane's element of each of its four 1 KiB chunks (chunk c = 8 j + wave) of a K tile
+  const cplx* pa[4];
+  const cplx* pb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = 8 * j + wave;
+    const int ra = min(m0 + dma_row<KCA>(c, lane), g.M - 1), rb = min(n0 + dma_row<KCB>(c, lane), g.N - 1);
+    pa[j] = A + (i64)ra * g.sAm + (i64)(kbeg + dma_k<KCA>(c, lane)) * g.sAk;
+    pb[j] = B + (i64)rb * g.sBn + (i64)(kbeg + dma_k<KCB>(c, lane)) * g.sBk;
+  }
+  const i64 dA = (i64)BK * g.sAk, dB = (i64)BK * g.sBk;
+  auto fetch = [&](int t, cplx* la, cplx* lb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      dma16(pa[j] + t * dA, la + 64 * (8 * j + wave));
+      dma16(pb[j] + t * dB, lb + 64 * (8 * j + wave));
+    }
+  };
+  // LDS element of this lane's fragment of K step q (k = 4q + lane/16) in block i (A) or j (B)
+  const int rr = lane & 15, gq = lane >> 4;
+  auto offa = [&](int q, int i) {
+    return KCA ? (wm + 16 * i + rr) * BK + ((4 * q + gq) ^ rr) : (4 * q + gq) * 128 + wm + 16 * i + rr;
+  };
+  auto offb = [&](int q, int j) {
+    return KCB ? (wn + 16 * j + rr) * BK + ((4 * q + gq) ^ rr) : (4 * q + gq) * 128 + wn + 16 * j + rr;
+  };
+  d4 cr[FM][FN], ci[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      cr[i][j] = d4{0, 0, 0, 0};
+      ci[i][j] = d4{0, 0, 0, 0};
+    }
+  double2 fa[2][FM], fb[2][FN];
+  auto fread = [&](const cplx* la, const cplx* lb, int q, int s) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i) fa[s][i] = CJ ? flip_im(la[offa(q, i)], sgnA) : la[offa(q, i)];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) fb[s][j] = CJ ? flip_im(lb[offb(q, j)], sgnB) : lb[offb(q, j)];
+  };
+  // the 32 MFMAs of one 4-deep K step on the fragments in slot s
+  auto mfma_q = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].x, fb[s][j].x, cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].x, fb[s][j].y, ci[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].y, fb[s][j].y, cr[i][j], 0, 0, kNegA);
+        ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][i].y, fb[s][j].x, ci[i][j], 0, 0, 0);
+      }
+  };
+  // a whole K tile on one stage, its first fragments read here
+  auto compute = [&](const cplx* la, const cplx* lb) {
+    fread(la, lb, 0, 0);
+#pragma unroll
+    for (int q = 0; q < BK / 4; ++q) {
+      const int s = q & 1;
+      if (q + 1 < BK / 4) fread(la, lb, q + 1, s ^ 1);
+      mfma_q(s);
+    }
+  };
+  // one K tile on stage (ca, cb) while tile t + 1 loads into (na, nb); the
+  // last tile reloads itself into the idle stage (no branch around the loads).
+  // The tile's first fragments are already in slot 0.  The wait for the loads
+  // and the barrier come once the last K step's fragments are in registers,
+  // so the next tile's first fragments are read while that step's MFMAs run
+  // (2% faster than a barrier after the last MFMA).
+  auto step = [&](int t, const cplx* ca, const cplx* cb, cplx* na, cplx* nb) {
+    fetch(t + 1 < nfull ? t + 1 : t, na, nb);
+    __builtin_amdgcn_sched_barrier(0);
+    fread(ca, cb, 1, 1);
+    mfma_q(0);
+    fread(ca, cb, 2, 0);
+    mfma_q(1);
+    fread(ca, cb, 3, 1);
+    mfma_q(0);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    fread(na, nb, 0, 0);
+    mfma_q(1);
+  };
+  if (nfull > 0) {
+    fetch(0, sA0, sB0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    fread(sA0, sB0, 0, 0);
+    for (int t = 0; t < nfull; t += 2) {
+      step(t, sA0, sB0, sA1, sB1);
+      if (t + 1 < nfull) step(t + 1, sA1, sB1, sA0, sB0);
+    }
+    __syncthreads();  // every wave is done reading the stages before the remainder overwrites one
+  }
+  if (tail > 0) {  // K remainder: through registers, zero beyond kend (both stages are idle here)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 8 * j + wave;
+      const cplx z = make_double2(0.0, 0.0);
+      sA0[64 * c + lane] = dma_k<KCA>(c, lane) < tail ? pa[j][nfull * dA] : z;
+      sB0[64 * c + lane] = dma_k<KCB>(c, lane) < tail ? pb[j][nfull * dB] : z;
+    }
+    __syncthreads();
+    compute(sA0, sB0);
+  }
+  cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          const double xr = cr[i][j][r], xi = ci[i][j][r];
+          cplx y = make_double2(g.ar * xr - g.ai * xi, g.ar * xi + g.ai * xr);
+          cplx* dst = C + (i64)m * g.sCm + (i64)n * g.sCn;
+          if (g.beta) {
+            const cplx o = *dst;
+            y.x += o.x;
+            y.y += o.y;
+          }
+          *dst = y;
+        }
+      }
+}
+
+template <bool AK, bool BNF>
+__global__ __launch_bounds__(512, 2) void k_zgemm_dma(GemmArgs g, int tm, int tn, int gm, int xcd) {
+  int mi, ni, bz;
+  // the two stages of each operand are separate arrays, so the compiler knows
+  // that reads of one stage do not depend on the direct loads into the other
+  __shared__ cplx sA0[kDmaTile], sA1[kDmaTile], sB0[kDmaTile], sB1[kDmaTile];
+  tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
+  if (g.conjA || g.conjB) zgemm_tile_dma<AK, BNF, true>(g, mi * 128, ni * 128, bz, sA0, sA1, sB0, sB1);
+  else zgemm_tile_dma<AK, BNF, false>(g, mi * 128, ni * 128, bz, sA0, sA1, sB0, sB1);
+}
+
 // Grouped persistent form: one launch walks the tiles of several products
 // (problem p owns tiles [tstart[p], tstart[p+1])), each workgroup taking
 // every gridDim.x-th tile.  The LDS of a tile is released by the barrier
@@ -954,8 +1153,26 @@ static void launch_w1(const GemmArgs& g, bool grouped, hipStream_t s) {
   else hipLaunchKernelGGL((k_zgemm_w1<false, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
 }
 
+static void launch_dma(const GemmArgs& g, bool grouped, hipStream_t s) {
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128, gm = grouped ? std::min(tm, kGroupM) : tm;
+  const int xcd = grouped ? 1 : 0;
+  const i64 total = (i64)tm * tn * g.batch;
+  REQUIRE(total >= 1 && total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
+  dim3 grid((unsigned)total);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_dma<true, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_dma<true, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_dma<false, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else hipLaunchKernelGGL((k_zgemm_dma<false, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+}
+
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  if (variant == GEMM_128x128_DMA || variant == GEMM_128x128_DMA_GROUPED) {
+    launch_dma(g, variant == GEMM_128x128_DMA_GROUPED, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   if (variant == GEMM_128x128_G4 || variant == GEMM_128x128_G4_GROUPED) {
     launch_w1(g, variant == GEMM_128x128_G4_GROUPED, s);
     HIPCHK(hipGetLastError());

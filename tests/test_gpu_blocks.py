@@ -72,7 +72,7 @@ def test_zgemm(gpu, M, N, K, ta, tb):
 
 
 VARIANT_CASES = [(1, 1, 1, 1), (130, 70, 33, 3), (300, 200, 50, 1), (257, 1, 64, 2), (64, 640, 17, 5),
-                 (1100, 65, 40, 1), (260, 300, 70, 2)]
+                 (1100, 65, 40, 1), (260, 300, 70, 2), (129, 257, 160, 1), (5, 130, 15, 2)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", VARIANT_CASES)
@@ -89,19 +89,20 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
     B = crand(rng, batch, K, N)
     C0 = crand(rng, batch, M, N)
     alpha = 0.3 + 1.1j
-    for variant in range(15):
-        for ta, tb, beta in [(False, False, 0), (True, True, 1), (False, True, 1), (True, False, 0)]:
+    for variant in range(17):
+        for ta, tb, beta, cj in [(False, False, 0, 1), (True, True, 1, 0), (False, True, 1, 1), (True, False, 0, 0),
+                                 (False, True, 0, 0), (True, False, 1, 1)]:
             Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
             Bd = dev(B.transpose(0, 2, 1).copy() if tb else B)
             Cd = dev(C0)
             sAm, sAk = (1, M) if ta else (K, 1)
             sBk, sBn = (1, K) if tb else (N, 1)
             rc = L.cclr_dbg_zgemm_f64(variant, batch, M, N, K, Ad.data_ptr(), M * K, sAm, sAk, 0, Bd.data_ptr(),
-                                      K * N, sBk, sBn, 1, Cd.data_ptr(), M * N, N, 1, alpha.real, alpha.imag, beta)
+                                      K * N, sBk, sBn, cj, Cd.data_ptr(), M * N, N, 1, alpha.real, alpha.imag, beta)
             assert rc == 0
-            ref = alpha * (A @ B.conj()) + (C0 if beta else 0)
+            ref = alpha * (A @ (B.conj() if cj else B)) + (C0 if beta else 0)
             err = np.abs(Cd.cpu().numpy() - ref).max() / max(1.0, np.abs(ref).max())
-            assert err <= 1e-12, (variant, ta, tb, beta, err)
+            assert err <= 1e-12, (variant, ta, tb, beta, cj, err)
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4, 13])
