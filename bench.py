@@ -529,20 +529,32 @@ LADDER_TRAFFIC = os.path.join(ROOT, "profiles", "ladder_gemm_o20v200_traffic.md"
 GEMM_SOURCE = os.path.join(ROOT, "paper_2307_14296_amd", "csrc", "gemm_f64.hip")
 
 
+def gemm_kernel_digest():
+    """sha256 of the source of the 128x128 direct-load FP64 GEMM: its tile
+    order function and its tile function and kernel, as marked in the GEMM
+    source (the rest of that file does not change what it moves)."""
+    import hashlib
+    text = open(GEMM_SOURCE).read()
+    i = text.index("__device__ __forceinline__ void tile_of(")
+    order = text[i:text.index("\n}\n", i) + 3]
+    j = text.index("// 128x128 four-product tile whose operand tiles go from HBM to LDS")
+    tile = text[j:text.index("// grouped persistent form of the direct-load tile", j)]
+    return hashlib.sha256((order + tile).encode()).hexdigest()
+
+
 def ladder_traffic(variant):
     """HBM bytes per launch of the batched FP64 ladder GEMM (12 vectors at
     o=20, v=200) in the kernel variant the autotuner chose, from the
-    committed rocprofv3 --pmc summary (one figure per variant); None when
-    the GEMM source differs from the one the counters were taken on."""
-    import hashlib
+    committed rocprofv3 --pmc summary (one figure per variant); None for a
+    variant other than the direct-load tiles (15, 16) or when their source
+    differs from the one the counters were taken on."""
     try:
         text = open(LADDER_TRAFFIC).read()
     except OSError:
         return None
     vals = dict(re.findall(r"^- (\w+): (\S+)$", text, flags=re.M))
-    src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
     key = f"variant_{variant}_hbm_bytes_per_launch"
-    if vals.get("kernel_source_sha256") != src or key not in vals:
+    if variant not in (15, 16) or vals.get("dma_kernel_source_sha256") != gemm_kernel_digest() or key not in vals:
         return None
     return float(vals[key])
 

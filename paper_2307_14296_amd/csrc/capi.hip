@@ -427,7 +427,7 @@ void grouped_products(cclr_ctx* c0, std::vector<GemmArgs> g) {
     int best = GEMM_128x64_G4;
     double best_ms = -1;
     std::vector<std::pair<int, double>> ms_all;
-    for (int var : {GEMM_128x64_G3, GEMM_64x64_G3, GEMM_128x64_G4, GEMM_64x64_G4, GEMM_128x128_G4}) {
+    for (int var : {GEMM_128x64_G3, GEMM_64x64_G3, GEMM_128x64_G4, GEMM_64x64_G4, GEMM_128x128_G4, GEMM_128x128_DMA}) {
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));

@@ -805,6 +805,28 @@ __global__ __launch_bounds__(512, 2) void k_zgemm_dma(GemmArgs g, int tm, int tn
   else zgemm_tile_dma<AK, BNF, false>(g, mi * 128, ni * 128, bz, sA0, sA1, sB0, sB1);
 }
 
+// grouped persistent form of the direct-load tile (one workgroup per CU); the
+// barrier ahead of each tile keeps its first loads from overwriting a stage
+// that another wave still reads for the previous tile
+template <bool AK, bool BNF>
+__global__ __launch_bounds__(512, 2) void k_zgemm_group_dma(const GemmArgs* __restrict__ probs,
+                                                           const int* __restrict__ tstart, int nprob, int total) {
+  __shared__ cplx sA0[kDmaTile], sA1[kDmaTile], sB0[kDmaTile], sB1[kDmaTile];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int p = 0;
+    while (p + 1 < nprob && t >= tstart[p + 1]) ++p;
+    const GemmArgs g = probs[p];
+    const int lt = t - tstart[p];
+    const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+    const int mi = lt % tm, rest = lt / tm;
+    __syncthreads();
+    if (g.conjA || g.conjB)
+      zgemm_tile_dma<AK, BNF, true>(g, mi * 128, (rest % tn) * 128, rest / tn, sA0, sA1, sB0, sB1);
+    else
+      zgemm_tile_dma<AK, BNF, false>(g, mi * 128, (rest % tn) * 128, rest / tn, sA0, sA1, sB0, sB1);
+  }
+}
+
 // Grouped persistent form: one launch walks the tiles of several products
 // (problem p owns tiles [tstart[p], tstart[p+1])), each workgroup taking
 // every gridDim.x-th tile.  The LDS of a tile is released by the barrier
@@ -1217,13 +1239,25 @@ static void launch_group(const GemmArgs* probs, const int* tstart, int nprob, in
 }
 
 int gemm_tile_rows(int variant) {
-  return (variant == GEMM_128x64_G3 || variant == GEMM_128x64_G4 || variant == GEMM_128x128_G4) ? 128 : 64;
+  return (variant == GEMM_128x64_G3 || variant == GEMM_128x64_G4 || variant == GEMM_128x128_G4 ||
+          variant == GEMM_128x128_DMA)
+             ? 128
+             : 64;
 }
-int gemm_tile_cols(int variant) { return variant == GEMM_128x128_G4 ? 128 : 64; }
+int gemm_tile_cols(int variant) { return (variant == GEMM_128x128_G4 || variant == GEMM_128x128_DMA) ? 128 : 64; }
 
 void launch_zgemm_group(const GemmArgs* probs, const int* tstart, int nprob, int total, int variant, bool ak, bool bn,
                         hipStream_t s) {
   if (total <= 0) return;
+  if (variant == GEMM_128x128_DMA) {
+    const int grid = std::min(total, 256);
+    if (ak && bn) hipLaunchKernelGGL((k_zgemm_group_dma<true, true>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    else if (ak) hipLaunchKernelGGL((k_zgemm_group_dma<true, false>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    else if (bn) hipLaunchKernelGGL((k_zgemm_group_dma<false, true>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    else hipLaunchKernelGGL((k_zgemm_group_dma<false, false>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   if (variant == GEMM_128x128_G4) {
     const int grid = std::min(total, 256);
     if (ak && bn) hipLaunchKernelGGL((k_zgemm_group_w1<true, true>), dim3(grid), dim3(512), 0, s, probs, tstart, nprob, total);

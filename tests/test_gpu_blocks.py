@@ -105,7 +105,7 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
             assert err <= 1e-12, (variant, ta, tb, beta, cj, err)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 13])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 13, 15])
 def test_zgemm_grouped_persistent_launch(gpu, variant):
     """The persistent grouped launch (several products of different shapes
     dealt as one tile sequence) in every tile shape that has a grouped form,
@@ -115,7 +115,9 @@ def test_zgemm_grouped_persistent_launch(gpu, variant):
     L.cclr_dbg_zgemm_group_f64.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(P)]
-    shapes = [(257, 300, 140), (130, 70, 33), (64, 129, 17), (300, 260, 50), (1, 1, 1)]
+    # the last product alone has more 128x128 tiles than there are workgroups (256), so some
+    # workgroups run several tiles, some with a K remainder
+    shapes = [(257, 300, 140), (130, 70, 33), (64, 129, 17), (300, 260, 50), (1, 1, 1), (2100, 2100, 20)]
     rng = np.random.default_rng(17 + variant)
     for bt in (0, 1):
         As = [crand(rng, m, k) for m, n, k in shapes]
