@@ -23,7 +23,9 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
  * variant (0: simple; 1..4: MFMA tiles 128x64 / 64x64 with three or four
  * real products per complex block; 4 + k: variant k in the XCD-grouped tile
  * order; 9, 10 and 11, 12: 64x64 and 128x64 four-product tiles with one LDS
- * buffer, plain and grouped order).  All pointers are device memory; strides in elements.  For tests
+ * buffer, plain and grouped order; 13, 14: 128x128 tiles, operands staged
+ * through registers; 15, 16: 128x128 tiles with direct global-to-LDS operand
+ * loads; plain and grouped order).  All pointers are device memory; strides in elements.  For tests
  * of every variant (the autotuner otherwise runs only the fastest). */
 int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c64* A, long long sAb, long long sAm,
                        long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
@@ -33,7 +35,7 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
 /* Several independent products C[p] = A[p] B[p] (A[p] row-major M[p] x K[p];
  * B[p] row-major K[p] x N[p], or N[p] x K[p] when btrans; C[p] row-major
  * M[p] x N[p]; all device pointers) in the one persistent grouped launch of
- * FP64 variant 1, 2, 3, 4 or 13 (the tile shapes that have a grouped form). */
+ * FP64 variant 1, 2, 3, 4, 13 or 15 (the tile shapes that have a grouped form). */
 int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N, const int* K,
                              const cclr_c64* const* A, const cclr_c64* const* B, int btrans, cclr_c64* const* C);
 
@@ -123,6 +125,14 @@ int cclr_dbg_hessian(cclr_ctx* ctx, int nvec, const cclr_c64* x1, const cclr_c64
 /* Bytes of the fixed work space that the context's last
  * cclr_jacobian_right_noalloc call took at most (0 before the first). */
 int cclr_dbg_fixed_ws_peak(const cclr_ctx* ctx, long long* bytes);
+
+/* The GPU eigensolver of the EOM-EE Davidson subspace (Householder
+ * reduction, shifted QR, back substitution; one workgroup) on a host matrix
+ * H (n x n row-major, 1 <= n <= 120): all eigenvalues in w[n] (in the order
+ * of the Schur form), the nroots eigenvalues of smallest real part (ties by
+ * index) in theta and their unit-norm right eigenvectors in vecs[nroots][n].
+ * Host pointers.  CCLR_ENOTCONV if the QR iteration does not converge. */
+int cclr_dbg_small_eig(int n, const cclr_c64* H, int nroots, cclr_c64* w, cclr_c64* theta, cclr_c64* vecs);
 
 /* Autotuner record: writes up to cap bytes of text, one line per tuned
  * GEMM shape class: "MxNxK bB layoutL timed mxNxK bb: variant=ms ... -> chosen"

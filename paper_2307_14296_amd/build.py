@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcclr.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["gemm_f64.hip", "gemm_skinny.hip", "kernels.hip", "pairs.hip", "gemm_split.hip", "engine.hip", "hbar.hip", "sigma.hip", "solver.hip", "response.hip", "adjoint.hip", "ground.hip", "capi.hip", "debug.hip"]
+SOURCES = ["gemm_f64.hip", "gemm_skinny.hip", "kernels.hip", "pairs.hip", "gemm_split.hip", "smalleig.hip", "engine.hip", "hbar.hip", "sigma.hip", "solver.hip", "response.hip", "adjoint.hip", "ground.hip", "capi.hip", "debug.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -74,7 +74,7 @@ int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N,
   int rc = CCLR_OK;
   try {
     REQUIRE(variant == GEMM_128x64_G3 || variant == GEMM_64x64_G3 || variant == GEMM_128x64_G4 ||
-                variant == GEMM_64x64_G4 || variant == GEMM_128x128_G4,
+                variant == GEMM_64x64_G4 || variant == GEMM_128x128_G4 || variant == GEMM_128x128_DMA,
             CCLR_EINVAL, "no grouped form of this GEMM variant");
     REQUIRE(nprob > 0 && M && N && K && A && B && C, CCLR_EINVAL, "grouped GEMM: missing arguments");
     std::vector<GemmArgs> g(nprob);
@@ -316,6 +316,47 @@ int cclr_dbg_fixed_ws_peak(const cclr_ctx* c, long long* bytes) {
   if (!c || !bytes) return CCLR_EINVAL;
   *bytes = (long long)c->fixed_ws_peak;
   return CCLR_OK;
+}
+
+int cclr_dbg_small_eig(int n, const cclr_c64* H, int nroots, cclr_c64* w, cclr_c64* theta, cclr_c64* vecs) {
+  void* dev = nullptr;
+  int rc = CCLR_OK;
+  try {
+    REQUIRE(H && w && theta && vecs, CCLR_EINVAL, "small eigensolver: null argument");
+    REQUIRE(n >= 1 && n <= kSmallEigMax && nroots >= 1 && nroots <= n, CCLR_EINVAL, "small eigensolver: bad size");
+    const size_t nn = (size_t)n * n;
+    // device: Hu (column-major copy), Hl (row-major), work, coef, coef2, theta, w, status
+    const size_t elems = 2 * nn + small_eig_work_elems(n) + 2 * (size_t)nroots * n + nroots + n;
+    HIPCHK(hipMalloc(&dev, sizeof(cplx) * elems + 256));
+    cplx* Hu = (cplx*)dev;
+    cplx* Hl = Hu + nn;
+    cplx* work = Hl + nn;
+    cplx* coef = work + small_eig_work_elems(n);
+    cplx* coef2 = coef + (size_t)nroots * n;
+    cplx* th = coef2 + (size_t)nroots * n;
+    cplx* wall = th + nroots;
+    int* status = (int*)(wall + n);
+    std::vector<cplx> hu(nn), hl(nn);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const cplx x = make_double2(H[(size_t)i * n + j].re, H[(size_t)i * n + j].im);
+        hu[(size_t)j * n + i] = x;
+        hl[(size_t)i * n + j] = x;
+      }
+    HIPCHK(hipMemcpy(Hu, hu.data(), sizeof(cplx) * nn, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(Hl, hl.data(), sizeof(cplx) * nn, hipMemcpyHostToDevice));
+    launch_small_eig(n, Hu, Hl, n, work, nroots, coef, coef2, n, th, wall, status, nullptr);
+    int ok = 0;
+    HIPCHK(hipMemcpy(&ok, status, sizeof(int), hipMemcpyDeviceToHost));
+    REQUIRE(ok == 1, CCLR_ENOTCONV, "small eigensolver: QR iteration did not converge");
+    HIPCHK(hipMemcpy(w, wall, sizeof(cplx) * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(theta, th, sizeof(cplx) * nroots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(vecs, coef, sizeof(cplx) * (size_t)nroots * n, hipMemcpyDeviceToHost));
+  } catch (const CclrError& e) {
+    rc = e.code;
+  }
+  if (dev) (void)hipFree(dev);
+  return rc;
 }
 
 int cclr_dbg_tuning(cclr_ctx* c, int enable, char* buf, long long cap) {

@@ -170,6 +170,16 @@ SplitMat launch_split(int rows, int K, const cplx* src, i64 sR, i64 sK, int conj
 // C[m][n] (+)= alpha * sum_k A[m][k] B[n][k] on operands split for one form, FP32 accumulation
 void launch_split_gemm(const SplitMat& A, const SplitMat& B, cplx* C, i64 sCm, i64 sCn, double ar, double ai,
                        int beta, hipStream_t s);
+// Eigenpairs of a small dense complex matrix on the GPU (one workgroup):
+// H(i, j) = Hu[j ld + i] for i <= j and Hl[i ld + j] for i > j, n <= kSmallEigMax;
+// work holds small_eig_work_elems(n) elements.  Writes theta[r] and the unit-norm
+// right eigenvector coef[r ldc + i] of the nroots eigenvalues of smallest real
+// part (ties by index), coef2 = -theta coef, all eigenvalues in wall (if not
+// null), and status[0] = 1, or 0 if the QR iteration did not converge.
+constexpr int kSmallEigMax = 120;
+size_t small_eig_work_elems(int n);
+void launch_small_eig(int n, const cplx* Hu, const cplx* Hl, int ld, cplx* work, int nroots, cplx* coef, cplx* coef2,
+                      int ldc, cplx* theta, cplx* wall, int* status, hipStream_t st);
 // products with K <= 32 on the vector ALU (returns false if the form does not apply)
 bool launch_zgemm_smallk(const GemmArgs& g, hipStream_t s);
 // C[b][m][n] = (beta ? C : 0) + alpha * sum_s W[b][s][m][n]

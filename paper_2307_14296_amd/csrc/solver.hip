@@ -659,7 +659,9 @@ int solve_system(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rh
 // EOM-EE excitation energies that are the poles of the response function
 // (SI, "EOM-EE sigma-vectors"; Davidson's method for a few eigenpairs of a
 // non-Hermitian matrix).  One subspace shared by all roots: orthonormal b_i,
-// s_i = A b_i, projected matrix H = B^H S (dense eigenproblem on the host),
+// s_i = A b_i, projected matrix H = B^H S (built and solved on the GPU: the
+// Gram products write its new rows and columns in place, the small
+// eigensolver writes the Ritz coefficients straight into the combinations),
 // Ritz pairs (theta_k, x_k = B y_k), residuals r_k = S y_k - theta_k x_k,
 // corrections (theta_k - D)^-1 r_k orthogonalized twice against the
 // subspace.  When the subspace is full it restarts from the Ritz vectors.
@@ -684,6 +686,12 @@ int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, st
   const VS R{Rv.s, Rv.d, 1}, E{Ev.s, Ev.d, 1}, X{xout.s, xout.d, 1};
   cplx* tmpv = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nroots * ms);
   cplx* coef = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nroots * ms);
+  cplx* coef2 = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nroots * ms);
+  // projected matrix: Hu[j ms + i] = H[i][j] (i <= j), Hl[j ms + i] = H[j][i] (i < j)
+  cplx* Hu = (cplx*)c->arena.get(sizeof(cplx) * (size_t)ms * ms);
+  cplx* Hl = (cplx*)c->arena.get(sizeof(cplx) * (size_t)ms * ms);
+  cplx* eigw = (cplx*)c->arena.get(sizeof(cplx) * small_eig_work_elems(ms));
+  int* eig_status = (int*)c->arena.get(sizeof(int));
   cplx* partial = (cplx*)c->arena.get(sizeof(cplx) * (size_t)nroots * ms * kChunks);
   int* act_d = (int*)c->arena.get(sizeof(int) * nroots);
   cplx* z_d = (cplx*)c->arena.get(sizeof(cplx) * nroots);
@@ -756,20 +764,12 @@ int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, st
   HIPCHK(hipStreamSynchronize(st));
   int m = nstart;
   transform(0, m);
-  std::vector<eigsmall::zc> H((size_t)ms * ms, 0.0);
   auto update_H = [&](int j0, int j1) {  // rows and columns of H for the new vectors j0..j1-1
     std::vector<int> zero{0};
     set_active(zero);
-    std::vector<cplx> hv;
     for (int j = j0; j < j1; ++j) {
-      gram(B, 0, j + 1, S, j, tmpv, ms, 0, 0);  // H[i][j] = <b_i, s_j>, i <= j
-      fetch(tmpv, hv, (size_t)(j + 1));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * ms + j] = eigsmall::zc(hv[i].x, hv[i].y);
-      if (j > 0) {
-        gram(S, 0, j, B, j, tmpv, ms, 0, 1);  // H[j][i] = <b_j, s_i>, i < j
-        fetch(tmpv, hv, (size_t)j);
-        for (int i = 0; i < j; ++i) H[(size_t)j * ms + i] = eigsmall::zc(hv[i].x, hv[i].y);
-      }
+      gram(B, 0, j + 1, S, j, Hu, 0, j * ms, 0);  // H[i][j] = <b_i, s_j>, i <= j
+      if (j > 0) gram(S, 0, j, B, j, Hl, 0, j * ms, 1);  // H[j][i] = <b_j, s_i>, i < j
     }
   };
   update_H(0, m);
@@ -782,35 +782,20 @@ int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, st
   for (int k = 0; k < nroots; ++k) roots[k] = k;
   while (true) {
     ++iters;
-    // Ritz pairs of the projected matrix
-    std::vector<eigsmall::zc> Hm((size_t)m * m), w, V;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) Hm[(size_t)i * m + j] = H[(size_t)i * ms + j];
-    REQUIRE(eigsmall::eig(m, Hm, w, V), CCLR_ENOTCONV, "projected eigenproblem did not converge");
-    std::vector<int> ord(m);
-    for (int i = 0; i < m; ++i) ord[i] = i;
-    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
-    std::vector<cplx> cf((size_t)nroots * ms, cx(0.0)), cf2((size_t)nroots * ms, cx(0.0));
-    for (int k = 0; k < nroots; ++k) {
-      const eigsmall::zc th = w[ord[k]];
-      omega[k] = cx(th.real(), th.imag());
-      for (int i = 0; i < m; ++i) {
-        const eigsmall::zc y = V[(size_t)i * m + ord[k]];
-        cf[(size_t)k * ms + i] = cx(y.real(), y.imag());
-        const eigsmall::zc t = -th * y;
-        cf2[(size_t)k * ms + i] = cx(t.real(), t.imag());
-      }
-    }
+    // Ritz pairs of the projected matrix (on the GPU): theta_k in z_d, y_k in coef, -theta_k y_k in coef2
+    launch_small_eig(m, Hu, Hl, ms, eigw, nroots, coef, coef2, ms, z_d, nullptr, eig_status, st);
     set_active(roots);
-    HIPCHK(hipMemcpyAsync(coef, cf.data(), sizeof(cplx) * cf.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(z_d, omega.data(), sizeof(cplx) * nroots, hipMemcpyHostToDevice, st));
     lincomb(X, 0, B, 0, m, coef, ms, 0);   // x_k = B y_k
     lincomb(R, 0, S, 0, m, coef, ms, 0);   // r_k = S y_k ...
-    HIPCHK(hipMemcpyAsync(coef, cf2.data(), sizeof(cplx) * cf2.size(), hipMemcpyHostToDevice, st));
-    lincomb(R, 0, B, 0, m, coef, ms, 1);   // ... - theta_k B y_k
+    lincomb(R, 0, B, 0, m, coef2, ms, 1);  // ... - theta_k B y_k
     gram(R, 0, 1, R, 0, tmpv, 1, 0, 0);
-    std::vector<cplx> hv;
-    fetch(tmpv, hv, (size_t)nroots);
+    std::vector<cplx> hv((size_t)nroots);
+    int eig_ok = 0;
+    HIPCHK(hipMemcpyAsync(hv.data(), tmpv, sizeof(cplx) * nroots, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(omega.data(), z_d, sizeof(cplx) * nroots, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&eig_ok, eig_status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    REQUIRE(eig_ok == 1, CCLR_ENOTCONV, "projected eigenproblem did not converge");
     std::vector<int> open;
     for (int k = 0; k < nroots; ++k) {
       res[k] = std::sqrt(std::max(hv[k].x, 0.0));
@@ -835,7 +820,6 @@ int eom_davidson(cclr_ctx* c, int side, int nroots, double tol, int maxit_in, st
       }
       m = m2;
       transform(0, m);
-      std::fill(H.begin(), H.end(), eigsmall::zc(0.0));
       update_H(0, m);
       continue;
     }
