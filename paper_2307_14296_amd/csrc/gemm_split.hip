@@ -143,7 +143,10 @@ __device__ __forceinline__ void dma_tile(const u4v* __restrict__ g, u4v* lds, in
 // waits: about 1.2 times faster than four waves of 64 x 64 with one wave per
 // SIMD), double-buffered LDS filled by direct loads one k step ahead: each
 // step requests the next step's tiles into the other stage, then reads its
-// operand fragments and runs its MFMAs while the loads are in flight.  The
+// operand fragments and runs its MFMAs while the loads are in flight; the
+// wait for the loads and the barrier come before the MFMAs of its last row
+// block, whose time covers the reads of the next step's first fragments
+// (3-5% faster than a barrier after the last MFMA).  The
 // stages are separate LDS arrays, so the compiler does not make the reads of
 // one wait for the direct loads into the other.  Workgroups are numbered so
 // that each XCD (workgroups are dealt to the 8 XCDs round-robin) walks a
@@ -191,36 +194,65 @@ __global__ __launch_bounds__(512) void k_cgemm_bf16s(const u4v* __restrict__ As,
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[a][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto mfma_i = [&](int i, const bf8 (&a)[PA], const bf8 (&b)[FN][PB]) {
+#pragma unroll
+    for (int q = 0; q < D.nprod; ++q)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[D.prod[q][2]][i][j] = MF(a[D.prod[q][0]], b[j][D.prod[q][1]], acc[D.prod[q][2]][i][j]);
+  };
+  auto read_b = [&](const u4v* cb, bf8 (&b)[FN][PB]) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int p = 0; p < PB; ++p) b[j][p] = as_bf8(cb[offb[p] + 16 * j * RSB]);
+  };
+  auto read_a = [&](const u4v* ca, int i, bf8 (&a)[PA]) {
+#pragma unroll
+    for (int p = 0; p < PA; ++p) a[p] = as_bf8(ca[offa[p] + 16 * i * RSA]);
+  };
+  bf8 bq[FN][PB], aq[PA];  // the first fragments of the next step, read ahead
   // one k step on the stage (ca, cb) while the next step's tiles load into (na, nb)
   auto step = [&](int kc, const u4v* ca, const u4v* cb, u4v* na, u4v* nb) {
     // the last step reloads its own tiles into the idle stage (no branch)
     fetch(kc + 1 < nkc ? kc + 1 : kc, na, nb);
     __builtin_amdgcn_sched_barrier(0);  // the loads are requested first, not scheduled between the MFMAs
-    bf8 b[FN][PB];
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int p = 0; p < PB; ++p) b[j][p] = as_bf8(cb[offb[p] + 16 * j * RSB]);
+    // the wait and the barrier come once the last fragments of this stage
+    // are read; the next stage's first fragments are read while the MFMAs
+    // of the last row block run
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       bf8 a[PA];
+      if (i == 0) {
 #pragma unroll
-      for (int p = 0; p < PA; ++p) a[p] = as_bf8(ca[offa[p] + 16 * i * RSA]);
-#pragma unroll
-      for (int q = 0; q < D.nprod; ++q)
+        for (int p = 0; p < PA; ++p) a[p] = aq[p];
+      } else {
+        read_a(ca, i, a);
+      }
+      if (i + 1 < FM) {
+        mfma_i(i, a, bq);
+      } else {
+        bf8 bn[FN][PB], an[PA];
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        read_b(nb, bn);
+        read_a(na, 0, an);
+        mfma_i(i, a, bq);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          acc[D.prod[q][2]][i][j] = MF(a[D.prod[q][0]], b[j][D.prod[q][1]], acc[D.prod[q][2]][i][j]);
+#pragma unroll
+          for (int p = 0; p < PB; ++p) bq[j][p] = bn[j][p];
+#pragma unroll
+        for (int p = 0; p < PA; ++p) aq[p] = an[p];
+      }
     }
-    // the next step's tiles have landed and every wave is done with this
-    // stage; the scheduling barrier keeps the wait behind the MFMAs
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
   };
   fetch(0, sA0, sB0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  read_b(sB0, bq);
+  read_a(sA0, 0, aq);
   for (int kc = 0; kc < nkc; kc += 2) {
     step(kc, sA0, sB0, sA1, sB1);
     if (kc + 1 < nkc) step(kc + 1, sA1, sB1, sA0, sB0);
@@ -338,34 +370,63 @@ __global__ __launch_bounds__(512) void k_cgemm_f32s(const u4v* __restrict__ As, 
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[a][i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  auto step = [&](int kb, const u4v* ca, const u4v* cb, u4v* na, u4v* nb) {
-    fetch(kb + 1 < nkb ? kb + 1 : kb, na, nb);
-    __builtin_amdgcn_sched_barrier(0);  // the loads are requested first, not scheduled between the MFMAs
-    f4 b[FN][3];
+  auto mfma_i = [&](int i, const f4 (&a)[3], const f4 (&b)[FN][3]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p][s], b[j][p][s], acc[p][i][j], 0, 0, 0);
+  };
+  auto read_b = [&](const u4v* cb, f4 (&b)[FN][3]) {
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int p = 0; p < 3; ++p) b[j][p] = __builtin_bit_cast(f4, cb[(wn + 16 * j) * RS + off[p]]);
+  };
+  auto read_a = [&](const u4v* ca, int i, f4 (&a)[3]) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) a[p] = __builtin_bit_cast(f4, ca[(wm + 16 * i) * RS + off[p]]);
+  };
+  f4 bq[FN][3], aq[3];  // the first fragments of the next step, read ahead
+  auto step = [&](int kb, const u4v* ca, const u4v* cb, u4v* na, u4v* nb) {
+    fetch(kb + 1 < nkb ? kb + 1 : kb, na, nb);
+    __builtin_amdgcn_sched_barrier(0);  // the loads are requested first, not scheduled between the MFMAs
+    // as in the split-BF16 kernel: wait and barrier before the last row block's MFMAs
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       f4 a[3];
+      if (i == 0) {
 #pragma unroll
-      for (int p = 0; p < 3; ++p) a[p] = __builtin_bit_cast(f4, ca[(wm + 16 * i) * RS + off[p]]);
+        for (int p = 0; p < 3; ++p) a[p] = aq[p];
+      } else {
+        read_a(ca, i, a);
+      }
+      if (i + 1 < FM) {
+        mfma_i(i, a, bq);
+      } else {
+        f4 bn[FN][3], an[3];
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        read_b(nb, bn);
+        read_a(na, 0, an);
+        mfma_i(i, a, bq);
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+          for (int p = 0; p < 3; ++p) bq[j][p] = bn[j][p];
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p][s], b[j][p][s], acc[p][i][j], 0, 0, 0);
+        for (int p = 0; p < 3; ++p) aq[p] = an[p];
+      }
     }
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
   };
   fetch(0, sA0, sB0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  read_b(sB0, bq);
+  read_a(sA0, 0, aq);
   for (int kb = 0; kb < nkb; kb += 2) {
     step(kb, sA0, sB0, sA1, sB1);
     if (kb + 1 < nkb) step(kb + 1, sA1, sB1, sA0, sB0);
