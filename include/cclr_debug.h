@@ -32,6 +32,14 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
                        int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,
                        int beta);
 
+/* Split-K form of one FP64 MFMA variant (1 .. 16): the partial products
+ * W[s][m][n] = sum over k in chunk s (k = s kchunk .. min(K, (s+1) kchunk) - 1)
+ * of A(m, k) B(k, n), for s < ceil(K / kchunk); A(m, k) = A[m sAm + k sAk],
+ * B(k, n) = B[k sBk + n sBn]; device pointers.  For tests of the chunk
+ * bounds that the split-K products of the engine rely on. */
+int cclr_dbg_zgemm_f64_splitk(int variant, int M, int N, int K, int kchunk, const cclr_c64* A, long long sAm,
+                              long long sAk, const cclr_c64* B, long long sBk, long long sBn, cclr_c64* W);
+
 /* Several independent products C[p] = A[p] B[p] (A[p] row-major M[p] x K[p];
  * B[p] row-major K[p] x N[p], or N[p] x K[p] when btrans; C[p] row-major
  * M[p] x N[p]; all device pointers) in the one persistent grouped launch of

@@ -68,6 +68,26 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
   return CCLR_OK;
 }
 
+int cclr_dbg_zgemm_f64_splitk(int variant, int M, int N, int K, int kchunk, const cclr_c64* A, long long sAm,
+                              long long sAk, const cclr_c64* B, long long sBk, long long sBn, cclr_c64* W) {
+  try {
+    REQUIRE(variant >= 1 && variant < GEMM_NVAR, CCLR_EINVAL, "no such MFMA GEMM variant");
+    REQUIRE(M > 0 && N > 0 && K > 0 && kchunk > 0, CCLR_EINVAL, "empty product");
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K; g.kchunk = kchunk;
+    g.batch = (K + kchunk - 1) / kchunk;  // one batch entry per K chunk
+    g.A = (const cplx*)A; g.sAm = sAm; g.sAk = sAk;
+    g.B = (const cplx*)B; g.sBk = sBk; g.sBn = sBn;
+    g.C = (cplx*)W; g.sCb = (i64)M * N; g.sCm = N; g.sCn = 1;
+    g.ar = 1.0; g.ai = 0.0; g.beta = 0;
+    launch_zgemm_variant(g, variant, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+  } catch (const CclrError& e) {
+    return e.code;
+  }
+  return CCLR_OK;
+}
+
 int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N, const int* K,
                              const cclr_c64* const* A, const cclr_c64* const* B, int btrans, cclr_c64* const* C) {
   void* dev = nullptr;

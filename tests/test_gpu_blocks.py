@@ -105,6 +105,33 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
             assert err <= 1e-12, (variant, ta, tb, beta, cj, err)
 
 
+@pytest.mark.parametrize("M,N,K,kchunk", [(130, 70, 200, 48), (257, 129, 130, 64), (5, 300, 97, 32)])
+def test_zgemm_split_k_every_variant(gpu, M, N, K, kchunk):
+    """The split-K form (one partial product per K chunk, the last chunk
+    ragged) of every MFMA variant, both operand orientations, against numpy
+    chunk by chunk."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_zgemm_f64_splitk.argtypes = [ctypes.c_int] * 5 + [P, LL, LL, P, LL, LL, P]
+    rng = np.random.default_rng(M + 3 * N + 7 * K + kchunk)
+    A = crand(rng, M, K)
+    B = crand(rng, K, N)
+    S = (K + kchunk - 1) // kchunk
+    ref = np.stack([A[:, s * kchunk:(s + 1) * kchunk] @ B[s * kchunk:(s + 1) * kchunk] for s in range(S)])
+    for variant in range(1, 17):
+        for ta, tb in [(False, False), (False, True), (True, False)]:
+            Ad = dev(A.T.copy() if ta else A)
+            Bd = dev(B.T.copy() if tb else B)
+            Wd = torch.full((S, M, N), 3.0 + 0j, dtype=torch.complex128, device="cuda")
+            sAm, sAk = (1, M) if ta else (K, 1)
+            sBk, sBn = (1, K) if tb else (N, 1)
+            rc = L.cclr_dbg_zgemm_f64_splitk(variant, M, N, K, kchunk, Ad.data_ptr(), sAm, sAk, Bd.data_ptr(), sBk,
+                                             sBn, Wd.data_ptr())
+            assert rc == 0
+            err = np.abs(Wd.cpu().numpy() - ref).max() / max(1.0, np.abs(ref).max())
+            assert err <= 1e-12, (variant, ta, tb, err)
+
+
 @pytest.mark.parametrize("variant", [1, 2, 3, 4, 13, 15])
 def test_zgemm_grouped_persistent_launch(gpu, variant):
     """The persistent grouped launch (several products of different shapes
