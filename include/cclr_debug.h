@@ -32,6 +32,14 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
                        int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,
                        int beta);
 
+/* The engine's strided copy: for every index (i_0 .. i_{nd-1}) < dim,
+ * dst[sum i_d sd[d]] = (acc ? dst : 0) + alpha * op(src[sum i_d ss[d]]), op
+ * the conjugate when conj; alpha = 0 writes zeros without reading src.
+ * nd <= 6; device pointers; strides in elements.  For tests of its forms
+ * (merged indices, 32-bit index path, LDS-tiled transpose). */
+int cclr_dbg_tcopy(int nd, const long long* dim, const long long* sd, const long long* ss, cclr_c64* dst,
+                   const cclr_c64* src, double ar, double ai, int conj, int acc);
+
 /* Split-K form of one FP64 MFMA variant (1 .. 16): the partial products
  * W[s][m][n] = sum over k in chunk s (k = s kchunk .. min(K, (s+1) kchunk) - 1)
  * of A(m, k) B(k, n), for s < ceil(K / kchunk); A(m, k) = A[m sAm + k sAk],

@@ -68,6 +68,34 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
   return CCLR_OK;
 }
 
+int cclr_dbg_tcopy(int nd, const long long* dim, const long long* sd, const long long* ss, cclr_c64* dst,
+                   const cclr_c64* src, double ar, double ai, int conj, int acc) {
+  try {
+    REQUIRE(nd >= 1 && nd <= 6 && dim && sd && ss && dst && src, CCLR_EINVAL, "tcopy: bad arguments");
+    CopyArgs a{};
+    a.nd = nd;
+    a.total = 1;
+    for (int d = 0; d < nd; ++d) {
+      REQUIRE(dim[d] >= 1, CCLR_EINVAL, "tcopy: empty extent");
+      a.dim[d] = dim[d];
+      a.sd[d] = sd[d];
+      a.ss[d] = ss[d];
+      a.total *= dim[d];
+    }
+    a.dst = (cplx*)dst;
+    a.src = (const cplx*)src;
+    a.ar = ar;
+    a.ai = ai;
+    a.conj = conj;
+    a.acc = acc;
+    launch_tcopy(a, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+  } catch (const CclrError& e) {
+    return e.code;
+  }
+  return CCLR_OK;
+}
+
 int cclr_dbg_zgemm_f64_splitk(int variant, int M, int N, int K, int kchunk, const cclr_c64* A, long long sAm,
                               long long sAk, const cclr_c64* B, long long sBk, long long sBn, cclr_c64* W) {
   try {

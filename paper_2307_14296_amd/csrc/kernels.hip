@@ -6,15 +6,19 @@ namespace {
 // --------------------------------------------------------------------------
 // Strided tensor copy / accumulate: dst[idx] (+)= alpha * op(src[idx]).
 // --------------------------------------------------------------------------
+template <typename IT>
 __global__ __launch_bounds__(256) void k_tcopy(CopyArgs a) {
+  // IT: the index type of the element number and its decomposition (32-bit
+  // when the count fits: integer division is several times cheaper)
   const i64 stride = (i64)gridDim.x * blockDim.x;
   for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < a.total; e += stride) {
-    i64 r = e, od = 0, os = 0;
+    IT r = (IT)e;
+    i64 od = 0, os = 0;
     for (int d = a.nd - 1; d >= 0; --d) {
-      const i64 i = r % a.dim[d];
-      r /= a.dim[d];
-      od += i * a.sd[d];
-      os += i * a.ss[d];
+      const IT n = (IT)a.dim[d], q = r / n, i = r - q * n;
+      r = q;
+      od += (i64)i * a.sd[d];
+      os += (i64)i * a.ss[d];
     }
     cplx y = make_double2(0.0, 0.0);
     if (a.ar != 0.0 || a.ai != 0.0) {  // alpha = 0 writes zeros without reading src
@@ -28,6 +32,58 @@ __global__ __launch_bounds__(256) void k_tcopy(CopyArgs a) {
       y.y += o.y;
     }
     a.dst[od] = y;
+  }
+}
+
+// Transposing form: the source's unit-stride index d0 and the destination's
+// unit-stride index d1 are tiled 32 x 32 through LDS, so both the reads and
+// the writes are unit-stride runs of 32 elements; the other indices (at most
+// four, in a.dim/sd/ss[0 .. a.nd - 1]) are the batch, one per blockIdx.y.
+struct TransArgs {
+  CopyArgs a;     // batch indices only
+  i64 n0, n1;     // extents of d0 and d1
+  i64 sd0, ss1;   // destination stride of d0, source stride of d1
+  i64 nbatch;
+};
+__global__ __launch_bounds__(256) void k_tcopy_t(TransArgs t) {
+  __shared__ cplx tile[32][33];
+  const CopyArgs& a = t.a;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const i64 t0n = (t.n0 + 31) / 32;
+  const i64 t0 = blockIdx.x % t0n, t1 = blockIdx.x / t0n;
+  const bool rd = a.ar != 0.0 || a.ai != 0.0;
+  for (i64 b = blockIdx.y; b < t.nbatch; b += gridDim.y) {
+    i64 r = b, od = 0, os = 0;
+    for (int d = a.nd - 1; d >= 0; --d) {
+      const i64 i = r % a.dim[d];
+      r /= a.dim[d];
+      od += i * a.sd[d];
+      os += i * a.ss[d];
+    }
+    __syncthreads();  // the previous batch entry's tile has been written out
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const i64 i0 = t0 * 32 + tx, i1 = t1 * 32 + ty + 8 * k;
+      cplx x = make_double2(0.0, 0.0);
+      if (rd && i0 < t.n0 && i1 < t.n1) x = a.src[os + i0 + i1 * t.ss1];
+      tile[ty + 8 * k][tx] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const i64 i1 = t1 * 32 + tx, i0 = t0 * 32 + ty + 8 * k;
+      if (i0 >= t.n0 || i1 >= t.n1) continue;
+      cplx x = tile[tx][ty + 8 * k];
+      if (a.conj) x.y = -x.y;
+      cplx y = make_double2(a.ar * x.x - a.ai * x.y, a.ar * x.y + a.ai * x.x);
+      cplx* p = a.dst + od + i1 + i0 * t.sd0;
+      if (a.acc) {
+        const cplx o = *p;
+        y.x += o.x;
+        y.y += o.y;
+      }
+      *p = y;
+    }
   }
 }
 
@@ -239,9 +295,67 @@ inline unsigned grid_for(i64 total) {
 }
 }  // namespace
 
-void launch_tcopy(const CopyArgs& a, hipStream_t s) {
-  if (a.total <= 0) return;
-  hipLaunchKernelGGL(k_tcopy, dim3(grid_for(a.total)), dim3(256), 0, s, a);
+void launch_tcopy(const CopyArgs& a0, hipStream_t s) {
+  if (a0.total <= 0) return;
+  // drop unit extents and merge neighbouring indices that are contiguous in
+  // both tensors (fewer divisions per element)
+  CopyArgs a = a0;
+  a.nd = 0;
+  for (int d = 0; d < a0.nd; ++d) {
+    if (a0.dim[d] == 1) continue;
+    const int k = a.nd - 1;
+    if (k >= 0 && a.sd[k] == a0.sd[d] * a0.dim[d] && a.ss[k] == a0.ss[d] * a0.dim[d]) {
+      a.dim[k] *= a0.dim[d];
+      a.sd[k] = a0.sd[d];
+      a.ss[k] = a0.ss[d];
+      continue;
+    }
+    a.dim[a.nd] = a0.dim[d];
+    a.sd[a.nd] = a0.sd[d];
+    a.ss[a.nd] = a0.ss[d];
+    ++a.nd;
+  }
+  if (a.nd == 0) {  // a single element
+    a.nd = 1;
+    a.dim[0] = 1;
+    a.sd[0] = a.ss[0] = 1;
+  }
+  // a transpose: the source and the destination have their unit strides on different indices
+  int d0 = -1, d1 = -1;
+  const bool rd = a.ar != 0.0 || a.ai != 0.0;
+  for (int d = 0; d < a.nd; ++d) {
+    if (a.ss[d] == 1 && a.dim[d] >= 16) d0 = d;
+    if (a.sd[d] == 1 && a.dim[d] >= 16) d1 = d;
+  }
+  if (rd && d0 >= 0 && d1 >= 0 && d0 != d1) {
+    TransArgs t{};
+    t.a = a;
+    t.a.nd = 0;
+    t.nbatch = 1;
+    for (int d = 0; d < a.nd; ++d) {
+      if (d == d0 || d == d1) continue;
+      t.a.dim[t.a.nd] = a.dim[d];
+      t.a.sd[t.a.nd] = a.sd[d];
+      t.a.ss[t.a.nd] = a.ss[d];
+      t.nbatch *= a.dim[d];
+      ++t.a.nd;
+    }
+    t.n0 = a.dim[d0];
+    t.n1 = a.dim[d1];
+    t.sd0 = a.sd[d0];
+    t.ss1 = a.ss[d1];
+    const i64 tiles = ((t.n0 + 31) / 32) * ((t.n1 + 31) / 32);
+    if (tiles < (1ll << 31)) {
+      hipLaunchKernelGGL(k_tcopy_t, dim3((unsigned)tiles, (unsigned)std::min<i64>(t.nbatch, 65535)), dim3(256), 0, s,
+                         t);
+      HIPCHK(hipGetLastError());
+      return;
+    }
+  }
+  if (a.total < (1ll << 31))
+    hipLaunchKernelGGL(k_tcopy<unsigned>, dim3(grid_for(a.total)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_tcopy<i64>, dim3(grid_for(a.total)), dim3(256), 0, s, a);
   HIPCHK(hipGetLastError());
 }
 

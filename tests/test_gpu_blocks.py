@@ -305,3 +305,41 @@ def test_intermediates(gpu, o, v):
         assert not bad, bad
     finally:
         cc.cclr_destroy(ctx)
+
+
+TCOPY_CASES = [
+    ((100, 70), (1, 0)),            # 2-D transpose (LDS tiles, ragged edges)
+    ((8, 40, 50), (2, 0, 1)),       # 3-D cyclic permutation
+    ((6, 1, 33, 17, 5), (3, 1, 0, 4, 2)),  # unit extent, mixed sizes
+    ((4, 5, 6, 7), (0, 1, 2, 3)),   # identity: all indices merge into one
+    ((12, 9, 20), (0, 2, 1)),       # inner transpose with a batch index
+    ((3, 7, 11), (2, 1, 0)),        # all extents below 16: element-wise path
+    ((2, 3, 40, 2, 24, 3), (4, 1, 0, 5, 2, 3)),  # six indices, transpose of 40 and 24
+]
+
+
+@pytest.mark.parametrize("shape,perm", TCOPY_CASES)
+def test_strided_copy_forms(gpu, shape, perm):
+    """dst[i] = (acc ? dst : 0) + alpha op(src[P i]) for permutations through
+    every form of the strided copy, with conjugation, accumulation and the
+    alpha = 0 zero fill, against numpy."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_tcopy.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int]
+    rng = np.random.default_rng(sum(shape) + 7 * len(shape))
+    src = crand(rng, *shape)
+    out_shape = tuple(shape[p] for p in perm)
+    d0 = crand(rng, *out_shape)
+    nd = len(shape)
+    dims = (LL * nd)(*out_shape)
+    sd = (LL * nd)(*[int(np.prod(out_shape[d + 1:])) for d in range(nd)])
+    sstr = [int(np.prod(shape[d + 1:])) for d in range(nd)]
+    ss = (LL * nd)(*[sstr[perm[d]] for d in range(nd)])
+    want = np.transpose(src, perm)
+    for alpha, conj, acc in [(1.0 + 0j, 0, 0), (0.5 - 2j, 1, 1), (0j, 0, 0)]:
+        Sd, Dd = dev(src), dev(d0)
+        rc = L.cclr_dbg_tcopy(nd, dims, sd, ss, Dd.data_ptr(), Sd.data_ptr(), alpha.real, alpha.imag, conj, acc)
+        assert rc == 0
+        ref = (d0 if acc else 0) + alpha * (want.conj() if conj else want)
+        np.testing.assert_allclose(Dd.cpu().numpy(), ref, rtol=1e-14, atol=1e-14)
