@@ -428,6 +428,48 @@ PAPER_SIGMA_S = {(10, 102): (6, 1), (10, 130): (13, 2), (10, 160): (26, 5), (10,
                  (40, 102): (96, 8), (40, 130): (203, 13), (40, 160): (395, 21), (40, 200): (821, 37)}
 
 
+def copy_bench(cc, dev, reps=5):
+    """The library's strided copy (the engine's index permutations) on
+    o=20, v=200 shaped tensors: median time of `reps` calls after one, and the
+    algorithmic bandwidth (every element read and written once, 32 B)."""
+    import numpy as np
+    import torch
+    L = cc.lib()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_tcopy.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int]
+    rows = []
+    for shape, perm in [((200, 20, 200, 200), (1, 0, 2, 3)), ((200, 20, 200, 200), (0, 1, 3, 2)),
+                        ((20, 200, 20, 200), (0, 2, 1, 3)), ((4000, 4000), (1, 0)),
+                        ((200, 200, 20, 200), (2, 3, 0, 1))]:
+        g = torch.Generator(device=dev).manual_seed(5)
+        src = torch.randn(shape, dtype=torch.complex128, device=dev, generator=g)
+        out_shape = tuple(shape[p] for p in perm)
+        dst = torch.empty(out_shape, dtype=torch.complex128, device=dev)
+        nd = len(shape)
+        dims = (LL * nd)(*out_shape)
+        sd = (LL * nd)(*[int(np.prod(out_shape[d + 1:])) for d in range(nd)])
+        sstr = [int(np.prod(shape[d + 1:])) for d in range(nd)]
+        ss = (LL * nd)(*[sstr[perm[d]] for d in range(nd)])
+        ts = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc = L.cclr_dbg_tcopy(nd, dims, sd, ss, dst.data_ptr(), src.data_ptr(), 1.0, 0.0, 0, 0)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            assert rc == 0, rc
+        assert torch.equal(dst, src.permute(*perm))
+        t = sorted(ts[1:])[reps // 2]
+        tbs = 32 * src.numel() / t / 1e12
+        rows.append({"shape": list(shape), "perm": list(perm), "ms": round(t * 1e3, 3), "TB_per_s": round(tbs, 2),
+                     "frac_of_8TBs": round(tbs / 8.0, 3)})
+        log(f"copy {shape} perm {perm}: {t * 1e3:.3f} ms, {tbs:.2f} TB/s")
+        del src, dst
+        torch.cuda.empty_cache()
+    return rows
+
+
 def sweep_bench(cc, dev, seed=3, reps=3):
     """One right transform of one vector (FP64) at each of the paper's sigma
     benchmark shapes: median of reps timed calls after a warm-up call."""
@@ -599,10 +641,11 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--omega", type=float, default=0.0774)
     ap.add_argument("--gamma", type=float, default=0.005)
-    ap.add_argument("--mode", choices=["response", "sigma", "sweep", "cpu"], default="response",
+    ap.add_argument("--mode", choices=["response", "sigma", "sweep", "cpu", "copy"], default="response",
                     help="response: the whole job (default); sigma: transforms of --nvec vectors; sweep: one "
                          "transform at each of the paper's sigma-benchmark shapes; cpu: the oracle's timings on "
-                         "the host (transforms at four sizes, every core and one thread, and two response tensors)")
+                         "the host (transforms at four sizes, every core and one thread, and two response tensors); "
+                         "copy: the library's strided copy on index permutations of o=20, v=200 tensors")
     ap.add_argument("--nvec", type=int, default=12, help="vectors per transform call in --mode sigma")
     ap.add_argument("--max-subspace", type=int, default=24)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -742,6 +785,9 @@ def main():
 
     if args.mode == "cpu":
         print(json.dumps({"cpu_oracle_table": cpu_table(dev)}), flush=True)
+        return
+    if args.mode == "copy":
+        print(json.dumps({"strided_copy": copy_bench(cc, dev)}), flush=True)
         return
     if args.mode == "sweep":
         rows = sweep_bench(cc, dev)

@@ -149,6 +149,8 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(VS out, int oj, VS X, int 
   for (i64 e = (i64)blockIdx.x * kThreads + threadIdx.x; e < n; e += (i64)gridDim.x * kThreads) {
     cplx y = make_double2(0.0, 0.0);
     if (acc_out) y = e < ov ? os[e] : od[e - ov];
+    // four loads in flight per thread (the loop is latency-bound otherwise)
+#pragma unroll 4
     for (int j = 0; j < nj; ++j) {
       const cplx x = e < ov ? vs_s(X, r, xj0 + j, ov)[e] : vs_d(X, r, xj0 + j, nd)[e - ov];
       const cplx p = cmul(c[j], x);
