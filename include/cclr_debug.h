@@ -25,7 +25,7 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
  * order; 9, 10 and 11, 12: 64x64 and 128x64 four-product tiles with one LDS
  * buffer, plain and grouped order; 13, 14: 128x128 tiles, operands staged
  * through registers; 15, 16: 128x128 tiles with direct global-to-LDS operand
- * loads; plain and grouped order).  All pointers are device memory; strides in elements.  For tests
+ * loads; 17, 18: 64x256 direct-load tiles; plain and grouped order).  All pointers are device memory; strides in elements.  For tests
  * of every variant (the autotuner otherwise runs only the fastest). */
 int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c64* A, long long sAb, long long sAm,
                        long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
@@ -40,7 +40,7 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
 int cclr_dbg_tcopy(int nd, const long long* dim, const long long* sd, const long long* ss, cclr_c64* dst,
                    const cclr_c64* src, double ar, double ai, int conj, int acc);
 
-/* Split-K form of one FP64 MFMA variant (1 .. 16): the partial products
+/* Split-K form of one FP64 MFMA variant (1 .. 18): the partial products
  * W[s][m][n] = sum over k in chunk s (k = s kchunk .. min(K, (s+1) kchunk) - 1)
  * of A(m, k) B(k, n), for s < ceil(K / kchunk); A(m, k) = A[m sAm + k sAk],
  * B(k, n) = B[k sBk + n sBn]; device pointers.  For tests of the chunk

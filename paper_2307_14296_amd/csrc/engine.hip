@@ -606,7 +606,7 @@ constexpr int kTuneRows = 8192, kTuneBatch = 16;
 bool gemm_variant_grouped(int variant) {
   return (variant > GEMM_64x64_G4 && variant <= 2 * GEMM_64x64_G4) || variant == GEMM_64x64_G4_SB_GROUPED ||
          variant == GEMM_128x64_G4_SB_GROUPED || variant == GEMM_128x128_G4_GROUPED ||
-         variant == GEMM_128x128_DMA_GROUPED;
+         variant == GEMM_128x128_DMA_GROUPED || variant == GEMM_64x256_DMA_GROUPED;
 }
 int octave_bucket(int x) {
   int p = 1;
@@ -684,13 +684,13 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   (void)hipEventDestroy(e1);
   // within the timing noise (2%) of the fastest, prefer the variant that
   // re-reads its operands from HBM least for the same time: the XCD-grouped
-  // tile order first, then larger tiles (128x128, 128x64, 64x64), then the
+  // tile order first, then tiles of 128 rows and of 128 or more columns, then the
   // faster one
   {
     auto rereads = [](int v) {
       const int base = gemm_variant_grouped(v) && v <= 2 * GEMM_64x64_G4 ? v - GEMM_64x64_G4 : v;
       const bool rows128 = base == GEMM_128x64_G3 || base == GEMM_128x64_G4 || v == GEMM_128x64_G4_SB ||
-                           v == GEMM_128x64_G4_SB_GROUPED || v >= GEMM_128x128_G4;
+                           v == GEMM_128x64_G4_SB_GROUPED || (v >= GEMM_128x128_G4 && v < GEMM_64x256_DMA);
       const bool cols128 = v >= GEMM_128x128_G4;
       return (gemm_variant_grouped(v) ? 0 : 3) + (rows128 ? 0 : 1) + (cols128 ? 0 : 1);
     };

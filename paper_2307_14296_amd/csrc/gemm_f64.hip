@@ -607,7 +607,7 @@ __global__ __launch_bounds__(512, 2) void k_zgemm_group_w1(const GemmArgs* __res
 }
 
 // --------------------------------------------------------------------------
-// 128x128 four-product tile whose operand tiles go from HBM to LDS by direct
+// 128x128 (or 64x256) four-product tile whose operand tiles go from HBM to LDS by direct
 // loads (global_load_lds_dwordx4: each lane names one 16-byte complex element,
 // the wave's 64 elements land as one contiguous KiB of LDS), so no register
 // staging, no LDS stores and no wait for the global loads sit in the K loop.
@@ -626,25 +626,34 @@ __global__ __launch_bounds__(512, 2) void k_zgemm_group_w1(const GemmArgs* __res
 // Conjugation flips the sign of the imaginary part of each operand fragment
 // (a separate instantiation, so products without it carry no flips).
 // --------------------------------------------------------------------------
-template <bool KC>
+// row and k of this lane's element of 1 KiB chunk c of an operand tile of R rows
+template <bool KC, int R>
 __device__ __forceinline__ int dma_row(int c, int lane) {
-  return KC ? 4 * c + (lane >> 4) : (c & 1) * 64 + lane;
+  return KC ? 4 * c + (lane >> 4) : (c % (R / 64)) * 64 + lane;
 }
-template <bool KC>
+template <bool KC, int R>
 __device__ __forceinline__ int dma_k(int c, int lane) {
-  return KC ? (lane & 15) ^ ((4 * c + (lane >> 4)) & 15) : c >> 1;
+  return KC ? (lane & 15) ^ ((4 * c + (lane >> 4)) & 15) : c / (R / 64);
 }
 __device__ __forceinline__ void dma16(const cplx* src, cplx* lds) {
   __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                    (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
-constexpr int kDmaTile = 128 * 16;  // complex elements per operand tile and stage
+// tile shapes: BM x BN with eight waves of 64 x 32 (BM = 128: 2 x 4 waves,
+// BN = 128; BM = 64: 1 x 8 waves, BN = 256, for products with few rows)
+template <int BM>
+struct DmaShape {
+  static constexpr int WAVES_M = BM / 64, WAVES_N = 8 / WAVES_M, BN = WAVES_N * 32;
+  static constexpr int TA = BM * 16, TB = BN * 16;  // complex elements per operand tile and stage
+};
 
-template <bool AK, bool BNF, bool CJ>
+template <int BM, bool AK, bool BNF, bool CJ>
 __device__ __forceinline__ void zgemm_tile_dma(const GemmArgs& g, const int m0, const int n0, const i64 bz,
                                                cplx* sA0, cplx* sA1, cplx* sB0, cplx* sB1) {
-  constexpr int BK = 16, WM = 64, WN = 32, FM = WM / 16, FN = WN / 16;
+  using SH = DmaShape<BM>;
+  constexpr int BN = SH::BN, BK = 16, WM = 64, WN = 32, FM = WM / 16, FN = WN / 16;
+  constexpr int JA = BM / 32, JB = BN / 32;  // 1 KiB chunks per wave and stage (of BM / 4 and BN / 4)
   constexpr bool KCA = AK, KCB = !BNF;  // which operands have unit-stride k
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int kbeg = 0, kend = g.K;
@@ -657,34 +666,38 @@ __device__ __forceinline__ void zgemm_tile_dma(const GemmArgs& g, const int m0, 
   }
   const cplx* __restrict__ A = g.A + boff(g, bb, g.sAb, g.sAb2);
   const cplx* __restrict__ B = g.B + boff(g, bb, g.sBb, g.sBb2);
-  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const int wm = (wave % SH::WAVES_M) * WM, wn = (wave / SH::WAVES_M) * WN;
   const unsigned sgnA = g.conjA ? 0x80000000u : 0u, sgnB = g.conjB ? 0x80000000u : 0u;
   const int nfull = (kend - kbeg) / BK, tail = kend - kbeg - nfull * BK;
-  // this lane's element of each of its four 1 KiB chunks (chunk c = 8 j + wave) of a K tile
-  const cplx* pa[4];
-  const cplx* pb[4];
+  // this lane's element of each of its 1 KiB chunks (chunk c = 8 j + wave) of a K tile
+  const cplx* pa[JA];
+  const cplx* pb[JB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < JA; ++j) {
     const int c = 8 * j + wave;
-    const int ra = min(m0 + dma_row<KCA>(c, lane), g.M - 1), rb = min(n0 + dma_row<KCB>(c, lane), g.N - 1);
-    pa[j] = A + (i64)ra * g.sAm + (i64)(kbeg + dma_k<KCA>(c, lane)) * g.sAk;
-    pb[j] = B + (i64)rb * g.sBn + (i64)(kbeg + dma_k<KCB>(c, lane)) * g.sBk;
+    const int ra = min(m0 + dma_row<KCA, BM>(c, lane), g.M - 1);
+    pa[j] = A + (i64)ra * g.sAm + (i64)(kbeg + dma_k<KCA, BM>(c, lane)) * g.sAk;
+  }
+#pragma unroll
+  for (int j = 0; j < JB; ++j) {
+    const int c = 8 * j + wave;
+    const int rb = min(n0 + dma_row<KCB, BN>(c, lane), g.N - 1);
+    pb[j] = B + (i64)rb * g.sBn + (i64)(kbeg + dma_k<KCB, BN>(c, lane)) * g.sBk;
   }
   const i64 dA = (i64)BK * g.sAk, dB = (i64)BK * g.sBk;
   auto fetch = [&](int t, cplx* la, cplx* lb) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      dma16(pa[j] + t * dA, la + 64 * (8 * j + wave));
-      dma16(pb[j] + t * dB, lb + 64 * (8 * j + wave));
-    }
+    for (int j = 0; j < JA; ++j) dma16(pa[j] + t * dA, la + 64 * (8 * j + wave));
+#pragma unroll
+    for (int j = 0; j < JB; ++j) dma16(pb[j] + t * dB, lb + 64 * (8 * j + wave));
   };
   // LDS element of this lane's fragment of K step q (k = 4q + lane/16) in block i (A) or j (B)
   const int rr = lane & 15, gq = lane >> 4;
   auto offa = [&](int q, int i) {
-    return KCA ? (wm + 16 * i + rr) * BK + ((4 * q + gq) ^ rr) : (4 * q + gq) * 128 + wm + 16 * i + rr;
+    return KCA ? (wm + 16 * i + rr) * BK + ((4 * q + gq) ^ rr) : (4 * q + gq) * BM + wm + 16 * i + rr;
   };
   auto offb = [&](int q, int j) {
-    return KCB ? (wn + 16 * j + rr) * BK + ((4 * q + gq) ^ rr) : (4 * q + gq) * 128 + wn + 16 * j + rr;
+    return KCB ? (wn + 16 * j + rr) * BK + ((4 * q + gq) ^ rr) : (4 * q + gq) * BN + wn + 16 * j + rr;
   };
   d4 cr[FM][FN], ci[FM][FN];
 #pragma unroll
@@ -761,12 +774,16 @@ __device__ __forceinline__ void zgemm_tile_dma(const GemmArgs& g, const int m0, 
     __syncthreads();  // every wave is done reading the stages before the remainder overwrites one
   }
   if (tail > 0) {  // K remainder: through registers, zero beyond kend (both stages are idle here)
+    const cplx z = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JA; ++j) {
       const int c = 8 * j + wave;
-      const cplx z = make_double2(0.0, 0.0);
-      sA0[64 * c + lane] = dma_k<KCA>(c, lane) < tail ? pa[j][nfull * dA] : z;
-      sB0[64 * c + lane] = dma_k<KCB>(c, lane) < tail ? pb[j][nfull * dB] : z;
+      sA0[64 * c + lane] = dma_k<KCA, BM>(c, lane) < tail ? pa[j][nfull * dA] : z;
+    }
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const int c = 8 * j + wave;
+      sB0[64 * c + lane] = dma_k<KCB, BN>(c, lane) < tail ? pb[j][nfull * dB] : z;
     }
     __syncthreads();
     compute(sA0, sB0);
@@ -794,15 +811,16 @@ __device__ __forceinline__ void zgemm_tile_dma(const GemmArgs& g, const int m0, 
       }
 }
 
-template <bool AK, bool BNF>
+template <int BM, bool AK, bool BNF>
 __global__ __launch_bounds__(512, 2) void k_zgemm_dma(GemmArgs g, int tm, int tn, int gm, int xcd) {
+  using SH = DmaShape<BM>;
   int mi, ni, bz;
   // the two stages of each operand are separate arrays, so the compiler knows
   // that reads of one stage do not depend on the direct loads into the other
-  __shared__ cplx sA0[kDmaTile], sA1[kDmaTile], sB0[kDmaTile], sB1[kDmaTile];
+  __shared__ cplx sA0[SH::TA], sA1[SH::TA], sB0[SH::TB], sB1[SH::TB];
   tile_of((int)blockIdx.x, (int)gridDim.x, tm, tn, gm, xcd, mi, ni, bz);
-  if (g.conjA || g.conjB) zgemm_tile_dma<AK, BNF, true>(g, mi * 128, ni * 128, bz, sA0, sA1, sB0, sB1);
-  else zgemm_tile_dma<AK, BNF, false>(g, mi * 128, ni * 128, bz, sA0, sA1, sB0, sB1);
+  if (g.conjA || g.conjB) zgemm_tile_dma<BM, AK, BNF, true>(g, mi * BM, ni * SH::BN, bz, sA0, sA1, sB0, sB1);
+  else zgemm_tile_dma<BM, AK, BNF, false>(g, mi * BM, ni * SH::BN, bz, sA0, sA1, sB0, sB1);
 }
 
 // grouped persistent form of the direct-load tile (one workgroup per CU); the
@@ -811,7 +829,7 @@ __global__ __launch_bounds__(512, 2) void k_zgemm_dma(GemmArgs g, int tm, int tn
 template <bool AK, bool BNF>
 __global__ __launch_bounds__(512, 2) void k_zgemm_group_dma(const GemmArgs* __restrict__ probs,
                                                            const int* __restrict__ tstart, int nprob, int total) {
-  __shared__ cplx sA0[kDmaTile], sA1[kDmaTile], sB0[kDmaTile], sB1[kDmaTile];
+  __shared__ cplx sA0[DmaShape<128>::TA], sA1[DmaShape<128>::TA], sB0[DmaShape<128>::TB], sB1[DmaShape<128>::TB];
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int p = 0;
     while (p + 1 < nprob && t >= tstart[p + 1]) ++p;
@@ -821,9 +839,9 @@ __global__ __launch_bounds__(512, 2) void k_zgemm_group_dma(const GemmArgs* __re
     const int mi = lt % tm, rest = lt / tm;
     __syncthreads();
     if (g.conjA || g.conjB)
-      zgemm_tile_dma<AK, BNF, true>(g, mi * 128, (rest % tn) * 128, rest / tn, sA0, sA1, sB0, sB1);
+      zgemm_tile_dma<128, AK, BNF, true>(g, mi * 128, (rest % tn) * 128, rest / tn, sA0, sA1, sB0, sB1);
     else
-      zgemm_tile_dma<AK, BNF, false>(g, mi * 128, (rest % tn) * 128, rest / tn, sA0, sA1, sB0, sB1);
+      zgemm_tile_dma<128, AK, BNF, false>(g, mi * 128, (rest % tn) * 128, rest / tn, sA0, sA1, sB0, sB1);
   }
 }
 
@@ -1175,23 +1193,30 @@ static void launch_w1(const GemmArgs& g, bool grouped, hipStream_t s) {
   else hipLaunchKernelGGL((k_zgemm_w1<false, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
 }
 
+template <int BM>
 static void launch_dma(const GemmArgs& g, bool grouped, hipStream_t s) {
+  constexpr int BN = DmaShape<BM>::BN;
   const bool ak = g.sAk == 1, bn = g.sBn == 1;
-  const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128, gm = grouped ? std::min(tm, kGroupM) : tm;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN, gm = grouped ? std::min(tm, kGroupM) : tm;
   const int xcd = grouped ? 1 : 0;
   const i64 total = (i64)tm * tn * g.batch;
   REQUIRE(total >= 1 && total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
   dim3 grid((unsigned)total);
-  if (ak && bn) hipLaunchKernelGGL((k_zgemm_dma<true, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
-  else if (ak) hipLaunchKernelGGL((k_zgemm_dma<true, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
-  else if (bn) hipLaunchKernelGGL((k_zgemm_dma<false, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
-  else hipLaunchKernelGGL((k_zgemm_dma<false, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_dma<BM, true, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_dma<BM, true, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_dma<BM, false, true>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
+  else hipLaunchKernelGGL((k_zgemm_dma<BM, false, false>), grid, dim3(512), 0, s, g, tm, tn, gm, xcd);
 }
 
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  if (variant == GEMM_64x256_DMA || variant == GEMM_64x256_DMA_GROUPED) {
+    launch_dma<64>(g, variant == GEMM_64x256_DMA_GROUPED, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   if (variant == GEMM_128x128_DMA || variant == GEMM_128x128_DMA_GROUPED) {
-    launch_dma(g, variant == GEMM_128x128_DMA_GROUPED, s);
+    launch_dma<128>(g, variant == GEMM_128x128_DMA_GROUPED, s);
     HIPCHK(hipGetLastError());
     return;
   }

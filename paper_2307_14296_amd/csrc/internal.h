@@ -124,12 +124,13 @@ void launch_zgemm(const GemmArgs& g, hipStream_t s);
 // waves per SIMD), plain and grouped order; 11, 12: the same for 128x64
 // tiles (two waves per SIMD); 13, 14: 128x128 four-product tiles with
 // double-buffered LDS and eight waves (two per SIMD, one workgroup per CU);
-// 15, 16: the same tile with direct global-to-LDS operand loads
+// 15, 16: the same tile with direct global-to-LDS operand loads; 17, 18: 64x256
+// direct-load tiles (eight waves in one row), for products with few rows
 enum {
   GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4,
   GEMM_64x64_G4_SB = 9, GEMM_64x64_G4_SB_GROUPED = 10, GEMM_128x64_G4_SB = 11, GEMM_128x64_G4_SB_GROUPED = 12,
   GEMM_128x128_G4 = 13, GEMM_128x128_G4_GROUPED = 14, GEMM_128x128_DMA = 15,
-  GEMM_128x128_DMA_GROUPED = 16, GEMM_NVAR = 17
+  GEMM_128x128_DMA_GROUPED = 16, GEMM_64x256_DMA = 17, GEMM_64x256_DMA_GROUPED = 18, GEMM_NVAR = 19
 };
 bool gemm_variant_grouped(int variant);
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);

@@ -89,7 +89,7 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
     B = crand(rng, batch, K, N)
     C0 = crand(rng, batch, M, N)
     alpha = 0.3 + 1.1j
-    for variant in range(17):
+    for variant in range(19):
         for ta, tb, beta, cj in [(False, False, 0, 1), (True, True, 1, 0), (False, True, 1, 1), (True, False, 0, 0),
                                  (False, True, 0, 0), (True, False, 1, 1)]:
             Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
@@ -118,7 +118,7 @@ def test_zgemm_split_k_every_variant(gpu, M, N, K, kchunk):
     B = crand(rng, K, N)
     S = (K + kchunk - 1) // kchunk
     ref = np.stack([A[:, s * kchunk:(s + 1) * kchunk] @ B[s * kchunk:(s + 1) * kchunk] for s in range(S)])
-    for variant in range(1, 17):
+    for variant in range(1, 19):
         for ta, tb in [(False, False), (False, True), (True, False)]:
             Ad = dev(A.T.copy() if ta else A)
             Bd = dev(B.T.copy() if tb else B)
