@@ -572,15 +572,19 @@ GEMM_SOURCE = os.path.join(ROOT, "paper_2307_14296_amd", "csrc", "gemm_f64.hip")
 
 
 def gemm_kernel_digest():
-    """sha256 of the source of the 128x128 direct-load FP64 GEMM: its tile
-    order function and its tile function and kernel, as marked in the GEMM
-    source (the rest of that file does not change what it moves)."""
+    """sha256 of the source of the direct-load FP64 GEMM: its tile order
+    function and its tile function and kernels, as marked in the GEMM source
+    (the rest of that file does not change what it moves); None if the
+    markers are not found."""
     import hashlib
-    text = open(GEMM_SOURCE).read()
-    i = text.index("__device__ __forceinline__ void tile_of(")
-    order = text[i:text.index("\n}\n", i) + 3]
-    j = text.index("// 128x128 four-product tile whose operand tiles go from HBM to LDS")
-    tile = text[j:text.index("// grouped persistent form of the direct-load tile", j)]
+    try:
+        text = open(GEMM_SOURCE).read()
+        i = text.index("__device__ __forceinline__ void tile_of(")
+        order = text[i:text.index("\n}\n", i) + 3]
+        j = text.index("four-product tile whose operand tiles go from HBM to LDS")
+        tile = text[j:text.index("// grouped persistent form of the direct-load tile", j)]
+    except (OSError, ValueError):
+        return None
     return hashlib.sha256((order + tile).encode()).hexdigest()
 
 
@@ -596,7 +600,8 @@ def ladder_traffic(variant):
         return None
     vals = dict(re.findall(r"^- (\w+): (\S+)$", text, flags=re.M))
     key = f"variant_{variant}_hbm_bytes_per_launch"
-    if variant not in (15, 16) or vals.get("dma_kernel_source_sha256") != gemm_kernel_digest() or key not in vals:
+    digest = gemm_kernel_digest()
+    if variant not in (15, 16) or digest is None or vals.get("dma_kernel_source_sha256") != digest or key not in vals:
         return None
     return float(vals[key])
 
