@@ -111,7 +111,8 @@ int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
 /* Per-product timing of the contraction engine's GEMMs: writes up to cap
  * bytes of the record so far, one line per product: "MxNxK bB sA(m,k)
  * sB(k,n) form F ms TFLOP/s" (F: FP64 variant >= 0, -1 short-reduction VALU
- * kernel, -2 split-K, -3 reduced precision, -4 short-output VALU kernel);
+ * kernel, -2 split-K, -3 reduced precision, -4 short-output VALU kernel, -5
+ * reduced precision on pre-split FP32 planes);
  * then, for enable >= 0, clears the record and switches timing on (1) or
  * off (0).  Timing synchronizes the stream after every product. */
 int cclr_dbg_gemm_trace(cclr_ctx* ctx, int enable, char* buf, long long cap);

@@ -506,7 +506,7 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
 // products to a workspace, summed in a fixed order afterwards.
 // form: the kernel that ran (FP64 variant >= 0, -1 short-reduction VALU
 // kernel, -2 split-K with the default variant, -3 reduced precision, -4
-// short-output VALU kernel)
+// short-output VALU kernel, -5 reduced precision on pre-split FP32 planes)
 static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form);
 void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
@@ -586,6 +586,21 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
   }
   if (lowp) {
     form = -3;
+    // large single products: each operand converted once to the three FP32
+    // Gauss planes, then the direct-load split kernel (the conversion passes
+    // cost less than the gain over converting inside the K loop once both
+    // output sides are a few hundred long)
+    if (g.batch == 1 && g.kchunk == 0 && g.nb2 <= 1 && g.M >= 512 && g.N >= 512 && g.K >= 256) {
+      form = -5;
+      Arena::Mark mk = c->arena.mark();
+      void* wa = c->arena.get(split_bytes(g.M, g.K, F32_G3, 0));
+      void* wb = c->arena.get(split_bytes(g.N, g.K, F32_G3, 1));
+      const SplitMat A = launch_split(g.M, g.K, g.A, g.sAm, g.sAk, g.conjA, wa, F32_G3, 0, c->stream);
+      const SplitMat B = launch_split(g.N, g.K, g.B, g.sBn, g.sBk, g.conjB, wb, F32_G3, 1, c->stream);
+      launch_split_gemm(A, B, g.C, g.sCm, g.sCn, g.ar, g.ai, g.beta, c->stream);
+      c->arena.reset(mk);
+      return;
+    }
     launch_zgemm_lowp(g, CCLR_FP32, c->stream);
   } else {
     form = tuned_gemm(c, g);

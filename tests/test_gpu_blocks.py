@@ -218,6 +218,51 @@ def test_run_gemm_dispatch(gpu, M, N, K, batch):
         cc.cclr_destroy(ctx)
 
 
+@pytest.mark.parametrize("M,N,K,batch", [(600, 530, 300, 1), (512, 700, 256, 1), (600, 530, 300, 2), (300, 530, 300, 1)])
+def test_run_gemm_dispatch_fp32(gpu, M, N, K, batch):
+    """The context's GEMM dispatch inside a reduced-precision transform (FP32
+    arithmetic): large single products on pre-split FP32 planes, batched or
+    narrower ones on the in-kernel conversion, with conjugation, complex
+    alpha, accumulation and a transposed output, within FP32 accuracy
+    (relative Frobenius error below 1e-5, and above 1e-12: FP32 really ran)."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_run_gemm.argtypes = [P] + [ctypes.c_int] * 4 + [P, LL, LL, LL, ctypes.c_int, P, LL, LL, LL,
+                                                               ctypes.c_int, P, LL, LL, LL, ctypes.c_double,
+                                                               ctypes.c_double, ctypes.c_int]
+    L.cclr_dbg_set_sigma_prec.argtypes = [P, ctypes.c_int]
+    ctx = cc.cclr_create(3, 6, cc.cclr_default_options())
+    try:
+        assert L.cclr_dbg_set_sigma_prec(ctx, cc.CCLR_FP32) == 0
+        rng = np.random.default_rng(M + 7 * N + K + batch)
+        for ta, conjA, conjB, beta, tc in [(False, 0, 1, 0, False), (True, 1, 0, 1, True), (False, 1, 1, 1, False)]:
+            A = crand(rng, batch, M, K)
+            B = crand(rng, batch, K, N)
+            C0 = crand(rng, batch, M, N)
+            Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
+            Bd = dev(B)
+            Cd = dev(C0.transpose(0, 2, 1).copy() if tc else C0)
+            sAm, sAk = (1, M) if ta else (K, 1)
+            sCm, sCn = (1, M) if tc else (N, 1)
+            alpha = 0.7 - 0.4j
+            rc = L.cclr_dbg_run_gemm(ctx, M, N, K, batch, Ad.data_ptr(), M * K, sAm, sAk, conjA, Bd.data_ptr(), K * N,
+                                     N, 1, conjB, Cd.data_ptr(), M * N, sCm, sCn, alpha.real, alpha.imag, beta)
+            assert rc == 0
+            Ae = A.conj() if conjA else A
+            Be = B.conj() if conjB else B
+            prod = alpha * (Ae @ Be)
+            got = Cd.cpu().numpy()
+            if tc:
+                got = got.transpose(0, 2, 1)
+            got = got - (C0 if beta else 0)
+            err = np.linalg.norm(got - prod) / np.linalg.norm(prod)
+            print(f"run_gemm FP32 {M}x{N}x{K} b{batch} ta={ta} conj=({conjA},{conjB}) beta={beta}: rel err {err:.1e}",
+                  flush=True)
+            assert 1e-12 < err < 1e-5
+    finally:
+        cc.cclr_destroy(ctx)
+
+
 def test_zgemm_batched_and_transposed_output(gpu):
     cc, L = _cc()
     rng = np.random.default_rng(5)
