@@ -163,13 +163,14 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int nb, int S, int M, int
 // Short reductions (K <= 32): memory-bound products such as the o-index
 // terms of the doubles.  FP64 on the vector ALU: the threads of a workgroup
 // run along n (coalesced B and C), each keeps its column of B in registers
-// and sweeps a block of 32 rows of A held in LDS, so every element of B and
-// C moves once.
+// and sweeps a block of 32 rows of A held in LDS, four rows at a time, so
+// every element of B and C moves once.
 // --------------------------------------------------------------------------
 constexpr int SK_MAX = 32, SK_MB = 32;
 
+template <int KM>  // an upper bound of K: 8, 16 or 32
 __global__ __launch_bounds__(256) void k_zgemm_smallk(GemmArgs g) {
-  __shared__ cplx sA[SK_MB][SK_MAX];
+  __shared__ cplx sA[SK_MB][KM];
   const i64 bz = blockIdx.z;
   const int n = blockIdx.x * 256 + threadIdx.x;
   const int m0 = blockIdx.y * SK_MB;
@@ -177,8 +178,8 @@ __global__ __launch_bounds__(256) void k_zgemm_smallk(GemmArgs g) {
   const cplx* __restrict__ B = g.B + boff(g, bz, g.sBb, g.sBb2);
   cplx* __restrict__ C = g.C + boff(g, bz, g.sCb, g.sCb2);
   const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
-  for (int e = threadIdx.x; e < SK_MB * SK_MAX; e += 256) {
-    const int mm = e / SK_MAX, kk = e % SK_MAX;
+  for (int e = threadIdx.x; e < SK_MB * KM; e += 256) {
+    const int mm = e / KM, kk = e % KM;
     cplx x = make_double2(0.0, 0.0);
     if (m0 + mm < g.M && kk < g.K) {
       x = A[(i64)(m0 + mm) * g.sAm + (i64)kk * g.sAk];
@@ -188,32 +189,38 @@ __global__ __launch_bounds__(256) void k_zgemm_smallk(GemmArgs g) {
   }
   __syncthreads();
   if (n >= g.N) return;
-  cplx b[SK_MAX];
+  cplx b[KM];
 #pragma unroll
-  for (int k = 0; k < SK_MAX; ++k) {
+  for (int k = 0; k < KM; ++k) {
     b[k] = make_double2(0.0, 0.0);
     if (k < g.K) {
       b[k] = B[(i64)k * g.sBk + (i64)n * g.sBn];
       b[k].y *= sb;
     }
   }
+  // four rows at a time: their C loads are in flight together
+  constexpr int R = 4;
   const int mend = min(SK_MB, g.M - m0);
-  for (int mm = 0; mm < mend; ++mm) {
-    double xr = 0.0, xi = 0.0;
+  for (int mm0 = 0; mm0 < mend; mm0 += R) {
+    cplx o[R];
 #pragma unroll
-    for (int k = 0; k < SK_MAX; ++k) {
-      const cplx a = sA[mm][k];
-      xr += a.x * b[k].x - a.y * b[k].y;
-      xi += a.x * b[k].y + a.y * b[k].x;
+    for (int r = 0; r < R; ++r) {
+      o[r] = make_double2(0.0, 0.0);
+      if (g.beta && mm0 + r < mend) o[r] = C[(i64)(m0 + mm0 + r) * g.sCm + (i64)n * g.sCn];
     }
-    cplx y = make_double2(g.ar * xr - g.ai * xi, g.ar * xi + g.ai * xr);
-    cplx* dst = C + (i64)(m0 + mm) * g.sCm + (i64)n * g.sCn;
-    if (g.beta) {
-      const cplx o = *dst;
-      y.x += o.x;
-      y.y += o.y;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (mm0 + r >= mend) break;
+      double xr = 0.0, xi = 0.0;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        const cplx a = sA[mm0 + r][k];
+        xr += a.x * b[k].x - a.y * b[k].y;
+        xi += a.x * b[k].y + a.y * b[k].x;
+      }
+      const cplx y = make_double2(g.ar * xr - g.ai * xi + o[r].x, g.ar * xi + g.ai * xr + o[r].y);
+      C[(i64)(m0 + mm0 + r) * g.sCm + (i64)n * g.sCn] = y;
     }
-    *dst = y;
   }
 }
 
@@ -1344,7 +1351,10 @@ bool launch_zgemm_smallk(const GemmArgs& g0, hipStream_t s) {
   }
   if (g.batch >= 65536 || (g.M + SK_MB - 1) / SK_MB >= 65536) return false;
   dim3 grid((g.N + 255) / 256, (g.M + SK_MB - 1) / SK_MB, g.batch);
-  hipLaunchKernelGGL(k_zgemm_smallk, grid, dim3(256), 0, s, g);
+  // the reduction length rounded up to 8, 16 or 32 (registers for B and FMAs scale with it)
+  if (g.K <= 8) hipLaunchKernelGGL(k_zgemm_smallk<8>, grid, dim3(256), 0, s, g);
+  else if (g.K <= 16) hipLaunchKernelGGL(k_zgemm_smallk<16>, grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(k_zgemm_smallk<32>, grid, dim3(256), 0, s, g);
   HIPCHK(hipGetLastError());
   return true;
 }

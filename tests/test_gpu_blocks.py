@@ -175,7 +175,9 @@ DISPATCH_CASES = [(20, 300, 5000, 1), (300, 20, 700, 3), (3, 1000, 700, 2), (1, 
                   # reductions, ragged row blocks and K chunks); 17 and more stay on MFMA
                   (16, 300, 2000, 3), (300, 16, 2000, 2), (260, 9, 5000, 4), (5000, 3, 40, 3), (70, 1, 129, 2),
                   (2, 500, 300, 2), (300, 6, 1000, 1),
-                  (24, 700, 3000, 2), (130, 17, 129, 2)]
+                  (24, 700, 3000, 2), (130, 17, 129, 2),
+                  # short reductions of every length class (K <= 8, 16, 32), ragged row blocks
+                  (70, 300, 5, 2), (100, 600, 12, 1), (33, 257, 32, 3), (45, 130, 17, 2)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", DISPATCH_CASES)
