@@ -182,7 +182,7 @@ static void hessian_block(cclr_ctx* c, const VecSet& xin, const VecSet& out) {
     g.B = c->Wp.c(); g.sBk = V2; g.sBn = 1;
     g.C = lo.d; g.sCm = V2; g.sCn = 1;
     g.ar = 1.0; g.ai = 0.0; g.beta = 0;
-    with_plain_wp(c, [&]() { launch_zgemm(g, c->stream); });
+    with_plain_wp(c, [&]() { tuned_gemm(c, g); });
     launch_unpack(1, (int)o, (int)v, lo.s, lo.d, nullptr, LW.p, c->stream);
   }
   contract(c, half, Woooo, "kimn", l2, "mnca", LW, "kica");
