@@ -25,7 +25,9 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
  * order; 9, 10 and 11, 12: 64x64 and 128x64 four-product tiles with one LDS
  * buffer, plain and grouped order; 13, 14: 128x128 tiles, operands staged
  * through registers; 15, 16: 128x128 tiles with direct global-to-LDS operand
- * loads; 17, 18: 64x256 direct-load tiles; plain and grouped order).  All pointers are device memory; strides in elements.  For tests
+ * loads; 17, 18: 64x256 direct-load tiles; plain and grouped order; 19: 128x32
+ * tiles with one LDS buffer, 20: 64x32 tiles, for outputs at most 32 wide).
+ * All pointers are device memory; strides in elements.  For tests
  * of every variant (the autotuner otherwise runs only the fastest). */
 int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c64* A, long long sAb, long long sAm,
                        long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
@@ -40,7 +42,7 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
 int cclr_dbg_tcopy(int nd, const long long* dim, const long long* sd, const long long* ss, cclr_c64* dst,
                    const cclr_c64* src, double ar, double ai, int conj, int acc);
 
-/* Split-K form of one FP64 MFMA variant (1 .. 18): the partial products
+/* Split-K form of one FP64 MFMA variant (1 .. 20): the partial products
  * W[s][m][n] = sum over k in chunk s (k = s kchunk .. min(K, (s+1) kchunk) - 1)
  * of A(m, k) B(k, n), for s < ceil(K / kchunk); A(m, k) = A[m sAm + k sAk],
  * B(k, n) = B[k sBk + n sBn]; device pointers.  For tests of the chunk
@@ -57,9 +59,10 @@ int cclr_dbg_zgemm_group_f64(int variant, int nprob, const int* M, const int* N,
 
 /* The same product (device pointers, the context's stream) through the
  * context's GEMM dispatch: the short-reduction vector-ALU kernel, the
- * short-output vector-ALU kernel (at most 16 columns), split-K, or the
- * autotuned MFMA kernels, chosen by shape as for the contractions of a
- * transform. */
+ * short-output vector-ALU kernels (at most 16 columns with the long operand
+ * contiguous in m, at most 8 with it contiguous in k), split-K, or the
+ * autotuned MFMA kernels (a product with at most 32 rows and more columns
+ * runs transposed), chosen by shape as for the contractions of a transform. */
 int cclr_dbg_run_gemm(cclr_ctx* ctx, int M, int N, int K, int batch, const cclr_c64* A, long long sAb, long long sAm,
                       long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
                       int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double alpha_re,
@@ -110,9 +113,12 @@ int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
 
 /* Per-product timing of the contraction engine's GEMMs: writes up to cap
  * bytes of the record so far, one line per product: "MxNxK bB sA(m,k)
- * sB(k,n) form F ms TFLOP/s" (F: FP64 variant >= 0, -1 short-reduction VALU
+ * sB(k,n) sC(m,n) sb(A,B,C) beta E form F ms TFLOP/s" (sb: the batch
+ * strides; E: 1 when the product accumulates into C; F: FP64 variant >= 0,
+ * -1 short-reduction VALU
  * kernel, -2 split-K, -3 reduced precision, -4 short-output VALU kernel, -5
- * reduced precision on pre-split FP32 planes);
+ * reduced precision on pre-split FP32 planes, -6 short-output VALU kernel on
+ * a long operand contiguous in k);
  * then, for enable >= 0, clears the record and switches timing on (1) or
  * off (0).  Timing synchronizes the stream after every product. */
 int cclr_dbg_gemm_trace(cclr_ctx* ctx, int enable, char* buf, long long cap);

@@ -506,7 +506,8 @@ void contract(cclr_ctx* c, cplx alpha, const Ten& A, const char* la, const Ten& 
 // products to a workspace, summed in a fixed order afterwards.
 // form: the kernel that ran (FP64 variant >= 0, -1 short-reduction VALU
 // kernel, -2 split-K with the default variant, -3 reduced precision, -4
-// short-output VALU kernel, -5 reduced precision on pre-split FP32 planes)
+// short-output VALU kernel, -5 reduced precision on pre-split FP32 planes, -6
+// short-output VALU kernel on a long operand contiguous in k)
 static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form);
 void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
@@ -526,16 +527,33 @@ void run_gemm(cclr_ctx* c, const GemmArgs& g) {
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  char line[256];
-  snprintf(line, sizeof line, "%dx%dx%d b%d sA(%lld,%lld) sB(%lld,%lld) form %d %.4f ms %.2f TFLOP/s", g.M, g.N, g.K,
-           g.batch, (long long)g.sAm, (long long)g.sAk, (long long)g.sBk, (long long)g.sBn, form, ms,
+  char line[384];
+  snprintf(line, sizeof line,
+           "%dx%dx%d b%d sA(%lld,%lld) sB(%lld,%lld) sC(%lld,%lld) sb(%lld,%lld,%lld) beta %d form %d %.4f ms "
+           "%.2f TFLOP/s",
+           g.M, g.N, g.K, g.batch, (long long)g.sAm, (long long)g.sAk, (long long)g.sBk, (long long)g.sBn,
+           (long long)g.sCm, (long long)g.sCn, (long long)g.sAb, (long long)g.sBb, (long long)g.sCb, g.beta, form, ms,
            8.0 * g.M * (double)g.N * g.K * g.batch / (ms * 1e-3) / 1e12);
   c->gemm_trace_log.push_back(line);
 }
 
-static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
+// C^T = B^T A^T: the same product with the roles of m and n exchanged
+static GemmArgs transposed(const GemmArgs& g0) {
+  GemmArgs g = g0;
+  g.M = g0.N; g.N = g0.M;
+  g.A = g0.B; g.sAb = g0.sBb; g.sAb2 = g0.sBb2; g.sAm = g0.sBn; g.sAk = g0.sBk; g.conjA = g0.conjB;
+  g.B = g0.A; g.sBb = g0.sAb; g.sBb2 = g0.sAb2; g.sBk = g0.sAk; g.sBn = g0.sAm; g.conjB = g0.conjA;
+  g.sCm = g0.sCn; g.sCn = g0.sCm;
+  return g;
+}
+
+static void run_gemm_form(cclr_ctx* c, const GemmArgs& g0, int& form) {
   form = -1;
-  if (g.K <= 32 && launch_zgemm_smallk(g, c->stream)) return;
+  if (g0.K <= 32 && launch_zgemm_smallk(g0, c->stream)) return;
+  // FP64 MFMA tiles are at least 32 columns but 64 rows high: a product with
+  // a short m side (at most 32) and a long n side runs transposed, so that
+  // its short side can take the 32-column tiles
+  const GemmArgs g = (c->sigma_prec == CCLR_FP64 && g0.M <= 32 && g0.N > 32) ? transposed(g0) : g0;
   {
     // at most 16 output columns: FP64 VALU rows instead of mostly empty MFMA tiles
     GemmArgs h;
@@ -549,6 +567,19 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g, int& form) {
       Arena::Mark mk = c->arena.mark();
       cplx* W = (cplx*)c->arena.get(sizeof(cplx) * (size_t)h.batch * S * h.M * (size_t)h.N);
       launch_zgemm_skinny(h, kc, S, W, c->stream);
+      c->arena.reset(mk);
+      return;
+    }
+    // at most 8 output columns, long operand contiguous in k: rows dotted along k
+    if (rowdot_plan(g, kc, S)) {
+      form = -6;
+      if (S == 1) {
+        launch_zgemm_rowdot(g, kc, 1, nullptr, c->stream);
+        return;
+      }
+      Arena::Mark mk = c->arena.mark();
+      cplx* W = (cplx*)c->arena.get(sizeof(cplx) * (size_t)g.batch * S * g.M * (size_t)g.N);
+      launch_zgemm_rowdot(g, kc, S, W, c->stream);
       c->arena.reset(mk);
       return;
     }
@@ -636,12 +667,21 @@ int shape_bucket(int x) {
   return ((x + q - 1) / q) * q;
 }
 
+bool gemm_variant_narrow(int variant) { return variant == GEMM_128x32_G4_SB || variant == GEMM_64x32_G4; }
+
+// the variant of a product that is not timed: 32-column tiles for outputs at
+// most 32 wide, 64-row tiles when the output has at most 64 rows (a 128-row
+// tile would be mostly empty)
+static int untimed_variant(const GemmArgs& g) {
+  if (g.N <= 32) return g.M <= 64 ? GEMM_64x32_G4 : GEMM_128x32_G4_SB;
+  return g.M <= 64 ? GEMM_64x64_G4 : gemm_default_variant(g);
+}
+
 int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return -1;
   const double flops = 8.0 * g.M * (double)g.N * (g.kchunk > 0 ? g.kchunk : g.K) * g.batch;
   if (!c->autotune || flops < 5e10) {
-    // untimed: 64-row tiles when the output has at most 64 rows (a 128-row tile would be mostly empty)
-    const int v = g.M <= 64 ? GEMM_64x64_G4 : gemm_default_variant(g);
+    const int v = untimed_variant(g);
     launch_zgemm_variant(g, v, c->stream);
     return v;
   }
@@ -659,7 +699,7 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
     return it->second;
   }
   if (c->no_timing) {  // a call that may not allocate: the untimed choice
-    const int v = g.M <= 64 ? GEMM_64x64_G4 : gemm_default_variant(g);
+    const int v = untimed_variant(g);
     launch_zgemm_variant(g, v, c->stream);
     return v;
   }
@@ -683,6 +723,10 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   int best = gemm_default_variant(g);
   double tbest = 1e300;
   for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) {  // the simple kernel (variant 0) never competes
+    if (gemm_variant_narrow(v) && g.N > kNarrowMaxN) {
+      ms[v] = 1e30;  // 32-column tiles on a wide output: not timed
+      continue;
+    }
     HIPCHK(hipEventRecord(e0, c->stream));
     launch_zgemm_variant(h, v, c->stream);
     HIPCHK(hipEventRecord(e1, c->stream));
@@ -705,8 +749,9 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
     auto rereads = [](int v) {
       const int base = gemm_variant_grouped(v) && v <= 2 * GEMM_64x64_G4 ? v - GEMM_64x64_G4 : v;
       const bool rows128 = base == GEMM_128x64_G3 || base == GEMM_128x64_G4 || v == GEMM_128x64_G4_SB ||
-                           v == GEMM_128x64_G4_SB_GROUPED || (v >= GEMM_128x128_G4 && v < GEMM_64x256_DMA);
-      const bool cols128 = v >= GEMM_128x128_G4;
+                           v == GEMM_128x64_G4_SB_GROUPED || (v >= GEMM_128x128_G4 && v < GEMM_64x256_DMA) ||
+                           v == GEMM_128x32_G4_SB;
+      const bool cols128 = v >= GEMM_128x128_G4 && !gemm_variant_narrow(v);
       return (gemm_variant_grouped(v) ? 0 : 3) + (rows128 ? 0 : 1) + (cols128 ? 0 : 1);
     };
     int pick = best;
@@ -719,7 +764,8 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   c->arena.reset(mk);
   c->gemm_choice[key] = best;
   std::vector<std::pair<int, double>> rec;
-  for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) rec.push_back({v, ms[v]});
+  for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v)
+    if (ms[v] < 1e29) rec.push_back({v, ms[v]});  // the variants that were timed
   // the product's shape, then the part that was timed (at most kTuneRows rows and kTuneBatch batch entries)
   c->gemm_tuning_log.push_back({std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + " b" +
                                     std::to_string(g.batch) + " layout" + std::to_string(std::get<4>(key)) +

@@ -1173,18 +1173,18 @@ static void launch_p(const GemmArgs& g, bool grouped, hipStream_t s) {
   else hipLaunchKernelGGL((k_zgemm_p<BM, BN, false, false, G3>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
 }
 
-template <int BM>
+template <int BM, int BN = 64>
 static void launch_p1(const GemmArgs& g, bool grouped, hipStream_t s) {
   const bool ak = g.sAk == 1, bn = g.sBn == 1;
-  const int tm = (g.M + BM - 1) / BM, tn = (g.N + 63) / 64, gm = grouped ? std::min(tm, kGroupM) : tm;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN, gm = grouped ? std::min(tm, kGroupM) : tm;
   const int xcd = grouped ? 1 : 0;
   const i64 total = (i64)tm * tn * g.batch;
   REQUIRE(total >= 1 && total < (1ll << 31), CCLR_EINVAL, "GEMM launch has too many tiles");
   dim3 grid((unsigned)total);
-  if (ak && bn) hipLaunchKernelGGL((k_zgemm_p1<BM, 64, true, true, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
-  else if (ak) hipLaunchKernelGGL((k_zgemm_p1<BM, 64, true, false, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
-  else if (bn) hipLaunchKernelGGL((k_zgemm_p1<BM, 64, false, true, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
-  else hipLaunchKernelGGL((k_zgemm_p1<BM, 64, false, false, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  if (ak && bn) hipLaunchKernelGGL((k_zgemm_p1<BM, BN, true, true, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (ak) hipLaunchKernelGGL((k_zgemm_p1<BM, BN, true, false, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else if (bn) hipLaunchKernelGGL((k_zgemm_p1<BM, BN, false, true, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
+  else hipLaunchKernelGGL((k_zgemm_p1<BM, BN, false, false, false>), grid, dim3(256), 0, s, g, tm, tn, gm, xcd);
 }
 
 static void launch_w1(const GemmArgs& g, bool grouped, hipStream_t s) {
@@ -1224,6 +1224,16 @@ void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s) {
   }
   if (variant == GEMM_128x128_DMA || variant == GEMM_128x128_DMA_GROUPED) {
     launch_dma<128>(g, variant == GEMM_128x128_DMA_GROUPED, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  if (variant == GEMM_128x32_G4_SB) {
+    launch_p1<128, 32>(g, false, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  if (variant == GEMM_64x32_G4) {
+    launch_p<64, 32, false>(g, false, s);
     HIPCHK(hipGetLastError());
     return;
   }
@@ -1272,11 +1282,14 @@ static void launch_group(const GemmArgs* probs, const int* tstart, int nprob, in
 
 int gemm_tile_rows(int variant) {
   return (variant == GEMM_128x64_G3 || variant == GEMM_128x64_G4 || variant == GEMM_128x128_G4 ||
-          variant == GEMM_128x128_DMA)
+          variant == GEMM_128x128_DMA || variant == GEMM_128x32_G4_SB)
              ? 128
              : 64;
 }
-int gemm_tile_cols(int variant) { return (variant == GEMM_128x128_G4 || variant == GEMM_128x128_DMA) ? 128 : 64; }
+int gemm_tile_cols(int variant) {
+  if (variant == GEMM_128x32_G4_SB || variant == GEMM_64x32_G4) return 32;
+  return (variant == GEMM_128x128_G4 || variant == GEMM_128x128_DMA) ? 128 : 64;
+}
 
 void launch_zgemm_group(const GemmArgs* probs, const int* tstart, int nprob, int total, int variant, bool ak, bool bn,
                         hipStream_t s) {

@@ -125,14 +125,20 @@ void launch_zgemm(const GemmArgs& g, hipStream_t s);
 // tiles (two waves per SIMD); 13, 14: 128x128 four-product tiles with
 // double-buffered LDS and eight waves (two per SIMD, one workgroup per CU);
 // 15, 16: the same tile with direct global-to-LDS operand loads; 17, 18: 64x256
-// direct-load tiles (eight waves in one row), for products with few rows
+// direct-load tiles (eight waves in one row), for products with few rows;
+// 19, 20: 128x32 (one LDS buffer) and 64x32 four-product tiles, for products
+// with at most 32 output columns (a 64-column tile would be mostly padding)
 enum {
   GEMM_SIMPLE = 0, GEMM_128x64_G3 = 1, GEMM_64x64_G3 = 2, GEMM_128x64_G4 = 3, GEMM_64x64_G4 = 4,
   GEMM_64x64_G4_SB = 9, GEMM_64x64_G4_SB_GROUPED = 10, GEMM_128x64_G4_SB = 11, GEMM_128x64_G4_SB_GROUPED = 12,
   GEMM_128x128_G4 = 13, GEMM_128x128_G4_GROUPED = 14, GEMM_128x128_DMA = 15,
-  GEMM_128x128_DMA_GROUPED = 16, GEMM_64x256_DMA = 17, GEMM_64x256_DMA_GROUPED = 18, GEMM_NVAR = 19
+  GEMM_128x128_DMA_GROUPED = 16, GEMM_64x256_DMA = 17, GEMM_64x256_DMA_GROUPED = 18, GEMM_128x32_G4_SB = 19,
+  GEMM_64x32_G4 = 20, GEMM_NVAR = 21
 };
+// the narrow variants (19, 20): timed by the autotuner only for outputs at most this wide
+constexpr int kNarrowMaxN = 64;
 bool gemm_variant_grouped(int variant);
+bool gemm_variant_narrow(int variant);
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);
 int gemm_default_variant(const GemmArgs& g);
 // Several products (same operand layouts: ak = unit-stride k in A, bn = unit-
@@ -189,6 +195,11 @@ bool launch_zgemm_smallk(const GemmArgs& g, hipStream_t s);
 // or returns false; S > 1 needs a workspace W of batch*S*M*N elements (the launch also sums it into C)
 bool skinny_plan(const GemmArgs& g0, GemmArgs& g, int& kc, int& S);
 void launch_zgemm_skinny(const GemmArgs& g, int kc, int S, cplx* W, hipStream_t s);
+// products with at most 8 output columns whose long operand has unit stride in k
+// (sAk = 1): chunk length kc and chunk count S (a workspace of batch*S*M*N
+// elements when S > 1)
+bool rowdot_plan(const GemmArgs& g, int& kc, int& S);
+void launch_zgemm_rowdot(const GemmArgs& g, int kc, int S, cplx* W, hipStream_t s);
 void launch_splitk_reduce(int nb, int S, int M, int N, const cplx* W, cplx* C, i64 sCb, i64 sCm, i64 sCn, double ar,
                           double ai, int beta, hipStream_t s);
 // GEMM with automatic K splitting when the output has too few tiles to fill the GPU

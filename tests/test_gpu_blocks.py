@@ -89,7 +89,7 @@ def test_zgemm_every_variant(gpu, M, N, K, batch):
     B = crand(rng, batch, K, N)
     C0 = crand(rng, batch, M, N)
     alpha = 0.3 + 1.1j
-    for variant in range(19):
+    for variant in range(21):
         for ta, tb, beta, cj in [(False, False, 0, 1), (True, True, 1, 0), (False, True, 1, 1), (True, False, 0, 0),
                                  (False, True, 0, 0), (True, False, 1, 1)]:
             Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
@@ -118,7 +118,7 @@ def test_zgemm_split_k_every_variant(gpu, M, N, K, kchunk):
     B = crand(rng, K, N)
     S = (K + kchunk - 1) // kchunk
     ref = np.stack([A[:, s * kchunk:(s + 1) * kchunk] @ B[s * kchunk:(s + 1) * kchunk] for s in range(S)])
-    for variant in range(1, 19):
+    for variant in range(1, 21):
         for ta, tb in [(False, False), (False, True), (True, False)]:
             Ad = dev(A.T.copy() if ta else A)
             Bd = dev(B.T.copy() if tb else B)
@@ -176,6 +176,11 @@ DISPATCH_CASES = [(20, 300, 5000, 1), (300, 20, 700, 3), (3, 1000, 700, 2), (1, 
                   (16, 300, 2000, 3), (300, 16, 2000, 2), (260, 9, 5000, 4), (5000, 3, 40, 3), (70, 1, 129, 2),
                   (2, 500, 300, 2), (300, 6, 1000, 1),
                   (24, 700, 3000, 2), (130, 17, 129, 2),
+                  # at most 8 output columns with the long operand contiguous in k (row-dot kernel, direct and
+                  # transposed, split and whole reductions, ragged row blocks and K chunks)
+                  (700, 2, 2000, 1), (1, 300, 3000, 2), (5, 257, 1500, 1), (1000, 8, 700, 2),
+                  # at most 32 output columns or rows on the 32-column MFMA tiles (a short m side runs transposed)
+                  (2000, 20, 200, 1), (20, 3000, 400, 2), (32, 1500, 64, 1),
                   # short reductions of every length class (K <= 8, 16, 32), ragged row blocks
                   (70, 300, 5, 2), (100, 600, 12, 1), (33, 257, 32, 3), (45, 130, 17, 2)]
 
@@ -193,18 +198,20 @@ def test_run_gemm_dispatch(gpu, M, N, K, batch):
     ctx = cc.cclr_create(3, 6, cc.cclr_default_options())
     try:
         rng = np.random.default_rng(M + 7 * N + K + batch)
-        for ta, conjA, conjB, beta, tc in [(False, 0, 1, 0, False), (True, 1, 0, 1, True)]:
+        for ta, tb, conjA, conjB, beta, tc in [(False, False, 0, 1, 0, False), (True, False, 1, 0, 1, True),
+                                               (False, True, 1, 1, 1, False)]:
             A = crand(rng, batch, M, K)
             B = crand(rng, batch, K, N)
             C0 = crand(rng, batch, M, N)
             Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
-            Bd = dev(B)
+            Bd = dev(B.transpose(0, 2, 1).copy() if tb else B)
             Cd = dev(C0.transpose(0, 2, 1).copy() if tc else C0)
             sAm, sAk = (1, M) if ta else (K, 1)
+            sBk, sBn = (1, K) if tb else (N, 1)
             sCm, sCn = (1, M) if tc else (N, 1)
             alpha = 0.7 - 0.4j
             rc = L.cclr_dbg_run_gemm(ctx, M, N, K, batch, Ad.data_ptr(), M * K, sAm, sAk, conjA, Bd.data_ptr(), K * N,
-                                     N, 1, conjB, Cd.data_ptr(), M * N, sCm, sCn, alpha.real, alpha.imag, beta)
+                                     sBk, sBn, conjB, Cd.data_ptr(), M * N, sCm, sCn, alpha.real, alpha.imag, beta)
             assert rc == 0
             Ae = A.conj() if conjA else A
             Be = B.conj() if conjB else B
@@ -213,9 +220,55 @@ def test_run_gemm_dispatch(gpu, M, N, K, batch):
             if tc:
                 got = got.transpose(0, 2, 1)
             err = np.abs(got - ref).max() / np.abs(ref).max()
-            print(f"run_gemm {M}x{N}x{K} b{batch} ta={ta} conj=({conjA},{conjB}) beta={beta}: rel err {err:.1e}",
-                  flush=True)
+            print(f"run_gemm {M}x{N}x{K} b{batch} ta={ta} tb={tb} conj=({conjA},{conjB}) beta={beta}: "
+                  f"rel err {err:.1e}", flush=True)
             assert err <= 1e-12
+    finally:
+        cc.cclr_destroy(ctx)
+
+
+# (M, N, K, batch, A stored transposed, B stored transposed, kernel form the dispatch must choose):
+# -6 row-dot kernel, -4 short-output kernel, 19 the 128x32 MFMA tile (untimed choice for at most 32 columns)
+FORM_CASES = [(700, 2, 2000, 1, False, False, -6), (700, 2, 2000, 1, True, False, -4),
+              (1, 300, 3000, 2, False, True, -6), (1, 300, 3000, 2, False, False, -4),
+              (1000, 8, 700, 2, False, False, -6), (2000, 20, 200, 1, False, False, 19),
+              (20, 3000, 400, 2, False, False, 19), (32, 1500, 64, 1, True, True, 19)]
+
+
+@pytest.mark.parametrize("M,N,K,batch,ta,tb,form", FORM_CASES)
+def test_run_gemm_form_choice(gpu, M, N, K, batch, ta, tb, form):
+    """The dispatch picks the row-dot kernel for at most 8 columns on a long
+    operand contiguous in k (directly, or after transposing a product with
+    a short m side), and the 32-column MFMA tiles for outputs at most 32
+    wide (a short m side transposed first); the result is checked too."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_run_gemm.argtypes = [P] + [ctypes.c_int] * 4 + [P, LL, LL, LL, ctypes.c_int, P, LL, LL, LL,
+                                                               ctypes.c_int, P, LL, LL, LL, ctypes.c_double,
+                                                               ctypes.c_double, ctypes.c_int]
+    L.cclr_dbg_gemm_trace.argtypes = [P, ctypes.c_int, ctypes.c_char_p, ctypes.c_longlong]
+    ctx = cc.cclr_create(3, 6, cc.cclr_default_options())
+    try:
+        rng = np.random.default_rng(M + 5 * N + K)
+        A = crand(rng, batch, M, K)
+        B = crand(rng, batch, K, N)
+        Ad = dev(A.transpose(0, 2, 1).copy() if ta else A)
+        Bd = dev(B.transpose(0, 2, 1).copy() if tb else B)
+        Cd = torch.zeros((batch, M, N), dtype=torch.complex128, device="cuda")
+        sAm, sAk = (1, M) if ta else (K, 1)
+        sBk, sBn = (1, K) if tb else (N, 1)
+        assert L.cclr_dbg_gemm_trace(ctx, 1, None, 0) == 0
+        rc = L.cclr_dbg_run_gemm(ctx, M, N, K, batch, Ad.data_ptr(), M * K, sAm, sAk, 0, Bd.data_ptr(), K * N, sBk,
+                                 sBn, 0, Cd.data_ptr(), M * N, N, 1, 1.0, 0.0, 0)
+        assert rc == 0
+        buf = ctypes.create_string_buffer(1 << 16)
+        assert L.cclr_dbg_gemm_trace(ctx, 0, buf, len(buf)) == 0
+        lines = [ln for ln in buf.value.decode().splitlines() if ln]
+        print(lines, flush=True)
+        assert len(lines) == 1 and int(lines[0].split(" form ")[1].split()[0]) == form, lines
+        ref = A @ B
+        err = np.abs(Cd.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= 1e-12, err
     finally:
         cc.cclr_destroy(ctx)
 
