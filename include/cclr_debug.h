@@ -68,6 +68,13 @@ int cclr_dbg_run_gemm(cclr_ctx* ctx, int M, int N, int K, int batch, const cclr_
                       int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double alpha_re,
                       double alpha_im, int beta);
 
+/* The same dispatch with a two-level batch: batch entry b = b1 nb2 + b2
+ * (b1 < nb1, 1 < nb2) of X starts at b1 sXb + b2 sXb2; no conjugation. */
+int cclr_dbg_run_gemm_b2(cclr_ctx* ctx, int M, int N, int K, int nb1, int nb2, const cclr_c64* A, long long sAb,
+                         long long sAb2, long long sAm, long long sAk, const cclr_c64* B, long long sBb,
+                         long long sBb2, long long sBk, long long sBn, cclr_c64* C, long long sCb, long long sCb2,
+                         long long sCm, long long sCn, double alpha_re, double alpha_im, int beta);
+
 /* The same product (batch 1) in reduced arithmetic on pre-split operands, the
  * form of the transforms' ladder and ring products: prec = CCLR_FP32 (FP32
  * MFMA, three real products per complex block), CCLR_BF16X3 or CCLR_BF16X2

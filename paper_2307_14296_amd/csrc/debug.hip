@@ -26,6 +26,28 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
   }
 }
 
+int cclr_dbg_run_gemm_b2(cclr_ctx* c, int M, int N, int K, int nb1, int nb2, const cclr_c64* A, long long sAb,
+                         long long sAb2, long long sAm, long long sAk, const cclr_c64* B, long long sBb, long long sBb2,
+                         long long sBk, long long sBn, cclr_c64* C, long long sCb, long long sCb2, long long sCm,
+                         long long sCn, double ar, double ai, int beta) {
+  if (!c) return CCLR_EINVAL;
+  try {
+    REQUIRE(M > 0 && N > 0 && K > 0 && nb1 > 0 && nb2 > 1 && (long long)nb1 * nb2 < 65536, CCLR_EINVAL,
+            "two-level batch: empty product or batch out of range");
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K; g.batch = nb1 * nb2; g.nb2 = nb2;
+    g.A = (const cplx*)A; g.sAb = sAb; g.sAb2 = sAb2; g.sAm = sAm; g.sAk = sAk;
+    g.B = (const cplx*)B; g.sBb = sBb; g.sBb2 = sBb2; g.sBk = sBk; g.sBn = sBn;
+    g.C = (cplx*)C; g.sCb = sCb; g.sCb2 = sCb2; g.sCm = sCm; g.sCn = sCn;
+    g.ar = ar; g.ai = ai; g.beta = beta;
+    run_gemm(c, g);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const CclrError& e) {
+    return e.code;
+  }
+  return CCLR_OK;
+}
+
 int cclr_dbg_run_gemm(cclr_ctx* c, int M, int N, int K, int batch, const cclr_c64* A, long long sAb, long long sAm,
                       long long sAk, int conjA, const cclr_c64* B, long long sBb, long long sBk, long long sBn,
                       int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,

@@ -547,8 +547,67 @@ static GemmArgs transposed(const GemmArgs& g0) {
   return g;
 }
 
+// dst[b][e][r][q] (+)= src[b][e][r][q] between two strided 4-index views
+// (b, e: the two levels of a GEMM batch)
+static void copy4(cclr_ctx* c, const i64 (&dim)[4], cplx* dst, const i64 (&sd)[4], const cplx* src,
+                  const i64 (&ss)[4], bool acc) {
+  CopyArgs a{};
+  a.nd = 4;
+  a.total = 1;
+  for (int d = 0; d < 4; ++d) {
+    a.dim[d] = dim[d];
+    a.sd[d] = sd[d];
+    a.ss[d] = ss[d];
+    a.total *= dim[d];
+  }
+  a.dst = dst;
+  a.src = src;
+  a.ar = 1.0;
+  a.ai = 0.0;
+  a.conj = 0;
+  a.acc = acc ? 1 : 0;
+  launch_tcopy(a, c->stream);
+}
+
 static void run_gemm_form(cclr_ctx* c, const GemmArgs& g0, int& form) {
   form = -1;
+  // An operand or output whose unit stride is a batch index would have every
+  // tile (or every thread's row) touch one element per cache line of it:
+  // such tensors are copied to a batch-outermost layout first, and the
+  // output is added back afterwards.
+  if (g0.kchunk == 0 && g0.batch >= 8) {
+    const i64 M = g0.M, N = g0.N, K = g0.K;
+    const i64 n2 = g0.nb2 > 1 ? g0.nb2 : 1, n1 = g0.batch / n2;
+    auto inner = [&](i64 s1, i64 s2, i64 sz) { return sz > 1 && (s1 == 1 || (n2 > 1 && s2 == 1)); };
+    const bool ca = inner(g0.sAb, g0.sAb2, M * K), cb = inner(g0.sBb, g0.sBb2, K * N),
+               cc = inner(g0.sCb, g0.sCb2, M * N);
+    const i64 big = (i64)g0.batch * std::max({ca ? M * K : 0, cb ? K * N : 0, cc ? M * N : 0});
+    if ((ca || cb || cc) && big >= (i64(1) << 20)) {
+      Arena::Mark mk = c->arena.mark();
+      GemmArgs h = g0;
+      const i64 s2b = n2 > 1 ? 1 : 0;  // the second batch level's stride factor in the copies
+      if (ca) {
+        cplx* t = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(g0.batch * M * K));
+        copy4(c, {n1, n2, M, K}, t, {n2 * M * K, M * K, K, 1}, g0.A, {g0.sAb, s2b * g0.sAb2, g0.sAm, g0.sAk}, false);
+        h.A = t; h.sAb = n2 * M * K; h.sAb2 = M * K; h.sAm = K; h.sAk = 1;
+      }
+      if (cb) {
+        cplx* t = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(g0.batch * K * N));
+        copy4(c, {n1, n2, K, N}, t, {n2 * K * N, K * N, N, 1}, g0.B, {g0.sBb, s2b * g0.sBb2, g0.sBk, g0.sBn}, false);
+        h.B = t; h.sBb = n2 * K * N; h.sBb2 = K * N; h.sBk = N; h.sBn = 1;
+      }
+      if (cc) {
+        cplx* t = (cplx*)c->arena.get(sizeof(cplx) * (size_t)(g0.batch * M * N));
+        h.C = t; h.sCb = n2 * M * N; h.sCb2 = M * N; h.sCm = N; h.sCn = 1; h.beta = 0;
+      }
+      run_gemm_form(c, h, form);
+      if (cc)
+        copy4(c, {n1, n2, M, N}, g0.C, {g0.sCb, s2b * g0.sCb2, g0.sCm, g0.sCn}, h.C, {n2 * M * N, M * N, N, 1},
+              g0.beta != 0);
+      c->arena.reset(mk);
+      return;
+    }
+  }
   if (g0.K <= 32 && launch_zgemm_smallk(g0, c->stream)) return;
   // FP64 MFMA tiles are at least 32 columns but 64 rows high: a product with
   // a short m side (at most 32) and a long n side runs transposed, so that

@@ -273,6 +273,93 @@ def test_run_gemm_form_choice(gpu, M, N, K, batch, ta, tb, form):
         cc.cclr_destroy(ctx)
 
 
+@pytest.mark.parametrize("M,N,K,batch,inner", [(200, 400, 20, 20, "C"), (100, 120, 64, 100, "BC"),
+                                                (300, 50, 80, 60, "A"), (70, 90, 40, 200, "ABC")])
+def test_run_gemm_batch_innermost(gpu, M, N, K, batch, inner):
+    """Products whose operands or output have the batch index as their unit
+    stride (the dispatch copies them to a batch-outermost layout and adds the
+    output back), with conjugation, complex alpha and accumulation."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_run_gemm.argtypes = [P] + [ctypes.c_int] * 4 + [P, LL, LL, LL, ctypes.c_int, P, LL, LL, LL,
+                                                               ctypes.c_int, P, LL, LL, LL, ctypes.c_double,
+                                                               ctypes.c_double, ctypes.c_int]
+    ctx = cc.cclr_create(3, 6, cc.cclr_default_options())
+    try:
+        rng = np.random.default_rng(M + N + K + batch)
+        A = crand(rng, batch, M, K)
+        B = crand(rng, batch, K, N)
+        C0 = crand(rng, batch, M, N)
+
+        def store(X, innermost):
+            # device copy and its (batch, row, column) strides
+            b, r, q = X.shape
+            if innermost:
+                return dev(X.transpose(1, 2, 0).copy()), (1, q * b, b)
+            return dev(X), (r * q, q, 1)
+
+        Ad, (sAb, sAm, sAk) = store(A, "A" in inner)
+        Bd, (sBb, sBk, sBn) = store(B, "B" in inner)
+        Cd, (sCb, sCm, sCn) = store(C0, "C" in inner)
+        alpha = -0.6 + 0.9j
+        rc = L.cclr_dbg_run_gemm(ctx, M, N, K, batch, Ad.data_ptr(), sAb, sAm, sAk, 1, Bd.data_ptr(), sBb, sBk, sBn, 0,
+                                 Cd.data_ptr(), sCb, sCm, sCn, alpha.real, alpha.imag, 1)
+        assert rc == 0
+        got = Cd.cpu().numpy()
+        if "C" in inner:
+            got = got.transpose(2, 0, 1)
+        ref = alpha * (A.conj() @ B) + C0
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"batch-innermost {inner} {M}x{N}x{K} b{batch}: rel err {err:.1e}", flush=True)
+        assert err <= 1e-12
+    finally:
+        cc.cclr_destroy(ctx)
+
+
+@pytest.mark.parametrize("M,N,K,nb1,nb2,inner,shared_b", [(60, 100, 50, 4, 50, "AC", False),
+                                                            (100, 80, 30, 3, 70, "C", True),
+                                                            (90, 70, 40, 2, 120, "B", False)])
+def test_run_gemm_two_level_batch_innermost(gpu, M, N, K, nb1, nb2, inner, shared_b):
+    """Two-level batches (b = b1 nb2 + b2) whose second index is the unit
+    stride of an operand or of the output, one case with B shared over b2
+    (stride 0), through the dispatch's batch-outermost copies."""
+    cc, L = _cc()
+    LL, P = ctypes.c_longlong, ctypes.c_void_p
+    L.cclr_dbg_run_gemm_b2.argtypes = [P] + [ctypes.c_int] * 5 + [P, LL, LL, LL, LL, P, LL, LL, LL, LL, P, LL, LL,
+                                                                  LL, LL, ctypes.c_double, ctypes.c_double,
+                                                                  ctypes.c_int]
+    ctx = cc.cclr_create(3, 6, cc.cclr_default_options())
+    try:
+        rng = np.random.default_rng(M + N + K + nb1 + nb2)
+        A = crand(rng, nb1, nb2, M, K)
+        B = crand(rng, nb1, 1 if shared_b else nb2, K, N)
+        C0 = crand(rng, nb1, nb2, M, N)
+
+        def store(X, innermost):
+            # device copy and its (b1, b2, row, column) strides
+            b1, b2, r, q = X.shape
+            if innermost:
+                return dev(X.transpose(0, 2, 3, 1).copy()), (r * q * b2, 1, q * b2, b2)
+            return dev(X), (b2 * r * q, 0 if b2 == 1 else r * q, q, 1)
+
+        Ad, (sAb, sAb2, sAm, sAk) = store(A, "A" in inner)
+        Bd, (sBb, sBb2, sBk, sBn) = store(B, "B" in inner)
+        Cd, (sCb, sCb2, sCm, sCn) = store(C0, "C" in inner)
+        alpha = 0.4 - 1.3j
+        rc = L.cclr_dbg_run_gemm_b2(ctx, M, N, K, nb1, nb2, Ad.data_ptr(), sAb, sAb2, sAm, sAk, Bd.data_ptr(), sBb,
+                                    sBb2, sBk, sBn, Cd.data_ptr(), sCb, sCb2, sCm, sCn, alpha.real, alpha.imag, 1)
+        assert rc == 0
+        got = Cd.cpu().numpy()
+        if "C" in inner:
+            got = got.transpose(0, 3, 1, 2)
+        ref = alpha * (A @ B) + C0
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"two-level batch {inner} {M}x{N}x{K} b{nb1}x{nb2}: rel err {err:.1e}", flush=True)
+        assert err <= 1e-12
+    finally:
+        cc.cclr_destroy(ctx)
+
+
 @pytest.mark.parametrize("M,N,K,batch", [(600, 530, 300, 1), (512, 700, 256, 1), (600, 530, 300, 2), (300, 530, 300, 1)])
 def test_run_gemm_dispatch_fp32(gpu, M, N, K, batch):
     """The context's GEMM dispatch inside a reduced-precision transform (FP32
