@@ -612,6 +612,11 @@ def gemm_kernel_name(variant):
     """HIP kernel behind an FP64 GEMM variant number of the autotuner."""
     if variant is None:
         return "FP64 GEMM"
+    variant %= 100  # 100 + v: variant v on the transposed product
+    if variant == 19:
+        return "k_zgemm_p1"
+    if variant == 20:
+        return "k_zgemm_p"
     if variant >= 15:
         return "k_zgemm_dma"
     if variant >= 13:

@@ -26,7 +26,8 @@ int cclr_dbg_zgemm(int M, int N, int K, int batch, const cclr_c64* A, long long 
  * buffer, plain and grouped order; 13, 14: 128x128 tiles, operands staged
  * through registers; 15, 16: 128x128 tiles with direct global-to-LDS operand
  * loads; 17, 18: 64x256 direct-load tiles; plain and grouped order; 19: 128x32
- * tiles with one LDS buffer, 20: 64x32 tiles, for outputs at most 32 wide).
+ * tiles with one LDS buffer, 20: 64x32 tiles, for outputs at most 32 wide;
+ * 100 + v: variant v on the transposed product C^T = B^T A^T).
  * All pointers are device memory; strides in elements.  For tests
  * of every variant (the autotuner otherwise runs only the fastest). */
 int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c64* A, long long sAb, long long sAm,
@@ -121,7 +122,8 @@ int cclr_dbg_set_inner_tol(cclr_ctx* ctx, double tol);
 /* Per-product timing of the contraction engine's GEMMs: writes up to cap
  * bytes of the record so far, one line per product: "MxNxK bB sA(m,k)
  * sB(k,n) sC(m,n) sb(A,B,C) beta E form F ms TFLOP/s" (sb: the batch
- * strides; E: 1 when the product accumulates into C; F: FP64 variant >= 0,
+ * strides; E: 1 when the product accumulates into C; F: FP64 variant >= 0
+ * (100 + v: variant v on the transposed product),
  * -1 short-reduction VALU
  * kernel, -2 split-K, -3 reduced precision, -4 short-output VALU kernel, -5
  * reduced precision on pre-split FP32 planes, -6 short-output VALU kernel on
@@ -169,7 +171,9 @@ int cclr_dbg_small_eig(int n, const cclr_c64* H, int nroots, cclr_c64* w, cclr_c
  * (the product's shape, then the part of it that was timed: at most 8192 rows
  * and 16 batch entries, so the times are those of the timed part; chosen is
  * the variant in use: within 2% of the fastest, the grouped tile order, then
- * larger tiles, are preferred).
+ * larger tiles, are preferred; 100 + v is variant v on the transposed product
+ * C^T = B^T A^T, timed for the 32-column variants when the row count is one
+ * they pad less than 64-row tiles would).
  * enable >= 0 switches tuning on (1) or off (0) for later products. */
 int cclr_dbg_tuning(cclr_ctx* ctx, int enable, char* buf, long long cap);
 

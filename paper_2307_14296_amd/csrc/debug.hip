@@ -74,7 +74,9 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
                        int conjB, cclr_c64* C, long long sCb, long long sCm, long long sCn, double ar, double ai,
                        int beta) {
   try {
-    REQUIRE(variant >= 0 && variant < GEMM_NVAR, CCLR_EINVAL, "no such GEMM variant");
+    REQUIRE((variant >= 0 && variant < GEMM_NVAR) ||
+                (variant > kTransposedChoice && variant < kTransposedChoice + GEMM_NVAR),
+            CCLR_EINVAL, "no such GEMM variant");
     REQUIRE(M > 0 && N > 0 && K > 0 && batch > 0, CCLR_EINVAL, "empty product");
     GemmArgs g{};
     g.M = M; g.N = N; g.K = K; g.batch = batch;
@@ -82,7 +84,7 @@ int cclr_dbg_zgemm_f64(int variant, int batch, int M, int N, int K, const cclr_c
     g.B = (const cplx*)B; g.sBb = sBb; g.sBk = sBk; g.sBn = sBn; g.conjB = conjB;
     g.C = (cplx*)C; g.sCb = sCb; g.sCm = sCm; g.sCn = sCn;
     g.ar = ar; g.ai = ai; g.beta = beta;
-    launch_zgemm_variant(g, variant, nullptr);
+    launch_gemm_choice(g, variant, nullptr);
     HIPCHK(hipDeviceSynchronize());
   } catch (const CclrError& e) {
     return e.code;

@@ -728,6 +728,15 @@ int shape_bucket(int x) {
 
 bool gemm_variant_narrow(int variant) { return variant == GEMM_128x32_G4_SB || variant == GEMM_64x32_G4; }
 
+// the 32-column tiles are worth timing for outputs at most kNarrowMaxN wide,
+// and for outputs up to 512 wide that 64-column tiles would pad by a further
+// eighth or more (200 columns: 224 against 256)
+static bool narrow_may_pay(int N) {
+  if (N <= kNarrowMaxN) return true;
+  const int p32 = (N + 31) / 32 * 32, p64 = (N + 63) / 64 * 64;
+  return N <= 512 && 8 * (p64 - p32) >= p32;
+}
+
 // the variant of a product that is not timed: 32-column tiles for outputs at
 // most 32 wide, 64-row tiles when the output has at most 64 rows (a 128-row
 // tile would be mostly empty)
@@ -735,6 +744,12 @@ static int untimed_variant(const GemmArgs& g) {
   if (g.N <= 32) return g.M <= 64 ? GEMM_64x32_G4 : GEMM_128x32_G4_SB;
   return g.M <= 64 ? GEMM_64x64_G4 : gemm_default_variant(g);
 }
+
+void launch_gemm_choice(const GemmArgs& g, int choice, hipStream_t s) {
+  if (choice >= kTransposedChoice) launch_zgemm_variant(transposed(g), choice - kTransposedChoice, s);
+  else launch_zgemm_variant(g, choice, s);
+}
+static void launch_choice(const GemmArgs& g, int choice, hipStream_t s) { launch_gemm_choice(g, choice, s); }
 
 int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return -1;
@@ -748,13 +763,16 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   const int tmr = std::min(g.M, kTuneRows),
             tbt = (g.nb2 > 1 || g.kchunk > 0) ? g.batch : std::min(g.batch, kTuneBatch);
   // split-K products (kchunk > 0: the batch index carries the K chunk) are classed by the chunk length
+  // (the transposed product runs on 32-column tiles only when its row count
+  // is one that they pad less, which the row octave alone does not tell)
+  const bool trans_narrow = g.M != g.N && narrow_may_pay(g.M);
   const auto key = std::make_tuple(octave_bucket(tmr), shape_bucket(g.N), shape_bucket(g.kchunk > 0 ? g.kchunk : g.K),
                                    octave_bucket(tbt),
                                    (g.sAk == 1 ? 1 : 0) + (g.sBn == 1 ? 2 : 0) + (g.nb2 > 1 ? 4 : 0) +
-                                       (g.kchunk > 0 ? 8 : 0));
+                                       (g.kchunk > 0 ? 8 : 0) + (trans_narrow ? 16 : 0));
   auto it = c->gemm_choice.find(key);
   if (it != c->gemm_choice.end()) {
-    launch_zgemm_variant(g, it->second, c->stream);
+    launch_choice(g, it->second, c->stream);
     return it->second;
   }
   if (c->no_timing) {  // a call that may not allocate: the untimed choice
@@ -777,25 +795,30 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  std::vector<double> ms(GEMM_NVAR, 0.0);
+  // candidates: every variant (the 32-column ones only where they may pay) and,
+  // when the rows are a count that 32-column tiles pad less, those tiles on the
+  // transposed product
+  std::vector<int> cand;
+  for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v)  // the simple kernel (variant 0) never competes
+    if (!gemm_variant_narrow(v) || narrow_may_pay(g.N)) cand.push_back(v);
+  if (trans_narrow)
+    for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v)
+      if (gemm_variant_narrow(v)) cand.push_back(kTransposedChoice + v);
+  std::vector<double> ms(cand.size(), 0.0);
   launch_zgemm_variant(h, gemm_default_variant(g), c->stream);  // warm caches and clocks
   int best = gemm_default_variant(g);
   double tbest = 1e300;
-  for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) {  // the simple kernel (variant 0) never competes
-    if (gemm_variant_narrow(v) && g.N > kNarrowMaxN) {
-      ms[v] = 1e30;  // 32-column tiles on a wide output: not timed
-      continue;
-    }
+  for (size_t q = 0; q < cand.size(); ++q) {
     HIPCHK(hipEventRecord(e0, c->stream));
-    launch_zgemm_variant(h, v, c->stream);
+    launch_choice(h, cand[q], c->stream);
     HIPCHK(hipEventRecord(e1, c->stream));
     HIPCHK(hipEventSynchronize(e1));
     float t = 0.f;
     HIPCHK(hipEventElapsedTime(&t, e0, e1));
-    ms[v] = t;
+    ms[q] = t;
     if (t < tbest) {
       tbest = t;
-      best = v;
+      best = cand[q];
     }
   }
   (void)hipEventDestroy(e0);
@@ -805,7 +828,8 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   // tile order first, then tiles of 128 rows and of 128 or more columns, then the
   // faster one
   {
-    auto rereads = [](int v) {
+    auto rereads = [](int choice) {
+      const int v = choice % kTransposedChoice;
       const int base = gemm_variant_grouped(v) && v <= 2 * GEMM_64x64_G4 ? v - GEMM_64x64_G4 : v;
       const bool rows128 = base == GEMM_128x64_G3 || base == GEMM_128x64_G4 || v == GEMM_128x64_G4_SB ||
                            v == GEMM_128x64_G4_SB_GROUPED || (v >= GEMM_128x128_G4 && v < GEMM_64x256_DMA) ||
@@ -813,25 +837,27 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
       const bool cols128 = v >= GEMM_128x128_G4 && !gemm_variant_narrow(v);
       return (gemm_variant_grouped(v) ? 0 : 3) + (rows128 ? 0 : 1) + (cols128 ? 0 : 1);
     };
-    int pick = best;
-    for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v) {
-      if (ms[v] > 1.02 * tbest) continue;
-      if (rereads(v) < rereads(pick) || (rereads(v) == rereads(pick) && ms[v] < ms[pick])) pick = v;
+    size_t pick = 0;
+    for (size_t q = 0; q < cand.size(); ++q)
+      if (cand[q] == best) pick = q;
+    for (size_t q = 0; q < cand.size(); ++q) {
+      if (ms[q] > 1.02 * tbest) continue;
+      if (rereads(cand[q]) < rereads(cand[pick]) || (rereads(cand[q]) == rereads(cand[pick]) && ms[q] < ms[pick]))
+        pick = q;
     }
-    best = pick;
+    best = cand[pick];
   }
   c->arena.reset(mk);
   c->gemm_choice[key] = best;
   std::vector<std::pair<int, double>> rec;
-  for (int v = GEMM_128x64_G3; v < GEMM_NVAR; ++v)
-    if (ms[v] < 1e29) rec.push_back({v, ms[v]});  // the variants that were timed
+  for (size_t q = 0; q < cand.size(); ++q) rec.push_back({cand[q], ms[q]});
   // the product's shape, then the part that was timed (at most kTuneRows rows and kTuneBatch batch entries)
   c->gemm_tuning_log.push_back({std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + " b" +
                                     std::to_string(g.batch) + " layout" + std::to_string(std::get<4>(key)) +
                                     " timed " + std::to_string(tmr) + "x" + std::to_string(g.N) + "x" +
                                     std::to_string(g.K) + " b" + std::to_string(tbt),
                                 rec, best});
-  launch_zgemm_variant(g, best, c->stream);
+  launch_choice(g, best, c->stream);
   return best;
 }
 

@@ -135,10 +135,15 @@ enum {
   GEMM_128x128_DMA_GROUPED = 16, GEMM_64x256_DMA = 17, GEMM_64x256_DMA_GROUPED = 18, GEMM_128x32_G4_SB = 19,
   GEMM_64x32_G4 = 20, GEMM_NVAR = 21
 };
-// the narrow variants (19, 20): timed by the autotuner only for outputs at most this wide
+// the narrow variants (19, 20): timed by the autotuner for outputs at most this
+// wide (and for wider ones up to 512 that 64-column tiles pad much more)
 constexpr int kNarrowMaxN = 64;
 bool gemm_variant_grouped(int variant);
 bool gemm_variant_narrow(int variant);
+// an autotuner choice: an FP64 variant v, or kTransposedChoice + v for variant
+// v on the transposed product C^T = B^T A^T
+constexpr int kTransposedChoice = 100;
+void launch_gemm_choice(const GemmArgs& g, int choice, hipStream_t s);
 void launch_zgemm_variant(const GemmArgs& g, int variant, hipStream_t s);
 int gemm_default_variant(const GemmArgs& g);
 // Several products (same operand layouts: ak = unit-stride k in A, bn = unit-

@@ -29,3 +29,5 @@ def test_kernel_names_of_the_variants():
     assert b.gemm_kernel_name(14) == "k_zgemm_w1"
     assert b.gemm_kernel_name(10) == "k_zgemm_p1"
     assert b.gemm_kernel_name(3) == "k_zgemm_p"
+    assert b.gemm_kernel_name(19) == "k_zgemm_p1"
+    assert b.gemm_kernel_name(120) == "k_zgemm_p"
