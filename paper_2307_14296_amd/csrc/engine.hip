@@ -609,10 +609,10 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g0, int& form) {
     }
   }
   if (g0.K <= 32 && launch_zgemm_smallk(g0, c->stream)) return;
-  // FP64 MFMA tiles are at least 32 columns but 64 rows high: a product with
-  // a short m side (at most 32) and a long n side runs transposed, so that
-  // its short side can take the 32-column tiles
-  const GemmArgs g = (c->sigma_prec == CCLR_FP64 && g0.M <= 32 && g0.N > 32) ? transposed(g0) : g0;
+  // the MFMA tiles are at least 32 columns but 64 (FP64) or 128 (FP32) rows
+  // high: a product with a short m side (at most 32) and a long n side runs
+  // transposed, so that its short side can take the 32-column tiles
+  const GemmArgs g = (g0.M <= 32 && g0.N > 32) ? transposed(g0) : g0;
   {
     // at most 16 output columns: FP64 VALU rows instead of mostly empty MFMA tiles
     GemmArgs h;

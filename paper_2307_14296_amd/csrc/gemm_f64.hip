@@ -1344,6 +1344,16 @@ void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
     HIPCHK(hipGetLastError());
     return;
   }
+  if (g.N <= 32) {
+    // at most 32 output columns (the o index): 32-column tiles pad half as much as 64-column ones
+    dim3 grid((g.M + 127) / 128, (g.N + 31) / 32, g.batch);
+    if (ak && bn) hipLaunchKernelGGL((k_cgemm_f32<128, 32, true, true>), grid, dim3(256), 0, s, g);
+    else if (ak) hipLaunchKernelGGL((k_cgemm_f32<128, 32, true, false>), grid, dim3(256), 0, s, g);
+    else if (bn) hipLaunchKernelGGL((k_cgemm_f32<128, 32, false, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_cgemm_f32<128, 32, false, false>), grid, dim3(256), 0, s, g);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   dim3 grid((g.M + 127) / 128, (g.N + 63) / 64, g.batch);
   if (ak && bn) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, true>), grid, dim3(256), 0, s, g);
   else if (ak) hipLaunchKernelGGL((k_cgemm_f32<128, 64, true, false>), grid, dim3(256), 0, s, g);
