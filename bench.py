@@ -759,19 +759,30 @@ def main():
             log(f"[{prec}] warm-up step {k} done in {time.perf_counter() - tw:.2f} s")
         L.cclr_dbg_profile(ctx, 1)
         torch.cuda.synchronize()
+        def tuning_record():
+            buf = ctypes.create_string_buffer(1 << 16)
+            L.cclr_dbg_tuning(ctx, -1, buf, len(buf))
+            return [ln for ln in buf.value.decode().splitlines() if ln]
+
+        tuned_before = len(tuning_record())
         t0 = time.perf_counter()
         ntr = 0
+        step_s = []
         for k in range(steps):
+            ts = time.perf_counter()
             ntr += step()
             torch.cuda.synchronize()
+            step_s.append(round(time.perf_counter() - ts, 4))
             log(f"[{prec}] timed step {k} done ({time.perf_counter() - t0:.2f} s so far)")
         dt = time.perf_counter() - t0
         nl, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
         L.cclr_dbg_profile_read(ctx, 1, opt.prec, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(fl))
         L.cclr_dbg_profile(ctx, 0)
-        buf = ctypes.create_string_buffer(1 << 16)
-        L.cclr_dbg_tuning(ctx, -1, buf, len(buf))
-        res["gemm_tuning"] = [ln for ln in buf.value.decode().splitlines() if ln]
+        res["gemm_tuning"] = tuning_record()
+        # every timed step's duration, and the GEMM shape classes first tuned inside the timed steps (0 when
+        # the warm-up covered them all)
+        res["step_s"] = step_s
+        res["shapes_tuned_while_timed"] = len(res["gemm_tuning"]) - tuned_before
         cc.cclr_destroy(ctx)
         if tight_tol and args.mode == "response":
             # untimed FP64 reference solved to the tight tolerance
@@ -832,7 +843,7 @@ def main():
     ms = ctypes.c_double(main_res["ms"])
     fl = ctypes.c_double(main_res["fl"])
     t_gen = main_res["input_generation_s"]
-    extra = {k: main_res[k] for k in ("solver", "rc") if k in main_res}
+    extra = {k: main_res[k] for k in ("solver", "rc", "step_s", "shapes_tuned_while_timed") if k in main_res}
     extra["gemm_tuning"] = main_res.get("gemm_tuning", [])[:16]
     achieved = fl.value / (ms.value * 1e-3) / 1e12 if ms.value > 0 else 0.0
     sf = sigma_flops(o, v)
@@ -902,7 +913,8 @@ def main():
         step_s = mres["dt"] / args.mixed_steps
         mx = {"prec": names[p], "value": mres["transforms"] / mres["dt"], "steps": args.mixed_steps,
               "ms_per_step": 1e3 * step_s, "transforms": mres["transforms"],
-              "job_speedup_vs_fp64": fp64_step / step_s}
+              "job_speedup_vs_fp64": fp64_step / step_s, "step_s": mres.get("step_s"),
+              "shapes_tuned_while_timed": mres.get("shapes_tuned_while_timed")}
         if "alpha" in mres:
             mx["alpha_err_vs_fp64_timed"] = alpha_err(mres["alpha"], main_res["alpha"])
             if ref_alpha is not None:
