@@ -182,8 +182,9 @@ DISPATCH_CASES = [(20, 300, 5000, 1), (300, 20, 700, 3), (3, 1000, 700, 2), (1, 
                   (700, 2, 2000, 1), (1, 300, 3000, 2), (5, 257, 1500, 1), (1000, 8, 700, 2),
                   # at most 32 output columns or rows on the 32-column MFMA tiles (a short m side runs transposed)
                   (2000, 20, 200, 1), (20, 3000, 400, 2), (32, 1500, 64, 1),
-                  # short reductions of every length class (K <= 8, 16, 32), ragged row blocks
-                  (70, 300, 5, 2), (100, 600, 12, 1), (33, 257, 32, 3), (45, 130, 17, 2)]
+                  # short reductions of every length class (K rounded up to a multiple of 4), ragged row blocks
+                  (70, 300, 5, 2), (100, 600, 12, 1), (33, 257, 32, 3), (45, 130, 17, 2), (40, 270, 1, 2),
+                  (60, 300, 20, 3), (35, 260, 23, 1), (50, 280, 27, 2), (70, 290, 8, 1), (36, 300, 14, 2)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", DISPATCH_CASES)
