@@ -7,7 +7,8 @@
 // system G' beta = -C' with G'_ij = <b_i, s_j>, C'_j = <b_j, xi> is solved by
 // LU with partial pivoting on the device; the residual is
 // R = sum_j beta_j s_j + xi; the correction (z - D)^-1 R is orthogonalized
-// against {b} by classical Gram-Schmidt applied twice and appended.  The
+// against {b} by classical Gram-Schmidt (a second pass where the first
+// removed more than half of its squared norm) and appended.  The
 // start vector is the unit vector on the largest |xi| component.  When the
 // subspace is full it restarts from the current solution.  All right-hand
 // sides advance in lockstep so each Jacobian transform is batched.
@@ -545,9 +546,35 @@ int davidson(cclr_ctx* c, int side, int nr, const cplx* zh, const VecSet& rhs, c
       gram(B, 0, 1, XI, 0, Cp, ms, 0, 0);
       nj = 1;
     }
-    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-      gram(B, 0, nj, E, 0, coef, ms, 0, 0);
-      lincomb(E, 0, B, 0, nj, coef, ms, -1.0, E, 0, 0, 1);
+    // classical Gram-Schmidt against the orthonormal subspace, with a second
+    // pass only for the right-hand sides whose correction lost more than half
+    // of its squared norm in the first (|e'|^2 = |e|^2 - sum |c_i|^2): a
+    // vector that is not nearly inside the subspace is orthogonal to working
+    // accuracy after one pass (Daniel, Gragg, Kaufman and Stewart's criterion)
+    gram(E, 0, 1, E, 0, tmpv, 1, 0, 0);
+    gram(B, 0, nj, E, 0, coef, ms, 0, 0);
+    lincomb(E, 0, B, 0, nj, coef, ms, -1.0, E, 0, 0, 1);
+    {
+      std::vector<cplx> ch((size_t)nr * ms), nh(nr);
+      HIPCHK(hipMemcpyAsync(ch.data(), coef, sizeof(cplx) * ch.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(nh.data(), tmpv, sizeof(cplx) * nr, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      std::vector<int> again;
+      for (int r : act) {
+        double p = 0.0;
+        for (int i = 0; i < nj; ++i) {
+          const cplx x = ch[(size_t)r * ms + i];
+          p += x.x * x.x + x.y * x.y;
+        }
+        if (!(p <= 0.5 * nh[r].x)) again.push_back(r);
+      }
+      if (!again.empty()) {
+        const std::vector<int> keep = act;
+        set_active(again);
+        gram(B, 0, nj, E, 0, coef, ms, 0, 0);
+        lincomb(E, 0, B, 0, nj, coef, ms, -1.0, E, 0, 0, 1);
+        set_active(keep);
+      }
     }
     gram(E, 0, 1, E, 0, tmpv, 1, 0, 0);
     j = nj;
