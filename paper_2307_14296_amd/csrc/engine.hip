@@ -700,7 +700,8 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g0, int& form) {
 // Autotuner.  The first time a large product of a given shape class (M, N,
 // K, batch, operand layouts) is requested, every MFMA kernel variant is
 // timed once with HIP events on a scratch output of the same strides, and
-// the fastest is cached in the context.  Small products use the default.
+// the fastest is cached in the context.  Products under 1e10 flop use the
+// untimed choice.
 // The row count M and the batch count carry the number of vectors a
 // transform is applied to, which changes from call to call (a lockstep
 // solve whose active right-hand sides converge one by one): they are timed
@@ -754,7 +755,7 @@ static void launch_choice(const GemmArgs& g, int choice, hipStream_t s) { launch
 int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return -1;
   const double flops = 8.0 * g.M * (double)g.N * (g.kchunk > 0 ? g.kchunk : g.K) * g.batch;
-  if (!c->autotune || flops < 5e10) {
+  if (!c->autotune || flops < 1e10) {
     const int v = untimed_variant(g);
     launch_zgemm_variant(g, v, c->stream);
     return v;
