@@ -472,6 +472,82 @@ def copy_bench(cc, dev, reps=5):
     return rows
 
 
+def products_bench(cc, dev, o, v, seed, z, max_subspace, tol, top=40):
+    """Per-product record of the contraction engine's GEMMs over one whole FP64
+    response step (after a warm-up step, so no product is tuned while
+    recorded), aggregated by shape and layout: launches, total ms, TFLOP/s
+    algorithmic.  Recording synchronizes after every product, so the step
+    runs slower than untraced; the packed ladder and ring GEMMs of the
+    transforms go through their own launcher and are not in the record.
+    Plain-copy reference bandwidths of the same GPU come first."""
+    import collections
+    import torch
+    from gen import synth as s
+    L = cc.lib()
+    P = ctypes.c_void_p
+    L.cclr_dbg_gemm_trace.argtypes = [P, ctypes.c_int, ctypes.c_char_p, ctypes.c_longlong]
+    ref = {}
+    for gib in (0.25, 2.0):
+        n = int(gib * (1 << 30) / 16)
+        a = torch.randn(n, dtype=torch.complex128, device=dev)
+        b = torch.empty_like(a)
+        for name, fn, nbytes in (("copy", lambda: b.copy_(a), 32 * n), ("sum", lambda: torch.view_as_real(a).sum(),
+                                                                           16 * n)):
+            ts = []
+            for _ in range(6):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = sorted(ts[1:])[2]
+            ref[f"{name}_{gib}GiB_TB_per_s"] = round(nbytes / t / 1e12, 2)
+        del a, b
+        torch.cuda.empty_cache()
+    log(f"plain-copy references: {ref}")
+    pb, f, V, t1, t2, X = make_inputs(o, v, seed, dev)
+    opt = cc.cclr_default_options()
+    opt.max_subspace = max_subspace
+    opt.tol = tol
+    ctx = cc.cclr_create(o, v, opt)
+    try:
+        cc.cclr_set_hamiltonian(ctx, f, *[V[k] for k in s.CANONICAL_BLOCKS])
+        del V
+        torch.cuda.empty_cache()
+
+        def step():
+            cc.cclr_set_amplitudes(ctx, t1, t2)
+            rc, out, info = cc.cclr_response_function(ctx, X, [z.real], [z.imag])
+            torch.cuda.synchronize()
+            return info.nsigma
+
+        step()
+        L.cclr_dbg_gemm_trace(ctx, 1, None, 0)
+        t0 = time.perf_counter()
+        ntr = step()
+        traced_s = time.perf_counter() - t0
+        buf = ctypes.create_string_buffer(1 << 24)
+        L.cclr_dbg_gemm_trace(ctx, 0, buf, len(buf))
+    finally:
+        cc.cclr_destroy(ctx)
+    agg = collections.defaultdict(lambda: [0, 0.0, 0.0])
+    lines = [ln for ln in buf.value.decode().splitlines() if ln]
+    for ln in lines:
+        key, rest = ln.split(" form ")
+        form, ms = rest.split()[0], float(rest.split()[1])
+        M, N, K = (int(x) for x in key.split()[0].split("x"))
+        nb = int(key.split()[1][1:])
+        a = agg[key + " form " + form]
+        a[0] += 1
+        a[1] += ms
+        a[2] += 8.0 * M * N * K * nb
+    rows = [{"product": k, "launches": a[0], "ms": round(a[1], 3), "tflops": round(a[2] / (a[1] * 1e-3) / 1e12, 2)}
+            for k, a in sorted(agg.items(), key=lambda kv: -kv[1][1])]
+    return {"workload": f"engine GEMMs of one FP64 response step o={o} v={v}, z={z}", "plain_copy": ref,
+            "traced_step_s": round(traced_s, 3), "transforms": ntr, "products": len(lines),
+            "total_ms": round(sum(a[1] for a in agg.values()), 1), "top": rows[:top]}
+
+
 def sweep_bench(cc, dev, seed=3, reps=3):
     """One right transform of one vector (FP64) at each of the paper's sigma
     benchmark shapes: median of reps timed calls after a warm-up call."""
@@ -653,11 +729,12 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--omega", type=float, default=0.0774)
     ap.add_argument("--gamma", type=float, default=0.005)
-    ap.add_argument("--mode", choices=["response", "sigma", "sweep", "cpu", "copy"], default="response",
+    ap.add_argument("--mode", choices=["response", "sigma", "sweep", "cpu", "copy", "products"], default="response",
                     help="response: the whole job (default); sigma: transforms of --nvec vectors; sweep: one "
                          "transform at each of the paper's sigma-benchmark shapes; cpu: the oracle's timings on "
                          "the host (transforms at four sizes, every core and one thread, and two response tensors); "
-                         "copy: the library's strided copy on index permutations of o=20, v=200 tensors")
+                         "copy: the library's strided copy on index permutations of o=20, v=200 tensors; "
+                         "products: per-product record of the engine's GEMMs over one FP64 response step")
     ap.add_argument("--nvec", type=int, default=12, help="vectors per transform call in --mode sigma")
     ap.add_argument("--max-subspace", type=int, default=24)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -811,6 +888,10 @@ def main():
         return
     if args.mode == "copy":
         print(json.dumps({"strided_copy": copy_bench(cc, dev)}), flush=True)
+        return
+    if args.mode == "products":
+        print(json.dumps({"engine_products": products_bench(cc, dev, o, v, args.seed, z, args.max_subspace,
+                                                             args.tol)}), flush=True)
         return
     if args.mode == "sweep":
         rows = sweep_bench(cc, dev)
