@@ -578,7 +578,7 @@ static void run_gemm_form(cclr_ctx* c, const GemmArgs& g0, int& form) {
   if (g0.kchunk == 0 && g0.batch >= 8) {
     const i64 M = g0.M, N = g0.N, K = g0.K;
     const i64 n2 = g0.nb2 > 1 ? g0.nb2 : 1, n1 = g0.batch / n2;
-    auto inner = [&](i64 s1, i64 s2, i64 sz) { return sz > 1 && (s1 == 1 || (n2 > 1 && s2 == 1)); };
+    auto inner = [&](i64 s1, i64 s2, i64 sz) { return sz > 1 && ((n1 > 1 && s1 == 1) || (n2 > 1 && s2 == 1)); };
     const bool ca = inner(g0.sAb, g0.sAb2, M * K), cb = inner(g0.sBb, g0.sBb2, K * N),
                cc = inner(g0.sCb, g0.sCb2, M * N);
     const i64 big = (i64)g0.batch * std::max({ca ? M * K : 0, cb ? K * N : 0, cc ? M * N : 0});
