@@ -1344,8 +1344,11 @@ void launch_zgemm_lowp(const GemmArgs& g, int prec, hipStream_t s) {
     HIPCHK(hipGetLastError());
     return;
   }
-  if (g.N <= 32) {
-    // at most 32 output columns (the o index): 32-column tiles pad half as much as 64-column ones
+  const int p32 = (g.N + 31) / 32 * 32, p64 = (g.N + 63) / 64 * 64;
+  if (g.N <= 32 || (g.N <= 512 && 8 * (p64 - p32) >= p32)) {
+    // at most 32 output columns (the o index): 32-column tiles pad half as much as
+    // 64-column ones; also outputs up to 512 wide that 64-column tiles pad by a
+    // further eighth or more (200: 224 columns against 256)
     dim3 grid((g.M + 127) / 128, (g.N + 31) / 32, g.batch);
     if (ak && bn) hipLaunchKernelGGL((k_cgemm_f32<128, 32, true, true>), grid, dim3(256), 0, s, g);
     else if (ak) hipLaunchKernelGGL((k_cgemm_f32<128, 32, true, false>), grid, dim3(256), 0, s, g);
