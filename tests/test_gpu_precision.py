@@ -51,8 +51,8 @@ def cfg1():
 
 GEMM_CASES = [(1, 1, 1, 0, 0), (17, 33, 5, 1, 0), (130, 3, 129, 0, 1), (200, 260, 300, 1, 1), (300, 257, 1000, 0, 0),
               (600, 530, 70, 0, 0), (1030, 600, 200, 1, 1), (520, 700, 33, 1, 0),
-              # at most 32 output columns (the FP32 engine kernel's 32-column tiles), ragged row tiles
-              (300, 20, 400, 0, 1), (257, 32, 64, 1, 0)]
+              # at most 32 output columns, and 200 (the FP32 engine kernel's 32-column tiles), ragged row tiles
+              (300, 20, 400, 0, 1), (257, 32, 64, 1, 0), (300, 200, 150, 0, 0), (130, 200, 70, 1, 1)]
 PRECS = {"fp32": (1, 1e-5, 1e-5), "bf16x3": (2, 5e-5, 1e-4), "bf16x2": (3, 3e-3, 3e-3)}
 # the engine's FP32 kernel of the remaining products (complex128 operands converted in the kernel)
 GEMM_PRECS = {**PRECS, "fp32_engine": (16, 1e-5, None)}
