@@ -243,12 +243,22 @@ def spectrum_bench(cc, dev, o=16, v=120, seed=2, nfreq=16):
         cc.cclr_set_amplitudes(ctx, t1, t2)
         om = [float(x) for x in np.linspace(0.0, 0.5, nfreq)]
         ga = [0.005] * nfreq
-        # warm-up of both forms (Lambda solve; first-use GEMM tuning of their product shapes, including
-        # those of the omega = 0 call, which solves 2 distinct systems per operator instead of 4)
+        L = cc.lib()
+        L.cclr_dbg_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_longlong]
+
+        def tuned_classes():
+            buf = ctypes.create_string_buffer(1 << 16)
+            L.cclr_dbg_tuning(ctx, -1, buf, len(buf))
+            return len([ln for ln in buf.value.decode().splitlines() if ln])
+
+        # warm-up of both forms, the whole per-frequency sweep included (Lambda solve; first-use GEMM tuning
+        # of every product shape class the two forms meet: the active right-hand sides of a call drop out as
+        # they converge, so each form has row counts of its own)
         cc.cclr_response_function(ctx, X, om, ga)
-        cc.cclr_response_function(ctx, X, om[0:1], ga[0:1])
-        cc.cclr_response_function(ctx, X, om[1:2], ga[1:2])
+        for w in range(nfreq):
+            cc.cclr_response_function(ctx, X, [om[w]], [ga[w]])
         torch.cuda.synchronize()
+        tuned0 = tuned_classes()
         t0 = time.perf_counter()
         rc, out, info = cc.cclr_response_function(ctx, X, om, ga)
         torch.cuda.synchronize()
@@ -263,6 +273,8 @@ def spectrum_bench(cc, dev, o=16, v=120, seed=2, nfreq=16):
         torch.cuda.synchronize()
         t_single = time.perf_counter() - t0
         log(f"spectrum: one call per frequency {t_single:.2f} s, {n_single} transforms")
+        # shape classes first met (and timed by the autotuner) inside the two timed forms
+        tuned_while_timed = tuned_classes() - tuned0
         diff = max(float(np.linalg.norm(out[w] - outs[w]) / np.linalg.norm(outs[w])) for w in range(nfreq))
         return {"workload": f"damped spectrum o={o} v={v} complex128, 3 dipoles x {nfreq} frequencies on [0, 0.5] Eh, "
                             f"gamma 0.005, tol 1e-8",
@@ -270,7 +282,8 @@ def spectrum_bench(cc, dev, o=16, v=120, seed=2, nfreq=16):
                              "transforms_per_s": round(info.nsigma / t_lock, 2), "iterations": info.iters, "rc": rc},
                 "one_call_per_frequency": {"seconds": round(t_single, 3), "transforms": n_single,
                                            "transforms_per_s": round(n_single / t_single, 2)},
-                "speedup_lockstep": round(t_single / t_lock, 3), "max_rel_diff_alpha": diff}
+                "speedup_lockstep": round(t_single / t_lock, 3), "max_rel_diff_alpha": diff,
+                "shapes_tuned_while_timed": tuned_while_timed}
     finally:
         cc.cclr_destroy(ctx)
         del f, t1, t2, X

@@ -174,7 +174,9 @@ int cclr_dbg_small_eig(int n, const cclr_c64* H, int nroots, cclr_c64* w, cclr_c
  * larger tiles, are preferred; 100 + v is variant v on the transposed product
  * C^T = B^T A^T, timed for the 32-column variants when the row count is one
  * they pad less than 64-row tiles would).
- * enable >= 0 switches tuning on (1) or off (0) for later products. */
+ * enable >= 0 switches tuning of new shape classes on (1) or off (0) for
+ * later products; with tuning off a product of a class not yet timed takes
+ * the untimed choice, and the classes already timed keep theirs. */
 int cclr_dbg_tuning(cclr_ctx* ctx, int enable, char* buf, long long cap);
 
 #ifdef __cplusplus

@@ -755,7 +755,7 @@ static void launch_choice(const GemmArgs& g, int choice, hipStream_t s) { launch
 int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return -1;
   const double flops = 8.0 * g.M * (double)g.N * (g.kchunk > 0 ? g.kchunk : g.K) * g.batch;
-  if (!c->autotune || flops < 1e10) {
+  if (flops < 1e10) {
     const int v = untimed_variant(g);
     launch_zgemm_variant(g, v, c->stream);
     return v;
@@ -776,7 +776,7 @@ int tuned_gemm(cclr_ctx* c, const GemmArgs& g) {
     launch_choice(g, it->second, c->stream);
     return it->second;
   }
-  if (c->no_timing) {  // a call that may not allocate: the untimed choice
+  if (c->no_timing || !c->autotune) {  // no new timing runs (a call that may not allocate, or tuning off)
     const int v = untimed_variant(g);
     launch_zgemm_variant(g, v, c->stream);
     return v;
